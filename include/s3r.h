@@ -1,0 +1,290 @@
+/*
+ * s3r.h -- C ABI of the MI355X (gfx950) per-view Gaussian rendering library
+ * for streamlined street-scene reconstruction (S3R-GS, arXiv 2503.08217).
+ *
+ * One call of each entry point processes a batch of V views (V >= 1, possibly
+ * of different sizes and timesteps).  The steps follow Sec. 3.3 of the paper:
+ * temporal-visibility selection, instance-specific projection, frustum test
+ * giving the visible mask M_t, adaptive-LOD cull, colour query of the
+ * survivors, alpha blending (Eq. 2) and the point-life / temporal-visibility
+ * update (Eqs. 5-6); plus the backward pass of the blending and projection.
+ * The conventional pipeline the paper compares against (Sec. 3.1: transform
+ * every instance Gaussian to the world frame, then project everything) is
+ * available as the "plain" route through s3r_plain_transform and the
+ * S3R_PLAIN flag, sharing every other kernel.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Struct arguments are host memory, read during the call, not retained.
+ *    Every array they point to is DEVICE memory owned by the caller.
+ *  - The library never allocates, frees or synchronises; it enqueues kernels on
+ *    the caller's `stream` (a hipStream_t passed as void*; NULL = default
+ *    stream) and returns.  All calls can be captured in a hipGraph.
+ *  - Float arrays are IEEE binary32; every array must be 16-byte aligned
+ *    (S3R_E_ALIGN otherwise).
+ *  - Return value: S3R_OK (0) or a negative S3R_E_* code; no exception
+ *    crosses the ABI.  s3r_status_string() names a code.  Errors detected on
+ *    the host leave all outputs untouched.
+ *  - Data-dependent sizes (survivor count, number of (tile, Gaussian) pairs)
+ *    stay on the device.  If they exceed the capacities in S3RParams the
+ *    device sets an overflow counter (S3RProjected.counters[S3R_CNT_OVF_*]),
+ *    drops the excess consistently and the caller re-runs with larger buffers.
+ *
+ * Gaussian layout (structure of arrays, N Gaussians, static ones first, each
+ * instance's Gaussians contiguous):
+ *   mean[N][3]      position, instance-local for instance Gaussians
+ *   scale[N][3]     per-axis standard deviation (activated)
+ *   quat[N][4]      rotation quaternion (w, x, y, z), need not be normalised
+ *   opacity[N]      in (0, 1) (activated)
+ *   sh[N][B][3]     real SH coefficients, B = (L+1)^2, L = sh_degree <= 3
+ *   inst[N]         0 = static, k in 1..S-1 = instance k
+ *   vis_s[N], vis_e[N]   temporal visibility interval
+ *   pose[T][S][12]  row-major 3x4 local->world pose of slot k at timestep tau
+ *                   (slot 0 must be the identity)
+ * Views (V views):
+ *   W[V][12]        row-major 3x4 world->camera extrinsic (OpenCV axes)
+ *   K[V][4]         fx, fy, cx, cy; pixel (x, y) is sampled at integer (x, y)
+ *   wh[V][2]        width, height
+ *   tstep[V]        timestep index tau in [0, T)
+ *   tile_offset[V+1]  exclusive prefix of tiles per view, gx*gy with
+ *                     gx = ceil(w/tile), gy = ceil(h/tile)
+ *   px_offset[V+1]    exclusive prefix of w*h
+ */
+#ifndef S3R_H
+#define S3R_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define S3R_ABI_VERSION 1
+
+enum {
+  S3R_OK = 0,
+  S3R_E_NULL = -1,      /* a required pointer is NULL                     */
+  S3R_E_ALIGN = -2,     /* a pointer is not 16-byte aligned               */
+  S3R_E_SIZE = -3,      /* a size is out of range (n, views, degree, tile) */
+  S3R_E_WORKSPACE = -4, /* workspace smaller than s3r_workspace_size()    */
+  S3R_E_HIP = -5,       /* a kernel launch failed                          */
+  S3R_E_ARG = -6        /* an argument value is invalid                    */
+};
+
+/* S3RParams.flags */
+enum {
+  S3R_TEMPORAL = 1, /* apply the temporal-visibility test (Sec. 3.3)       */
+  S3R_LOD = 2,      /* apply the LOD cull with threshold lod_r (Sec. 3.3)  */
+  S3R_PLAIN = 4     /* project the world-frame arrays of s3r_plain_transform
+                       with the view camera (conventional route, Sec. 3.1) */
+};
+
+/* modes of s3r_update_visibility */
+enum { S3R_VIS_UPDATE = 0, S3R_VIS_FOLD = 1, S3R_VIS_RESET = 2 };
+
+/* indices into S3RProjected.counters (device int32[16]) */
+enum {
+  S3R_CNT_SURV = 0,     /* number of survivor records written            */
+  S3R_CNT_OVF_SURV = 1, /* survivors dropped for lack of capacity        */
+  S3R_CNT_DUP = 2,      /* number of (tile, record) pairs                 */
+  S3R_CNT_OVF_DUP = 3,  /* pairs dropped for lack of capacity             */
+  S3R_CNT_SPIN = 4,     /* nonzero if a bounded wait gave up (never expected) */
+  S3R_CNT_TICKET = 5,   /* internal: project workgroup tickets             */
+  S3R_CNT_TICKET2 = 6   /* internal: scan workgroup tickets                */
+};
+
+typedef struct S3RParams {
+  int32_t tile;       /* tile edge in pixels: 8, 16 or 32                   */
+  uint32_t flags;     /* S3R_TEMPORAL | S3R_LOD | S3R_PLAIN                 */
+  float lod_r;        /* LOD threshold r in pixels (Sec. 3.3, "Adaptive LOD") */
+  float z_near, z_far;
+  float eps2d;        /* low-pass added to the 2D covariance (px^2)         */
+  float alpha_min, alpha_max, t_min;
+  float cutoff;       /* skip where the Mahalanobis power is below -cutoff  */
+  float jac_clamp;    /* EWA Jacobian clamp, multiple of the half FOV tangent */
+  float bg[3];        /* background colour                                  */
+  int64_t cap_surv;   /* capacity of the survivor-record arrays             */
+  int64_t cap_dup;    /* capacity of the (tile, record) pair arrays         */
+} S3RParams;
+
+typedef struct S3RScene {
+  const float* mean;
+  const float* scale;
+  const float* quat;
+  const float* opacity;
+  const float* sh;
+  const int32_t* inst;
+  const float* vis_s;
+  const float* vis_e;
+  const float* pose;
+  /* plain route only (S3R_PLAIN): world-frame arrays written by
+     s3r_plain_transform, [n_plain_slots][N][3] and [n_plain_slots][N][9]   */
+  const float* mean_w;
+  const float* rot_w;
+  int64_t n;          /* number of Gaussians, < 2^31                        */
+  int32_t sh_degree;  /* 0..3                                               */
+  int32_t n_slots;    /* S = number of instances + 1                        */
+  int32_t n_timesteps;/* T                                                  */
+  int32_t pad_;
+} S3RScene;
+
+typedef struct S3RViews {
+  const float* W;
+  const float* K;
+  const int32_t* wh;
+  const int32_t* tstep;
+  const int32_t* tile_offset;
+  const int64_t* px_offset;
+  const int32_t* plain_slot; /* [V] world-frame array slot of each view (plain route) */
+  int32_t n_views;           /* 1..64                                              */
+  int32_t total_tiles;       /* tile_offset[V], host copy                          */
+  int64_t total_px;          /* px_offset[V], host copy                            */
+} S3RViews;
+
+typedef struct S3RProjected {
+  /* written by s3r_project_cull */
+  float* cam;         /* [V][S][12] instance cameras P = W G, binary32        */
+  float* cen;         /* [V][S][4]  camera centre seen from each slot's frame */
+  float* t_norm;      /* [V] normalised rendering time in [-1, 1]             */
+  uint32_t* mask;     /* [V][ceil(N/64)*2] bit i of view v = M_t[i]           */
+  int32_t* rec_gid;   /* [cap_surv] Gaussian index of each survivor record    */
+  int32_t* rec_view;  /* [cap_surv] view of each record                       */
+  float* rec_geo;     /* [cap_surv][4] u, v, opacity, depth                   */
+  float* rec_conic;   /* [cap_surv][4] inverse 2D covariance A, B, C; pad     */
+  float* rec_rgb;     /* [cap_surv][4] r, g, b; pad                           */
+  int32_t* rec_rect;  /* [cap_surv][4] tile rect x0, y0, x1, y1 (view-local)  */
+  int32_t* counters;  /* [16] see S3R_CNT_*                                   */
+  int32_t* stats;     /* [V][4] N_t (temporal pass), N_f (= |M_t|), N_r (records),
+                         N_dup (pairs, written by s3r_sort)                     */
+  int32_t* tile_count;/* [total_tiles] number of records covering each tile     */
+} S3RProjected;
+
+typedef struct S3RBins {
+  int32_t* tile_start; /* [total_tiles+1] start of each tile's list          */
+  uint32_t* vals;      /* [cap_dup] record index of each list entry, sorted  */
+} S3RBins;
+
+typedef struct S3RImage {
+  float* color;   /* per view v: [3][h][w] planar at offset 3*px_offset[v]   */
+  float* T_final; /* [total_px] transmittance after the last contributor     */
+  int32_t* last;  /* [total_px] 1 + list position of the last contributor    */
+} S3RImage;
+
+typedef struct S3RGrads {
+  /* accumulated (+=) into caller-zeroed buffers */
+  float* mean;    /* [N][3] */
+  float* scale;   /* [N][3] */
+  float* quat;    /* [N][4] */
+  float* opacity; /* [N]    */
+  float* sh;      /* [N][B][3] */
+  float* pose;    /* [T][S][12] dL/d(3x4 pose); slot 0 left untouched        */
+  float* pose6;   /* [T][S][6]  right-perturbation (rho, omega) form of `pose`,
+                     overwritten from the accumulated `pose` (optional, may be NULL) */
+  /* plain route only: world-frame gradients, [n_plain_slots][N][3] / [..][9] */
+  float* mean_w;
+  float* rot_w;
+} S3RGrads;
+
+/* Sizes used to plan workspaces. */
+typedef struct S3RSizes {
+  int64_t n;
+  int32_t n_views;
+  int32_t total_tiles;
+  int64_t cap_surv;
+  int64_t cap_dup;
+  int32_t n_slots;
+  int32_t pad_;
+} S3RSizes;
+
+enum { S3R_WS_PROJECT = 0, S3R_WS_SORT = 1, S3R_WS_BACKWARD = 2 };
+
+/* Bytes of device workspace entry point `which` needs (S3R_WS_*). */
+int s3r_workspace_size(const S3RSizes* sizes, int32_t which, size_t* bytes);
+
+/*
+ * s3r_project_cull -- Sec. 3.3 steps 1-3 and the colour query, per view:
+ *   instance cameras W_{t,i} = W_t W_{t,i2g} (Sec. 3.3 "Instance-specific
+ *   projection"; composed in FP64, rounded once), normalised time t,
+ *   temporal selection v_s <= t <= v_e (Sec. 3.3 "Temporal separation"),
+ *   projection of mean and covariance (Eq. 1, EWA), frustum test -> M_t,
+ *   LOD cull of Gaussians whose 2D scale is at most lod_r (Sec. 3.3 "Adaptive
+ *   LOD", drop probability 1), SH colour of the survivors only.
+ * Writes one record per (view, surviving Gaussian), ordered by Gaussian block
+ * then view then Gaussian index (so record index increases with the Gaussian
+ * index within a view), plus M_t bits, stats and per-tile pair counts.
+ * `ws` must hold s3r_workspace_size(S3R_WS_PROJECT) bytes.
+ */
+int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RParams* params,
+                     S3RProjected* out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * s3r_sort -- builds per-tile contributor lists ordered by (depth bits,
+ * Gaussian index), the blending order of Eq. (2), bit-exactly: exclusive scan
+ * of the tile counts, key emission, per-tile sort.  Reads the records of
+ * s3r_project_cull; `ws` holds s3r_workspace_size(S3R_WS_SORT) bytes.
+ */
+int s3r_sort(const S3RProjected* proj, const S3RViews* views, const S3RParams* params,
+             S3RBins* bins, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * s3r_raster_fwd -- front-to-back alpha blending of Eq. (2) for every pixel of
+ * every view in one launch: Mahalanobis cut, alpha = min(alpha_max,
+ * o exp(power)), skip below alpha_min, stop before T would fall below t_min.
+ */
+int s3r_raster_fwd(const S3RProjected* proj, const S3RBins* bins, const S3RViews* views,
+                   const S3RParams* params, S3RImage* img, void* stream);
+
+/*
+ * s3r_l1_loss -- per-view mean absolute error against `target` (same layout
+ * as S3RImage.color), loss[v] written, and its gradient d_color.
+ */
+int s3r_l1_loss(const S3RImage* img, const float* target, const S3RViews* views,
+                float* loss, float* d_color, void* stream);
+
+/*
+ * s3r_raster_bwd -- gradient of the blending (replayed back to front from
+ * T_final and `last`) and of the projection, colour and instance cameras
+ * (chain of Eq. 1 and the SH colour), accumulated into `g`.  Pose gradients
+ * are chained through W_{t,i} = W_t W_{t,i2g} and also given in 6-DoF form.
+ * In the plain route the world-frame gradients g->mean_w / g->rot_w are
+ * filled instead of mean / quat; s3r_plain_transform_bwd finishes them.
+ */
+int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams* params,
+                   const S3RProjected* proj, const S3RBins* bins, const S3RImage* img,
+                   const float* d_color, S3RGrads* g, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * s3r_update_visibility -- Eqs. (5)-(6).  UPDATE: for every view v of the
+ * batch whose M_t bit is set, l_s = min(l_s, t_v), l_e = max(l_e, t_v).
+ * FOLD: v_s = l_s - margin, v_e = l_e + margin.  RESET: v = (-1, 1),
+ * l = (1, -1).  `mask` and `t_norm` are those of S3RProjected (UPDATE only).
+ */
+int s3r_update_visibility(float* life_s, float* life_e, float* vis_s, float* vis_e,
+                          const uint32_t* mask, const float* t_norm, int32_t n_views,
+                          int64_t n, int32_t mode, float margin, void* stream);
+
+/*
+ * s3r_plain_transform -- the conventional local->global transform of Sec. 3.1
+ * for the baseline route: for each of the n_ts timesteps in `tsteps` (host
+ * array), mean_w = R_G mean + t_G and rot_w = R_G R(q) for every Gaussian,
+ * written to out_mean_w[n_ts][N][3] and out_rot_w[n_ts][N][9].
+ */
+int s3r_plain_transform(const S3RScene* scene, const int32_t* tsteps, int32_t n_ts,
+                        float* out_mean_w, float* out_rot_w, void* stream);
+
+/*
+ * s3r_plain_transform_bwd -- chains world-frame gradients (S3RGrads.mean_w,
+ * rot_w) back to local mean / quat and to the poses of the n_ts timesteps.
+ */
+int s3r_plain_transform_bwd(const S3RScene* scene, const int32_t* tsteps, int32_t n_ts,
+                            S3RGrads* g, void* stream);
+
+int s3r_abi_version(void);
+const char* s3r_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* S3R_H */

@@ -20,6 +20,9 @@ Canonical order (s = tile size, p = camera-space mean, q = quaternion):
   temporal    pass = (v_s <= t) and (t <= v_e)
   mean        p_r = ((P_r0 mu_x + P_r1 mu_y) + P_r2 mu_z) + P_r3
   depth       z_near < p_z < z_far
+  plain route mu <- ((G_r0 mu_x + G_r1 mu_y) + G_r2 mu_z) + G_r3,
+              R <- R_G R(q) with entries (G_i0 R_0j + G_i1 R_1j) + G_i2 R_2j,
+              and the camera is W_t itself
   quaternion  n = sqrt(((w w + x x) + y y) + z z); q <- q / n (each comp.)
   rotation    R00 = 1 - 2 (yy + zz), R01 = 2 (xy - wz), R02 = 2 (xz + wy),
               R10 = 2 (xy + wz), R11 = 1 - 2 (xx + zz), R12 = 2 (yz - wx),
@@ -56,25 +59,34 @@ def _f(x):
     return np.float32(x)
 
 
+def rot32(quat):
+    """Rotation of the normalised quaternion (w, x, y, z), binary32, as a 3x3
+    nested list of (N,) arrays in the canonical order."""
+    w, x, y, z = quat[:, 0], quat[:, 1], quat[:, 2], quat[:, 3]
+    n = np.sqrt(((w * w + x * x) + y * y) + z * z)
+    w, x, y, z = w / n, x / n, y / n, z / n
+    xx, yy, zz = x * x, y * y, z * z
+    xy, xz, yz = x * y, x * z, y * z
+    wx, wy, wz = w * x, w * y, w * z
+    one, two = _f(1.0), _f(2.0)
+    return [[one - two * (yy + zz), two * (xy - wz), two * (xz + wy)],
+            [two * (xy + wz), one - two * (xx + zz), two * (yz - wx)],
+            [two * (xz - wy), two * (yz + wx), one - two * (xx + yy)]]
+
+
 def transform32(mean, quat, pose34):
-    """The conventional transform in binary32 (plain route): mu_g = R_G mu + t_G
-    with rows summed in order, and q_g = q_G (x) q with q_G the FP64 quaternion
-    of R_G rounded once to f32.  `pose34` is (N, 3, 4) f32."""
+    """The conventional transform in binary32 (plain route, Sec. 3.1):
+    mu_g = R_G mu + t_G and R_g = R_G R(q), rows summed in order.
+    `pose34` is (N, 3, 4) f32.  Returns (mu_g (N,3), R_g nested 3x3)."""
     R = pose34[:, :, :3]
     t = pose34[:, :, 3]
     mx, my, mz = mean[:, 0], mean[:, 1], mean[:, 2]
     mg = np.stack([((R[:, r, 0] * mx + R[:, r, 1] * my) + R[:, r, 2] * mz) + t[:, r]
                    for r in range(3)], axis=1)
-    qG = frames.rot_to_quat64(R.astype(np.float64)).astype(F)
-    w1, x1, y1, z1 = qG[:, 0], qG[:, 1], qG[:, 2], qG[:, 3]
-    w2, x2, y2, z2 = quat[:, 0], quat[:, 1], quat[:, 2], quat[:, 3]
-    qg = np.stack([
-        ((w1 * w2 - x1 * x2) - y1 * y2) - z1 * z2,
-        ((w1 * x2 + x1 * w2) + y1 * z2) - z1 * y2,
-        ((w1 * y2 - x1 * z2) + y1 * w2) + z1 * x2,
-        ((w1 * z2 + x1 * y2) - y1 * x2) + z1 * w2,
-    ], axis=1)
-    return mg.astype(F), qg.astype(F), qG
+    Rq = rot32(quat)
+    Rg = [[(R[:, i, 0] * Rq[0][j] + R[:, i, 1] * Rq[1][j]) + R[:, i, 2] * Rq[2][j]
+           for j in range(3)] for i in range(3)]
+    return mg.astype(F), Rg
 
 
 def lam_max32(a, c, det):
@@ -92,7 +104,7 @@ def project_cull32(scene, W34, Kv, wh, tau, params, plain=False):
       px, py, pz, u, v, a_raw, b, c_raw, a, c, det, lam_d, lam_raw, rad,
       x0, x1, y0, y1 (int32 tile rect), conic_a/b/c, depth_bits (uint32),
     plus `cam` (K+1, 3, 4) f32, `cam64`, `t` (f32 time) and for the plain
-    route `mean_g`, `quat_g`."""
+    route `mean_g`, `rot_g`."""
     N = scene.n
     T = scene.n_timesteps
     t = frames.time_norm(tau, T)
@@ -102,11 +114,12 @@ def project_cull32(scene, W34, Kv, wh, tau, params, plain=False):
     k = scene.inst
     out = {"t": t, "cam": cam, "cam64": cam64}
     if plain:
-        mean, quat, qG = transform32(scene.mean, scene.quat, pose[k])
+        mean, Rq = transform32(scene.mean, scene.quat, pose[k])
         P = np.broadcast_to(cam[0], (N, 3, 4))
-        out["mean_g"], out["quat_g"] = mean, quat
+        out["mean_g"], out["rot_g"] = mean, Rq
     else:
-        mean, quat = scene.mean, scene.quat
+        mean = scene.mean
+        Rq = rot32(scene.quat)
         P = cam[k]
 
     with np.errstate(all="ignore"):
@@ -122,16 +135,6 @@ def project_cull32(scene, W34, Kv, wh, tau, params, plain=False):
         px, py, pz = p
         depth_ok = (_f(params["z_near"]) < pz) & (pz < _f(params["z_far"]))
 
-        w, x, y, z = quat[:, 0], quat[:, 1], quat[:, 2], quat[:, 3]
-        n = np.sqrt(((w * w + x * x) + y * y) + z * z)
-        w, x, y, z = w / n, x / n, y / n, z / n
-        xx, yy, zz = x * x, y * y, z * z
-        xy, xz, yz = x * y, x * z, y * z
-        wx, wy, wz = w * x, w * y, w * z
-        one, two = _f(1.0), _f(2.0)
-        Rq = [[one - two * (yy + zz), two * (xy - wz), two * (xz + wy)],
-              [two * (xy + wz), one - two * (xx + zz), two * (yz - wx)],
-              [two * (xz - wy), two * (yz + wx), one - two * (xx + yy)]]
         s = [scene.scale[:, 0], scene.scale[:, 1], scene.scale[:, 2]]
         M = [[Rq[i][j] * s[j] for j in range(3)] for i in range(3)]
         S = [[None] * 3 for _ in range(3)]
@@ -140,6 +143,7 @@ def project_cull32(scene, W34, Kv, wh, tau, params, plain=False):
                 S[i][j] = (M[i][0] * M[j][0] + M[i][1] * M[j][1]) + M[i][2] * M[j][2]
                 S[j][i] = S[i][j]
 
+        one = _f(1.0)
         fx, fy, cx, cy = (_f(Kv[0]), _f(Kv[1]), _f(Kv[2]), _f(Kv[3]))
         W_, H_ = int(wh[0]), int(wh[1])
         tx = px / pz

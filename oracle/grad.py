@@ -46,9 +46,16 @@ def _quat_rot(q):
     ], -2)
 
 
-def project_t(params_t, ids, inst, W34, Kv, wh, pose_tau, rp, sh_degree):
-    """Differentiable projection + colour of Gaussians `ids` (conventional route).
-    Returns u, v, conic (n,3), opac, rgb (n,3), lam_d, pz (all torch FP64)."""
+def project_t(params_t, ids, inst, W34, Kv, wh, pose_tau, rp, sh_degree, route="instance"):
+    """Differentiable projection + colour of Gaussians `ids`.  Geometry follows
+    the conventional route; the viewing direction of the colour is taken in the
+    instance frame either as mu - c_{t,i} with c_{t,i} the centre of the
+    instance camera P = W G (route "instance", the streamlined definition) or
+    as R_G^T (mu_g - c_W) (route "conventional").  Both are the same function
+    on rigid poses; as functions of the twelve raw pose entries they differ off
+    the rotation manifold, so the raw pose gradient depends on the route while
+    its 6-DoF form does not.
+    Returns u, v, conic (n,3), opac, rgb (n,3) (torch FP64)."""
     mean, scale, quat, opac, shc = (params_t[k] for k in ("mean", "scale", "quat", "opacity", "sh"))
     idx = torch.as_tensor(ids, dtype=torch.long)
     k = torch.as_tensor(inst[ids], dtype=torch.long)
@@ -81,8 +88,14 @@ def project_t(params_t, ids, inst, W34, Kv, wh, pose_tau, rp, sh_degree):
     conic = torch.stack([c / det, -b / det, a / det], -1)
     u = fx * px / pz + cx
     v = fy * py / pz + cy
-    cw = torch.as_tensor(frames.camera_centre64(np.asarray(W34, np.float64)))
-    dv = torch.einsum("nji,nj->ni", RG, mg - cw)
+    if route == "instance":
+        Rcam = Rc @ RG                                     # (n,3,3) rotation of P = W G
+        tcam = torch.einsum("ij,nj->ni", Rc, tG) + tc      # translation of P
+        cen = -torch.einsum("nji,nj->ni", Rcam, tcam)      # -R_P^T t_P
+        dv = mu - cen
+    else:
+        cw = torch.as_tensor(frames.camera_centre64(np.asarray(W34, np.float64)))
+        dv = torch.einsum("nji,nj->ni", RG, mg - cw)
     dv = dv / torch.linalg.norm(dv, dim=-1, keepdim=True)
     rgb, raw = sh.colour(shc[idx], dv, sh_degree, xp=torch)
     return u, v, conic, opac[idx], rgb
@@ -125,7 +138,8 @@ def to_torch_params(scene, requires_grad=True):
             for k, v in p.items()}
 
 
-def render_t(params_t, scene, views, v, order_ids, rp, region=None, decisions=None):
+def render_t(params_t, scene, views, v, order_ids, rp, region=None, decisions=None,
+             route="instance"):
     """Differentiable image (3, h, w) of view v over contributors `order_ids`."""
     w, h = int(views.wh[v, 0]), int(views.wh[v, 1])
     x0, y0, x1, y1 = (0, 0, w, h) if region is None else region
@@ -138,7 +152,8 @@ def render_t(params_t, scene, views, v, order_ids, rp, region=None, decisions=No
         T = torch.ones(xs_t.numel(), dtype=TD)
     else:
         u, vv, conic, opac, rgb = project_t(params_t, order_ids, scene.inst, views.W[v], views.K[v],
-                                            views.wh[v], params_t["pose"][tau], rp, scene.sh_degree)
+                                            views.wh[v], params_t["pose"][tau], rp, scene.sh_degree,
+                                            route)
         img, T = composite_t(xs_t, ys_t, u, vv, conic, opac, rgb, rp, decisions)
     return img.T.reshape(3, y1 - y0, x1 - x0), T.reshape(y1 - y0, x1 - x0)
 
@@ -147,7 +162,7 @@ def l1_loss_t(img, target):
     return (img - torch.as_tensor(np.asarray(target, np.float64))).abs().mean()
 
 
-def loss_and_grads(scene, views, view_ids, orders, rp, targets):
+def loss_and_grads(scene, views, view_ids, orders, rp, targets, route="instance"):
     """Sum over views of mean-L1 and its FP64 gradients.
 
     orders[v] are the contributor ids of view v in blending order (frozen
@@ -156,7 +171,7 @@ def loss_and_grads(scene, views, view_ids, orders, rp, targets):
     loss = torch.zeros((), dtype=TD)
     imgs = {}
     for v in view_ids:
-        img, T = render_t(pt, scene, views, v, np.asarray(orders[v]), rp)
+        img, T = render_t(pt, scene, views, v, np.asarray(orders[v]), rp, route=route)
         imgs[v] = (img.detach().numpy(), T.detach().numpy())
         loss = loss + l1_loss_t(img, targets[v])
     loss.backward()

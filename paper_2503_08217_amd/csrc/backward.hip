@@ -1,0 +1,633 @@
+// Backward pass of the per-view step.
+//
+// k_raster_bwd replays each tile back to front from the stored final
+// transmittance and the position of the last contributor, recovering
+// T_i = T_{i+1} / (1 - alpha_i) instead of storing per-pixel lists.  With
+// C = sum_i c_i alpha_i T_i + T_N bg and S_i = sum_{j>i} c_j alpha_j T_j:
+//   dL/dc_i     = alpha_i T_i dL/dC
+//   dL/dalpha_i = T_i c_i . dL/dC - (S_i + T_N bg) . dL/dC / (1 - alpha_i)
+// and alpha_i = min(alpha_max, o_i exp(power_i)) chains to the 2D mean, the
+// conic and the opacity.  Per-record gradients are summed over the wave's 64
+// pixels before one set of atomics per wave.
+//
+// k_project_bwd chains those 2D gradients through the conic inverse, the EWA
+// covariance J R Sigma R^T J^T (Eq. 1), the quaternion/scale parameterisation,
+// the projection of the mean, the SH colour and its viewing direction, and
+// into the instance cameras P = W G; k_pose_bwd maps camera gradients to the
+// poses (dL/dG = W_R^T dL/dP) and k_pose6 to the 6-DoF right perturbation.
+#include "internal.hpp"
+
+namespace s3r {
+
+// ---------------------------------------------------------------------------
+// raster backward
+// ---------------------------------------------------------------------------
+template <int TS>
+__global__ __launch_bounds__(TS* TS) void k_raster_bwd(BwdArgs a) {
+  constexpr int NT = TS * TS;
+  constexpr int NW = NT / kWave > 0 ? NT / kWave : 1;
+  __shared__ float2 s_uv[NT];
+  __shared__ float4 s_con[NT];
+  __shared__ float4 s_rgb[NT];
+  __shared__ uint32_t s_rec[NT];
+  __shared__ int s_max[NW];
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave, wave = tid / kWave;
+  const int t = blockIdx.x;
+  const int v = find_view(a.tile_offset, a.nv, t);
+  const int lt = t - a.tile_offset[v];
+  const int W = a.wh[2 * v], H = a.wh[2 * v + 1];
+  const int gx = (W + TS - 1) / TS;
+  const int px = (lt % gx) * TS + tid % TS;
+  const int py = (lt / gx) * TS + tid / TS;
+  const bool inside = (px < W) && (py < H);
+  const float fxp = (float)px, fyp = (float)py;
+  const int64_t s = a.tile_start[t];
+  const int64_t e = min((int64_t)a.tile_start[t + 1], a.kp.cap_dup);
+
+  float T = 1.f, dCr = 0.f, dCg = 0.f, dCb = 0.f;
+  int last = 0;
+  if (inside) {
+    const int64_t npx = (int64_t)W * H;
+    const int64_t p = (int64_t)py * W + px;
+    const int64_t base = 3 * a.px_offset[v];
+    T = a.T_final[a.px_offset[v] + p];
+    last = a.last[a.px_offset[v] + p];
+    dCr = a.d_color[base + p];
+    dCg = a.d_color[base + npx + p];
+    dCb = a.d_color[base + 2 * npx + p];
+  }
+  const float bgdot = T * (a.kp.bg0 * dCr + a.kp.bg1 * dCg + a.kp.bg2 * dCb);
+  float Sr = 0.f, Sg = 0.f, Sb = 0.f;
+
+  // number of list entries any pixel of the tile needs
+  int m = last;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
+  if (lane == 0) s_max[wave] = m;
+  __syncthreads();
+  int nrep = 0;
+  for (int w = 0; w < NW; ++w) nrep = max(nrep, s_max[w]);
+  const int64_t end = min(e, s + nrep);
+
+  for (int64_t b_end = end; b_end > s; b_end -= NT) {
+    const int64_t b0 = max(s, b_end - NT);
+    __syncthreads();
+    const int64_t idx = b0 + tid;
+    if (idx < b_end) {
+      const uint32_t r = a.vals[idx];
+      const float4 g = a.rec_geo[r];
+      const float4 c = a.rec_conic[r];
+      s_uv[tid] = make_float2(g.x, g.y);
+      s_con[tid] = make_float4(c.x, c.y, c.z, g.z);
+      s_rgb[tid] = a.rec_rgb[r];
+      s_rec[tid] = r;
+    }
+    __syncthreads();
+    for (int j = (int)(b_end - b0) - 1; j >= 0; --j) {
+      const int pos = (int)(b0 - s) + j;
+      float g_u = 0.f, g_v = 0.f, g_A = 0.f, g_B = 0.f, g_C = 0.f, g_o = 0.f;
+      float g_r = 0.f, g_g = 0.f, g_b = 0.f;
+      bool contrib = false;
+      if (pos < last) {
+        const float2 uv = s_uv[j];
+        const float4 con = s_con[j];
+        const float dx = uv.x - fxp;
+        const float dy = uv.y - fyp;
+        const float power =
+            fmaf(-0.5f, fmaf(con.x * dx, dx, con.z * dy * dy), -con.y * dx * dy);
+        if (!(-power > a.kp.cutoff)) {
+          const float ex = __expf(power);
+          const float raw = con.w * ex;
+          const float alpha = fminf(a.kp.alpha_max, raw);
+          if (!(alpha < a.kp.alpha_min)) {
+            contrib = true;
+            const float one_m = 1.0f - alpha;
+            const float Tb = T / one_m;
+            const float wgt = alpha * Tb;
+            const float4 col = s_rgb[j];
+            g_r = wgt * dCr;
+            g_g = wgt * dCg;
+            g_b = wgt * dCb;
+            const float cdot = col.x * dCr + col.y * dCg + col.z * dCb;
+            const float sdot = Sr * dCr + Sg * dCg + Sb * dCb;
+            const float dal = Tb * cdot - (sdot + bgdot) / one_m;
+            Sr = fmaf(col.x, wgt, Sr);
+            Sg = fmaf(col.y, wgt, Sg);
+            Sb = fmaf(col.z, wgt, Sb);
+            T = Tb;
+            if (raw <= a.kp.alpha_max) {
+              const float dpow = dal * alpha;
+              g_o = dal * ex;
+              g_u = -dpow * (con.x * dx + con.y * dy);
+              g_v = -dpow * (con.z * dy + con.y * dx);
+              g_A = -0.5f * dpow * dx * dx;
+              g_B = -dpow * dx * dy;
+              g_C = -0.5f * dpow * dy * dy;
+            }
+          }
+        }
+      }
+      if (ballot(contrib) != 0ull) {
+        g_u = wave_sum(g_u); g_v = wave_sum(g_v); g_A = wave_sum(g_A);
+        g_B = wave_sum(g_B); g_C = wave_sum(g_C); g_o = wave_sum(g_o);
+        g_r = wave_sum(g_r); g_g = wave_sum(g_g); g_b = wave_sum(g_b);
+        if (lane == 0) {
+          float* G = reinterpret_cast<float*>(a.g2d + 3 * (size_t)s_rec[j]);
+          atomicAdd(G + 0, g_u); atomicAdd(G + 1, g_v); atomicAdd(G + 2, g_A);
+          atomicAdd(G + 3, g_B); atomicAdd(G + 4, g_C); atomicAdd(G + 5, g_o);
+          atomicAdd(G + 6, g_r); atomicAdd(G + 7, g_g); atomicAdd(G + 8, g_b);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// projection / colour backward
+// ---------------------------------------------------------------------------
+// dL/dq (raw quaternion) from dL/dR of R(q / |q|)
+__device__ __forceinline__ void quat_rot_bwd(float4 q, const float dR[9], float dq[4]) {
+  const float n = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+  const float w = q.x / n, x = q.y / n, y = q.z / n, z = q.w / n;
+  const float dw = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  const float dx = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] +
+                          z * dR[6] + w * dR[7] - 2.f * x * dR[8]);
+  const float dy = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] -
+                          w * dR[6] + z * dR[7] - 2.f * y * dR[8]);
+  const float dz = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] +
+                          y * dR[5] + x * dR[6] + y * dR[7]);
+  const float dot = w * dw + x * dx + y * dy + z * dz;
+  dq[0] = (dw - w * dot) / n;
+  dq[1] = (dx - x * dot) / n;
+  dq[2] = (dy - y * dot) / n;
+  dq[3] = (dz - z * dot) / n;
+}
+
+// Sum 12 values over the lanes of a wave that share a key (key < 0: none)
+// and add them to dst + key * 12.
+__device__ __forceinline__ void wave_segmented_add(int key, const float val[12], float* dst) {
+  const int lane = lane_id();
+  uint64_t todo = ballot(key >= 0);
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const int lk = __shfl(key, leader, kWave);
+    const bool mine = (key == lk);
+    const uint64_t grp = ballot(mine);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      const float s = wave_sum(mine ? val[q] : 0.f);
+      if (lane == leader) atomicAdd(dst + (size_t)lk * 12 + q, s);
+    }
+    todo &= ~grp;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
+  const int nrec = a.counters[S3R_CNT_SURV];
+  const bool plain = (a.kp.flags & S3R_PLAIN) != 0;
+  const int B = (a.sh_deg + 1) * (a.sh_deg + 1);
+  const int stride = gridDim.x * blockDim.x;
+  for (int base = blockIdx.x * blockDim.x; base < nrec; base += stride) {
+    const int r = base + threadIdx.x;
+    const bool active = r < nrec;
+    int cam_key = -1;
+    float dcam[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) dcam[q] = 0.f;
+    if (active) {
+      const int i = a.rec_gid[r];
+      const int v = a.rec_view[r];
+      const int k = clampi(a.inst[i], 0, a.n_slots - 1);
+      const int tau = clampi(a.tstep[v], 0, a.n_ts - 1);
+      const float4 G0 = a.g2d[3 * (size_t)r], G1 = a.g2d[3 * (size_t)r + 1],
+                   G2 = a.g2d[3 * (size_t)r + 2];
+      const float du = G0.x, dv = G0.y, dA = G0.z, dB = G0.w, dC = G1.x, dO = G1.y;
+      const float drgb[3] = {G1.z, G1.w, G2.x};
+      const float4 kv = reinterpret_cast<const float4*>(a.Kv)[v];
+      const float fx = kv.x, fy = kv.y;
+      const int Wd = a.wh[2 * v], Hd = a.wh[2 * v + 1];
+
+      // ---- forward recompute ----
+      float mx, my, mz, Rg[9];
+      float4 q = make_float4(1.f, 0.f, 0.f, 0.f);
+      int slot = 0;
+      if (plain) {
+        slot = a.plain_slot[v];
+        const float* mw = a.mean_w + ((size_t)slot * a.n + i) * 3;
+        mx = mw[0]; my = mw[1]; mz = mw[2];
+        const float* rw = a.rot_w + ((size_t)slot * a.n + i) * 9;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) Rg[t] = rw[t];
+      } else {
+        mx = a.mean[3 * i]; my = a.mean[3 * i + 1]; mz = a.mean[3 * i + 2];
+        q = reinterpret_cast<const float4*>(a.quat)[i];
+        quat_rot(q.x, q.y, q.z, q.w, Rg);
+      }
+      const float sc[3] = {a.scale[3 * i], a.scale[3 * i + 1], a.scale[3 * i + 2]};
+      float P[12];
+      {
+        const float4* c4 =
+            reinterpret_cast<const float4*>(a.cam + ((size_t)v * a.n_slots + (plain ? 0 : k)) * 12);
+        const float4 c0 = c4[0], c1 = c4[1], c2 = c4[2];
+        P[0] = c0.x; P[1] = c0.y; P[2] = c0.z; P[3] = c0.w;
+        P[4] = c1.x; P[5] = c1.y; P[6] = c1.z; P[7] = c1.w;
+        P[8] = c2.x; P[9] = c2.y; P[10] = c2.z; P[11] = c2.w;
+      }
+      const float px = ((P[0] * mx + P[1] * my) + P[2] * mz) + P[3];
+      const float py = ((P[4] * mx + P[5] * my) + P[6] * mz) + P[7];
+      const float pz = ((P[8] * mx + P[9] * my) + P[10] * mz) + P[11];
+      float M[9];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) M[ii * 3 + jj] = Rg[ii * 3 + jj] * sc[jj];
+      float S[9];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+          S[ii * 3 + jj] = M[ii * 3] * M[jj * 3] + M[ii * 3 + 1] * M[jj * 3 + 1] +
+                           M[ii * 3 + 2] * M[jj * 3 + 2];
+      const float tx = px / pz, ty = py / pz;
+      const float lx = a.kp.jac_clamp * ((0.5f * (float)Wd) / fx);
+      const float ly = a.kp.jac_clamp * ((0.5f * (float)Hd) / fy);
+      const bool clx = (tx < -lx) || (tx > lx);
+      const bool cly = (ty < -ly) || (ty > ly);
+      const float txc = fminf(fmaxf(tx, -lx), lx);
+      const float tyc = fminf(fmaxf(ty, -ly), ly);
+      const float iz = 1.f / pz;
+      const float J00 = fx * iz, J02 = -fx * txc * iz, J11 = fy * iz, J12 = -fy * tyc * iz;
+      float A[6];
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) {
+        A[jj] = J00 * P[jj] + J02 * P[8 + jj];
+        A[3 + jj] = J11 * P[4 + jj] + J12 * P[8 + jj];
+      }
+      float AS[6];  // A Sigma
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+          AS[ii * 3 + jj] = A[ii * 3] * S[jj] + A[ii * 3 + 1] * S[3 + jj] + A[ii * 3 + 2] * S[6 + jj];
+      const float ca = AS[0] * A[0] + AS[1] * A[1] + AS[2] * A[2] + a.kp.eps2d;
+      const float cb = AS[0] * A[3] + AS[1] * A[4] + AS[2] * A[5];
+      const float cc = AS[3] * A[3] + AS[4] * A[4] + AS[5] * A[5] + a.kp.eps2d;
+      const float det = ca * cc - cb * cb;
+      const float id2 = 1.f / (det * det);
+
+      // ---- conic -> 2D covariance ----
+      const float d_a = (-cc * cc * dA + cb * cc * dB - cb * cb * dC) * id2;
+      const float d_b = (2.f * cb * cc * dA - (det + 2.f * cb * cb) * dB + 2.f * ca * cb * dC) * id2;
+      const float d_c = (-cb * cb * dA + ca * cb * dB - ca * ca * dC) * id2;
+      // symmetric G' = [[d_a, d_b/2], [d_b/2, d_c]]
+      const float g00 = d_a, g01 = 0.5f * d_b, g11 = d_c;
+      // dSigma = A^T G' A (3x3)
+      float GA[6];  // G' A
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) {
+        GA[jj] = g00 * A[jj] + g01 * A[3 + jj];
+        GA[3 + jj] = g01 * A[jj] + g11 * A[3 + jj];
+      }
+      float dS[9];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) dS[ii * 3 + jj] = A[ii] * GA[jj] + A[3 + ii] * GA[3 + jj];
+      // dA = 2 G' A Sigma
+      float dAm[6];
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+          dAm[ii * 3 + jj] = 2.f * (GA[ii * 3] * S[jj] + GA[ii * 3 + 1] * S[3 + jj] +
+                                    GA[ii * 3 + 2] * S[6 + jj]);
+      // A = J R_c
+      float dRc[9];
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) {
+        dRc[jj] = J00 * dAm[jj];
+        dRc[3 + jj] = J11 * dAm[3 + jj];
+        dRc[6 + jj] = J02 * dAm[jj] + J12 * dAm[3 + jj];
+      }
+      const float dJ00 = dAm[0] * P[0] + dAm[1] * P[1] + dAm[2] * P[2];
+      const float dJ02 = dAm[0] * P[8] + dAm[1] * P[9] + dAm[2] * P[10];
+      const float dJ11 = dAm[3] * P[4] + dAm[4] * P[5] + dAm[5] * P[6];
+      const float dJ12 = dAm[3] * P[8] + dAm[4] * P[9] + dAm[5] * P[10];
+      float dpx = du * fx * iz;
+      float dpy = dv * fy * iz;
+      float dpz = -(du * fx * px + dv * fy * py) * iz * iz;
+      dpz += -(dJ00 * fx + dJ11 * fy) * iz * iz;
+      // J02 = -fx txc / pz, txc = clamp(px / pz)
+      dpz += dJ02 * fx * txc * iz * iz;
+      dpz += dJ12 * fy * tyc * iz * iz;
+      if (!clx) {
+        dpx += dJ02 * (-fx * iz * iz);
+        dpz += dJ02 * (fx * iz) * (px * iz * iz);
+      }
+      if (!cly) {
+        dpy += dJ12 * (-fy * iz * iz);
+        dpz += dJ12 * (fy * iz) * (py * iz * iz);
+      }
+      // Sigma = M M^T, M = R diag(s)
+      float dM[9];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+          dM[ii * 3 + jj] = 2.f * (dS[ii * 3] * M[jj] + dS[ii * 3 + 1] * M[3 + jj] +
+                                   dS[ii * 3 + 2] * M[6 + jj]);
+      float dsc[3], dRg[9];
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) {
+        dsc[jj] = Rg[jj] * dM[jj] + Rg[3 + jj] * dM[3 + jj] + Rg[6 + jj] * dM[6 + jj];
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) dRg[ii * 3 + jj] = dM[ii * 3 + jj] * sc[jj];
+      }
+      // p = R_c mu + tau
+      float dmu[3], dtau[3] = {dpx, dpy, dpz};
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) dmu[jj] = P[jj] * dpx + P[4 + jj] * dpy + P[8 + jj] * dpz;
+      const float mm[3] = {mx, my, mz};
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) dRc[ii * 3 + jj] += dtau[ii] * mm[jj];
+
+      // ---- colour ----
+      float dl[3], w3[3] = {0.f, 0.f, 0.f};
+      const float* Gp = nullptr;
+      if (plain) {
+        const float4 cw = reinterpret_cast<const float4*>(a.cen)[(size_t)v * a.n_slots];
+        w3[0] = mx - cw.x; w3[1] = my - cw.y; w3[2] = mz - cw.z;
+        Gp = a.pose + ((size_t)tau * a.n_slots + k) * 12;
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) dl[jj] = Gp[jj] * w3[0] + Gp[4 + jj] * w3[1] + Gp[8 + jj] * w3[2];
+      } else {
+        const float4 ce = reinterpret_cast<const float4*>(a.cen)[(size_t)v * a.n_slots + k];
+        dl[0] = mx - ce.x; dl[1] = my - ce.y; dl[2] = mz - ce.z;
+      }
+      const float nrm = sqrtf(dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]);
+      const float dir[3] = {dl[0] / nrm, dl[1] / nrm, dl[2] / nrm};
+      float Y[16];
+      sh_basis(a.sh_deg, dir[0], dir[1], dir[2], Y);
+      const float* f = a.sh + (size_t)i * B * 3;
+      float raw[3] = {0.5f, 0.5f, 0.5f};
+      for (int b = 0; b < B; ++b) {
+        raw[0] += Y[b] * f[3 * b];
+        raw[1] += Y[b] * f[3 * b + 1];
+        raw[2] += Y[b] * f[3 * b + 2];
+      }
+      float dr[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dr[c] = raw[c] >= 0.f ? drgb[c] : 0.f;
+      float gb[16];
+      float* dsh = a.d_sh + (size_t)i * B * 3;
+      for (int b = 0; b < B; ++b) {
+        gb[b] = f[3 * b] * dr[0] + f[3 * b + 1] * dr[1] + f[3 * b + 2] * dr[2];
+        atomicAdd(dsh + 3 * b, Y[b] * dr[0]);
+        atomicAdd(dsh + 3 * b + 1, Y[b] * dr[1]);
+        atomicAdd(dsh + 3 * b + 2, Y[b] * dr[2]);
+      }
+      float ddir[3];
+      sh_basis_grad(a.sh_deg, dir[0], dir[1], dir[2], gb, ddir[0], ddir[1], ddir[2]);
+      const float dd = dir[0] * ddir[0] + dir[1] * ddir[1] + dir[2] * ddir[2];
+      float ddl[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ddl[c] = (ddir[c] - dir[c] * dd) / nrm;
+
+      atomicAdd(a.d_opac + i, dO);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) atomicAdd(a.d_scale + 3 * i + c, dsc[c]);
+      if (plain) {
+        // dl = R_G^T w, w = mu_w - c_w
+        float dw[3];
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) dw[ii] = Gp[ii * 4] * ddl[0] + Gp[ii * 4 + 1] * ddl[1] + Gp[ii * 4 + 2] * ddl[2];
+        float* dmw = a.d_mean_w + ((size_t)slot * a.n + i) * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) atomicAdd(dmw + c, dmu[c] + dw[c]);
+        float* drw = a.d_rot_w + ((size_t)slot * a.n + i) * 9;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) atomicAdd(drw + t, dRg[t]);
+        if (k > 0) {
+          // dR_G[j][i] += w_j ddl_i (rotation part of the pose)
+#pragma unroll
+          for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < 3; ++ii) dcam[jj * 4 + ii] = w3[jj] * ddl[ii];
+          cam_key = tau * a.n_slots + k;
+        }
+      } else {
+        // d = mu - cen, cen = -R_c^T tau
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dmu[c] += ddl[c];
+        const float dcen[3] = {-ddl[0], -ddl[1], -ddl[2]};
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+#pragma unroll
+          for (int jj = 0; jj < 3; ++jj) dRc[ii * 3 + jj] += -P[ii * 4 + 3] * dcen[jj];
+          dtau[ii] += -(P[ii * 4] * dcen[0] + P[ii * 4 + 1] * dcen[1] + P[ii * 4 + 2] * dcen[2]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) atomicAdd(a.d_mean + 3 * i + c, dmu[c]);
+        float dq[4];
+        quat_rot_bwd(q, dRg, dq);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) atomicAdd(a.d_quat + 4 * i + c, dq[c]);
+        if (k > 0) {
+#pragma unroll
+          for (int ii = 0; ii < 3; ++ii) {
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) dcam[ii * 4 + jj] = dRc[ii * 3 + jj];
+            dcam[ii * 4 + 3] = dtau[ii];
+          }
+          cam_key = v * a.n_slots + k;
+        }
+      }
+    }
+    wave_segmented_add(cam_key, dcam, plain ? a.d_pose : a.d_cam);
+  }
+}
+
+// dL/dG_{tau,k} += W_R^T dL/dP_{v,k} for every view v (slot 0 skipped)
+__global__ void k_pose_bwd(const float* __restrict__ W, const int32_t* __restrict__ tstep,
+                           const float* __restrict__ d_cam, int nv, int S, int T,
+                           float* __restrict__ d_pose) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nv * S) return;
+  const int v = idx / S, k = idx % S;
+  if (k == 0) return;
+  const float* w = W + v * 12;
+  const float* dP = d_cam + (size_t)idx * 12;
+  float* dG = d_pose + ((size_t)clampi(tstep[v], 0, T - 1) * S + k) * 12;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float g = w[0 * 4 + r] * dP[0 * 4 + c] + w[1 * 4 + r] * dP[1 * 4 + c] +
+                      w[2 * 4 + r] * dP[2 * 4 + c];
+      if (g != 0.f) atomicAdd(dG + r * 4 + c, g);
+    }
+}
+
+// 6-DoF form of the pose gradient: M = G~^T D, rho = M[0:3,3],
+// omega = (M21 - M12, M02 - M20, M10 - M01)
+__global__ void k_pose6(const float* __restrict__ pose, const float* __restrict__ d_pose, int TS_,
+                        int S, float* __restrict__ d_pose6) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= TS_) return;
+  float* o = d_pose6 + (size_t)idx * 6;
+  if (idx % S == 0) return;
+  const float* G = pose + (size_t)idx * 12;
+  const float* D = d_pose + (size_t)idx * 12;
+  float M[12];  // rows 0..2 of G~^T D: M[i][c] = sum_r G[r][i] D[r][c]
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      M[i * 4 + c] = G[0 * 4 + i] * D[0 * 4 + c] + G[1 * 4 + i] * D[1 * 4 + c] +
+                     G[2 * 4 + i] * D[2 * 4 + c];
+  o[0] = M[3]; o[1] = M[7]; o[2] = M[11];
+  o[3] = M[2 * 4 + 1] - M[1 * 4 + 2];
+  o[4] = M[0 * 4 + 2] - M[2 * 4 + 0];
+  o[5] = M[1 * 4 + 0] - M[0 * 4 + 1];
+}
+
+// plain route: world-frame gradients -> local mean / quaternion and poses
+struct TsList2 {
+  int32_t tau[kMaxViews];
+};
+
+__global__ __launch_bounds__(256) void k_plain_transform_bwd(
+    const float* __restrict__ mean, const float* __restrict__ quat,
+    const int32_t* __restrict__ inst, const float* __restrict__ pose, int n, int S, TsList2 ts,
+    int n_ts, const float* __restrict__ d_mean_w, const float* __restrict__ d_rot_w,
+    float* __restrict__ d_mean, float* __restrict__ d_quat, float* __restrict__ d_pose) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int base = blockIdx.x * blockDim.x; base < n; base += stride) {
+    const int i = base + threadIdx.x;
+    const bool active = i < n;
+    const int k = active ? clampi(inst[i], 0, S - 1) : 0;
+    float mu[3] = {0.f, 0.f, 0.f};
+    float4 q = make_float4(1.f, 0.f, 0.f, 0.f);
+    float Rq[9];
+    if (active) {
+      mu[0] = mean[3 * i]; mu[1] = mean[3 * i + 1]; mu[2] = mean[3 * i + 2];
+      q = reinterpret_cast<const float4*>(quat)[i];
+    }
+    quat_rot(q.x, q.y, q.z, q.w, Rq);
+    float dmu[3] = {0.f, 0.f, 0.f}, dRq[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) dRq[t] = 0.f;
+    for (int sl = 0; sl < n_ts; ++sl) {
+      float dG[12];
+#pragma unroll
+      for (int t = 0; t < 12; ++t) dG[t] = 0.f;
+      int key = -1;
+      if (active) {
+        const float* G = pose + ((size_t)ts.tau[sl] * S + k) * 12;
+        const float* dmw = d_mean_w + ((size_t)sl * n + i) * 3;
+        const float* drw = d_rot_w + ((size_t)sl * n + i) * 9;
+        float gm[3] = {dmw[0], dmw[1], dmw[2]}, gr[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) gr[t] = drw[t];
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+          dmu[jj] += G[jj] * gm[0] + G[4 + jj] * gm[1] + G[8 + jj] * gm[2];
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc)
+            dRq[jj * 3 + cc] += G[jj] * gr[cc] + G[4 + jj] * gr[3 + cc] + G[8 + jj] * gr[6 + cc];
+        }
+        if (k > 0) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              dG[r * 4 + c] = gm[r] * mu[c] + gr[r * 3] * Rq[c * 3] + gr[r * 3 + 1] * Rq[c * 3 + 1] +
+                              gr[r * 3 + 2] * Rq[c * 3 + 2];
+            dG[r * 4 + 3] = gm[r];
+          }
+          key = ts.tau[sl] * S + k;
+        }
+      }
+      wave_segmented_add(key, dG, d_pose);
+    }
+    if (active) {
+      float dq[4];
+      quat_rot_bwd(q, dRq, dq);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) d_mean[3 * i + c] += dmu[c];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) d_quat[4 * i + c] += dq[c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+// zero the per-record gradient slots of the records that exist
+__global__ __launch_bounds__(256) void k_zero_g2d(float4* __restrict__ g2d,
+                                                  const int32_t* __restrict__ counters) {
+  const int64_t n = 3 * (int64_t)counters[S3R_CNT_SURV];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    g2d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_g2d, dim3(1024), dim3(256), 0, st, a.g2d, a.counters);
+  if (a.total_tiles <= 0) return hipGetLastError();
+  switch (a.kp.tile) {
+    case 8:
+      hipLaunchKernelGGL(k_raster_bwd<8>, dim3(a.total_tiles), dim3(64), 0, st, a);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_raster_bwd<16>, dim3(a.total_tiles), dim3(256), 0, st, a);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_raster_bwd<32>, dim3(a.total_tiles), dim3(1024), 0, st, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const ProjBwdArgs& a, int64_t cap_surv, hipStream_t st) {
+  const int64_t want = (cap_surv + 255) / 256;
+  const int grid = (int)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+  hipLaunchKernelGGL(k_project_bwd, dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_bwd(const float* W, const int32_t* tstep, const float* pose,
+                           const float* d_cam, int nv, int S, int T, float* d_pose,
+                           float* d_pose6, hipStream_t st) {
+  const int nvs = nv * S;
+  if (d_cam != nullptr && nvs > 0)
+    hipLaunchKernelGGL(k_pose_bwd, dim3((nvs + 127) / 128), dim3(128), 0, st, W, tstep, d_cam, nv,
+                       S, T, d_pose);
+  const int ts = T * S;
+  if (d_pose6 != nullptr && ts > 0)
+    hipLaunchKernelGGL(k_pose6, dim3((ts + 127) / 128), dim3(128), 0, st, pose, d_pose, ts, S,
+                       d_pose6);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_transform_bwd(const float* mean, const float* quat, const int32_t* inst,
+                                      const float* pose, int n, int S, const int32_t* tsteps,
+                                      int n_ts, const float* d_mean_w, const float* d_rot_w,
+                                      float* d_mean, float* d_quat, float* d_pose,
+                                      float* d_pose6, hipStream_t st) {
+  TsList2 ts;
+  for (int s = 0; s < kMaxViews; ++s) ts.tau[s] = s < n_ts ? tsteps[s] : 0;
+  const int64_t want = ((int64_t)n + 255) / 256;
+  const int grid = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+  hipLaunchKernelGGL(k_plain_transform_bwd, dim3(grid), dim3(256), 0, st, mean, quat, inst, pose,
+                     n, S, ts, n_ts, d_mean_w, d_rot_w, d_mean, d_quat, d_pose);
+  return hipGetLastError();
+}
+
+}  // namespace s3r

@@ -1,0 +1,293 @@
+// Device-side building blocks shared by the gfx950 kernels.
+//
+// Everything here is compiled with -ffp-contract=off and correctly rounded
+// binary32 division and square root, so the projection below evaluates each
+// expression exactly in the order it is written: every decision it feeds
+// (depth test, determinant sign, footprint rectangle, LOD test, depth key) is
+// reproducible bit for bit.  Rasterisation code that wants fused multiply-adds
+// asks for them explicitly with fmaf().
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/s3r.h"
+
+namespace s3r {
+
+constexpr int kWave = 64;
+constexpr int kMaxViews = 64;
+
+// ---------------------------------------------------------------------------
+// wave-level primitives (wave64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ int lane_rank(uint64_t mask) {
+  uint32_t lo = __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u);
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), lo);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// parameters copied by value into every kernel
+// ---------------------------------------------------------------------------
+struct KParams {
+  int tile;
+  uint32_t flags;
+  float lod_r, z_near, z_far, eps2d, alpha_min, alpha_max, t_min, cutoff, jac_clamp;
+  float bg0, bg1, bg2;
+  int64_t cap_surv, cap_dup;
+};
+
+// ---------------------------------------------------------------------------
+// canonical binary32 projection of one Gaussian into one view
+// ---------------------------------------------------------------------------
+struct Proj {
+  float px, py, pz;
+  float u, v;
+  float a_raw, b, c_raw;  // undilated 2D covariance
+  float a, c, det;        // dilated entries and determinant
+  float lam_raw;
+  int x0, y0, x1, y1;     // tile rectangle [x0,x1) x [y0,y1)
+  bool depth_ok, visible, keep;
+};
+
+// Unit quaternion (w,x,y,z) -> rotation, normalising first.
+__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float R[9]) {
+  float n = sqrtf(((w * w + x * x) + y * y) + z * z);
+  w = w / n; x = x / n; y = y / n; z = z / n;
+  float xx = x * x, yy = y * y, zz = z * z;
+  float xy = x * y, xz = x * z, yz = y * z;
+  float wx = w * x, wy = w * y, wz = w * z;
+  R[0] = 1.0f - 2.0f * (yy + zz); R[1] = 2.0f * (xy - wz); R[2] = 2.0f * (xz + wy);
+  R[3] = 2.0f * (xy + wz); R[4] = 1.0f - 2.0f * (xx + zz); R[5] = 2.0f * (yz - wx);
+  R[6] = 2.0f * (xz - wy); R[7] = 2.0f * (yz + wx); R[8] = 1.0f - 2.0f * (xx + yy);
+}
+
+__device__ __forceinline__ float lam_max(float a, float c, float det) {
+  float m = 0.5f * (a + c);
+  float disc = m * m - det;
+  return m + sqrtf(fmaxf(disc, 0.0f));
+}
+
+__device__ __forceinline__ float clamp_nan(float v, float hi) {
+  // clamp to [0, hi], propagating NaN like numpy's maximum/minimum
+  return (v != v) ? v : fminf(fmaxf(v, 0.0f), hi);
+}
+
+// Rg: the Gaussian's rotation (row-major 3x3), s: its scales, P: camera 3x4
+// (row-major), mean: position in the frame P maps from.
+__device__ __forceinline__ void project_canonical(const float P[12], float mx, float my, float mz,
+                                                  const float Rg[9], float s0, float s1, float s2,
+                                                  float fx, float fy, float cx, float cy, int W,
+                                                  int H, const KParams& kp, Proj& o) {
+  o.px = ((P[0] * mx + P[1] * my) + P[2] * mz) + P[3];
+  o.py = ((P[4] * mx + P[5] * my) + P[6] * mz) + P[7];
+  o.pz = ((P[8] * mx + P[9] * my) + P[10] * mz) + P[11];
+  o.depth_ok = (kp.z_near < o.pz) && (o.pz < kp.z_far);
+
+  float M[9];
+  M[0] = Rg[0] * s0; M[1] = Rg[1] * s1; M[2] = Rg[2] * s2;
+  M[3] = Rg[3] * s0; M[4] = Rg[4] * s1; M[5] = Rg[5] * s2;
+  M[6] = Rg[6] * s0; M[7] = Rg[7] * s1; M[8] = Rg[8] * s2;
+  float S00 = (M[0] * M[0] + M[1] * M[1]) + M[2] * M[2];
+  float S01 = (M[0] * M[3] + M[1] * M[4]) + M[2] * M[5];
+  float S02 = (M[0] * M[6] + M[1] * M[7]) + M[2] * M[8];
+  float S11 = (M[3] * M[3] + M[4] * M[4]) + M[5] * M[5];
+  float S12 = (M[3] * M[6] + M[4] * M[7]) + M[5] * M[8];
+  float S22 = (M[6] * M[6] + M[7] * M[7]) + M[8] * M[8];
+
+  float tx = o.px / o.pz;
+  float ty = o.py / o.pz;
+  float lx = kp.jac_clamp * ((0.5f * (float)W) / fx);
+  float ly = kp.jac_clamp * ((0.5f * (float)H) / fy);
+  float txc = fminf(fmaxf(tx, -lx), lx);
+  float tyc = fminf(fmaxf(ty, -ly), ly);
+  float j00 = fx / o.pz;
+  float j02 = -((fx * txc) / o.pz);
+  float j11 = fy / o.pz;
+  float j12 = -((fy * tyc) / o.pz);
+
+  float A00 = j00 * P[0] + j02 * P[8];
+  float A01 = j00 * P[1] + j02 * P[9];
+  float A02 = j00 * P[2] + j02 * P[10];
+  float A10 = j11 * P[4] + j12 * P[8];
+  float A11 = j11 * P[5] + j12 * P[9];
+  float A12 = j11 * P[6] + j12 * P[10];
+
+  float B00 = (A00 * S00 + A01 * S01) + A02 * S02;
+  float B01 = (A00 * S01 + A01 * S11) + A02 * S12;
+  float B02 = (A00 * S02 + A01 * S12) + A02 * S22;
+  float B10 = (A10 * S00 + A11 * S01) + A12 * S02;
+  float B11 = (A10 * S01 + A11 * S11) + A12 * S12;
+  float B12 = (A10 * S02 + A11 * S12) + A12 * S22;
+
+  o.a_raw = (B00 * A00 + B01 * A01) + B02 * A02;
+  o.b = (B00 * A10 + B01 * A11) + B02 * A12;
+  o.c_raw = (B10 * A10 + B11 * A11) + B12 * A12;
+  o.a = o.a_raw + kp.eps2d;
+  o.c = o.c_raw + kp.eps2d;
+  o.det = o.a * o.c - o.b * o.b;
+  float det_raw = o.a_raw * o.c_raw - o.b * o.b;
+  float lam_d = lam_max(o.a, o.c, o.det);
+  o.lam_raw = lam_max(o.a_raw, o.c_raw, det_raw);
+  float rad = ceilf(3.0f * sqrtf(lam_d));
+  o.u = fx * tx + cx;
+  o.v = fy * ty + cy;
+
+  const int ts = kp.tile;
+  const float sf = (float)ts;
+  const int gx = (W + ts - 1) / ts;
+  const int gy = (H + ts - 1) / ts;
+  float x0f = clamp_nan(floorf((o.u - rad) / sf), (float)gx);
+  float x1f = clamp_nan(floorf((o.u + rad) / sf) + 1.0f, (float)gx);
+  float y0f = clamp_nan(floorf((o.v - rad) / sf), (float)gy);
+  float y1f = clamp_nan(floorf((o.v + rad) / sf) + 1.0f, (float)gy);
+  bool bad = (x0f != x0f) || (x1f != x1f) || (y0f != y0f) || (y1f != y1f);
+  o.x0 = bad ? 0 : (int)x0f;
+  o.x1 = bad ? 0 : (int)x1f;
+  o.y0 = bad ? 0 : (int)y0f;
+  o.y1 = bad ? 0 : (int)y1f;
+  o.visible = o.depth_ok && (o.det > 0.0f) && (o.x1 > o.x0) && (o.y1 > o.y0);
+  const float r = kp.lod_r;
+  const bool lod = (kp.flags & S3R_LOD) && (r > 0.0f);
+  o.keep = !(lod && (o.lam_raw <= r * r));
+}
+
+// ---------------------------------------------------------------------------
+// real spherical harmonics, degree <= 3 (3DGS sign convention)
+// ---------------------------------------------------------------------------
+constexpr float kC0 = 0.28209479177387814f;
+constexpr float kC1 = 0.4886025119029199f;
+constexpr float kC2_0 = 1.0925484305920792f;
+constexpr float kC2_1 = -1.0925484305920792f;
+constexpr float kC2_2 = 0.31539156525252005f;
+constexpr float kC2_3 = -1.0925484305920792f;
+constexpr float kC2_4 = 0.5462742152960396f;
+constexpr float kC3_0 = -0.5900435899266435f;
+constexpr float kC3_1 = 2.890611442640554f;
+constexpr float kC3_2 = -0.4570457994644658f;
+constexpr float kC3_3 = 0.3731763325901154f;
+constexpr float kC3_4 = -0.4570457994644658f;
+constexpr float kC3_5 = 1.445305721320277f;
+constexpr float kC3_6 = -0.5900435899266435f;
+
+__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float Y[16]) {
+  Y[0] = kC0;
+  if (deg < 1) return;
+  Y[1] = -kC1 * y; Y[2] = kC1 * z; Y[3] = -kC1 * x;
+  if (deg < 2) return;
+  float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = kC2_0 * (x * y);
+  Y[5] = kC2_1 * (y * z);
+  Y[6] = kC2_2 * (2.0f * zz - xx - yy);
+  Y[7] = kC2_3 * (x * z);
+  Y[8] = kC2_4 * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = kC3_0 * y * (3.0f * xx - yy);
+  Y[10] = kC3_1 * (x * y) * z;
+  Y[11] = kC3_2 * y * (4.0f * zz - xx - yy);
+  Y[12] = kC3_3 * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+  Y[13] = kC3_4 * x * (4.0f * zz - xx - yy);
+  Y[14] = kC3_5 * z * (xx - yy);
+  Y[15] = kC3_6 * x * (xx - 3.0f * yy);
+}
+
+// d(sum_b g_b Y_b)/d(x,y,z) for per-basis weights g_b.
+__device__ __forceinline__ void sh_basis_grad(int deg, float x, float y, float z, const float g[16],
+                                              float& dx, float& dy, float& dz) {
+  dx = 0.f; dy = 0.f; dz = 0.f;
+  if (deg < 1) return;
+  dy += -kC1 * g[1]; dz += kC1 * g[2]; dx += -kC1 * g[3];
+  if (deg < 2) return;
+  float xx = x * x, yy = y * y, zz = z * z;
+  dx += kC2_0 * y * g[4]; dy += kC2_0 * x * g[4];
+  dy += kC2_1 * z * g[5]; dz += kC2_1 * y * g[5];
+  dx += -2.0f * kC2_2 * x * g[6]; dy += -2.0f * kC2_2 * y * g[6]; dz += 4.0f * kC2_2 * z * g[6];
+  dx += kC2_3 * z * g[7]; dz += kC2_3 * x * g[7];
+  dx += 2.0f * kC2_4 * x * g[8]; dy += -2.0f * kC2_4 * y * g[8];
+  if (deg < 3) return;
+  dx += kC3_0 * 6.0f * x * y * g[9]; dy += kC3_0 * (3.0f * xx - 3.0f * yy) * g[9];
+  dx += kC3_1 * y * z * g[10]; dy += kC3_1 * x * z * g[10]; dz += kC3_1 * x * y * g[10];
+  dx += kC3_2 * (-2.0f * x * y) * g[11]; dy += kC3_2 * (4.0f * zz - xx - 3.0f * yy) * g[11];
+  dz += kC3_2 * 8.0f * y * z * g[11];
+  dx += kC3_3 * (-6.0f * x * z) * g[12]; dy += kC3_3 * (-6.0f * y * z) * g[12];
+  dz += kC3_3 * (6.0f * zz - 3.0f * xx - 3.0f * yy) * g[12];
+  dx += kC3_4 * (4.0f * zz - 3.0f * xx - yy) * g[13]; dy += kC3_4 * (-2.0f * x * y) * g[13];
+  dz += kC3_4 * 8.0f * x * z * g[13];
+  dx += kC3_5 * 2.0f * x * z * g[14]; dy += kC3_5 * (-2.0f * y * z) * g[14];
+  dz += kC3_5 * (xx - yy) * g[14];
+  dx += kC3_6 * (3.0f * xx - 3.0f * yy) * g[15]; dy += kC3_6 * (-6.0f * x * y) * g[15];
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+__device__ __forceinline__ int find_view(const int32_t* __restrict__ tile_offset, int nv, int t) {
+  int v = 0;
+  while (v + 1 < nv && tile_offset[v + 1] <= t) ++v;
+  return v;
+}
+
+__device__ __forceinline__ uint64_t ld_acquire(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Decoupled look-back (single-pass exclusive scan across workgroups).
+// Called by one full wave; `flags` holds (status << 32 | value) per virtual
+// block: status 1 = aggregate of that block, 2 = inclusive prefix.  Returns
+// the exclusive prefix of block `vb`.  Predecessors take their ticket before
+// this block does, so they are resident and publish without waiting on
+// anything; the wait is still bounded, and gives up (flagging `spin_err`) so
+// that every wave always exits.
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+__device__ __forceinline__ uint32_t lookback(uint64_t* flags, int vb, int32_t* spin_err) {
+  const int lane = lane_id();
+  uint32_t excl = 0;
+  int base = vb - 1;
+  uint32_t spins = 0;
+  while (base >= 0) {
+    int j = base - lane;
+    uint64_t f = (j >= 0) ? ld_acquire(flags + j) : (2ull << 32);
+    uint32_t st = (uint32_t)(f >> 32);
+    uint64_t zero = ballot(st == 0u);
+    uint64_t incl = ballot(st == 2u);
+    int first = incl ? (__ffsll((unsigned long long)incl) - 1) : 64;
+    uint64_t need = (first >= 63) ? ~0ull : ((1ull << (first + 1)) - 1ull);
+    if ((zero & need) != 0ull) {
+      if (++spins < kSpinLimit) {
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      if (lane == 0) atomicExch(spin_err, 1);
+    }
+    uint32_t val = (lane <= first && st != 0u) ? (uint32_t)f : 0u;
+    excl += wave_sum_u32(val);
+    if (first < 64) break;
+    base -= kWave;
+  }
+  return excl;
+}
+
+}  // namespace s3r

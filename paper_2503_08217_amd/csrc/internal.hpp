@@ -1,0 +1,171 @@
+// Kernel argument blocks and host launchers shared between the translation
+// units of the library (not part of the public ABI).
+#pragma once
+
+#include "common.hpp"
+
+namespace s3r {
+
+struct ProjArgs {
+  // scene
+  const float* mean;
+  const float* scale;
+  const float* quat;
+  const float* opac;
+  const float* sh;
+  const int32_t* inst;
+  const float* vis_s;
+  const float* vis_e;
+  const float* pose;
+  const float* mean_w;
+  const float* rot_w;
+  int n, sh_deg, n_slots, n_ts;
+  // views
+  const float* Kv;
+  const int32_t* wh;
+  const int32_t* tstep;
+  const int32_t* tile_offset;
+  const int32_t* plain_slot;
+  int nv;
+  // per-view products of k_compose
+  const float* cam;
+  const float* cen;
+  const float* t_norm;
+  // outputs
+  uint32_t* mask;
+  int64_t mask_words;
+  int32_t* rec_gid;
+  int32_t* rec_view;
+  float4* rec_geo;
+  float4* rec_conic;
+  float4* rec_rgb;
+  int4* rec_rect;
+  int32_t* counters;
+  int32_t* tile_count;
+  // workspace
+  uint64_t* flags;
+  int32_t* bstat;
+  int nblk;
+  KParams kp;
+};
+
+struct RasterArgs {
+  const float4* rec_geo;
+  const float4* rec_conic;
+  const float4* rec_rgb;
+  const int32_t* tile_start;
+  const uint32_t* vals;
+  const int32_t* tile_offset;
+  const int64_t* px_offset;
+  const int32_t* wh;
+  const int32_t* counters;
+  int nv, total_tiles;
+  float* color;
+  float* T_final;
+  int32_t* last;
+  KParams kp;
+};
+
+struct BwdArgs {
+  // forward state
+  const float4* rec_geo;
+  const float4* rec_conic;
+  const float4* rec_rgb;
+  const int32_t* rec_gid;
+  const int32_t* rec_view;
+  const int32_t* tile_start;
+  const uint32_t* vals;
+  const int32_t* tile_offset;
+  const int64_t* px_offset;
+  const int32_t* wh;
+  const int32_t* counters;
+  const float* T_final;
+  const int32_t* last;
+  const float* d_color;
+  int nv, total_tiles;
+  // per-record 2D gradients (workspace), 12 floats each
+  float4* g2d;
+  KParams kp;
+};
+
+struct ProjBwdArgs {
+  const float* mean;
+  const float* scale;
+  const float* quat;
+  const float* opac;
+  const float* sh;
+  const int32_t* inst;
+  const float* pose;
+  const float* mean_w;
+  const float* rot_w;
+  int n, sh_deg, n_slots, n_ts;
+  const float* Kv;
+  const int32_t* wh;
+  const int32_t* tstep;
+  const int32_t* plain_slot;
+  int nv;
+  const float* cam;
+  const float* cen;
+  const int32_t* rec_gid;
+  const int32_t* rec_view;
+  const int32_t* counters;
+  const float4* g2d;
+  // gradients (accumulated)
+  float* d_mean;
+  float* d_scale;
+  float* d_quat;
+  float* d_opac;
+  float* d_sh;
+  float* d_mean_w;
+  float* d_rot_w;
+  float* d_cam;    // [V][S][12] workspace
+  float* d_pose;   // [T][S][12] (plain route: colour-direction part)
+  KParams kp;
+};
+
+// project.hip
+hipError_t launch_compose(const float* W, const int32_t* tstep, const float* pose, int S, int T,
+                          int nv, float* cam, float* cen, float* t_norm, hipStream_t st);
+hipError_t launch_plain_transform(const float* mean, const float* quat, const int32_t* inst,
+                                  const float* pose, int n, int S, const int32_t* tsteps, int n_ts,
+                                  float* mean_w, float* rot_w, hipStream_t st);
+int project_blocks(int64_t n);
+hipError_t launch_project(const ProjArgs& a, int32_t* stats, hipStream_t st);
+
+// util.hip
+hipError_t launch_zero(void* p0, size_t b0, void* p1, size_t b1, void* p2, size_t b2, void* p3,
+                       size_t b3, hipStream_t st);
+
+// sort.hip
+int scan_blocks(int64_t n);
+hipError_t launch_sort(const int32_t* tile_count, int total_tiles, const int32_t* tile_offset,
+                       int nv, const int32_t* wh, int tile, const int4* rec_rect,
+                       const float4* rec_geo, const int32_t* rec_view, int32_t* counters,
+                       int32_t* stats, int32_t* tile_start, uint32_t* vals, uint64_t* keys,
+                       uint64_t* keys_alt, int32_t* cursor, uint64_t* scan_flags,
+                       int64_t cap_dup, int64_t cap_surv, hipStream_t st);
+
+// raster.hip
+hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st);
+hipError_t launch_l1_loss(const float* color, const float* target, const int64_t* px_offset,
+                          const int32_t* wh, int nv, int64_t total_px, float* loss,
+                          float* d_color, hipStream_t st);
+
+// backward.hip
+hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st);
+hipError_t launch_project_bwd(const ProjBwdArgs& a, int64_t cap_surv, hipStream_t st);
+hipError_t launch_pose_bwd(const float* W, const int32_t* tstep, const float* pose,
+                           const float* d_cam, int nv, int S, int T, float* d_pose,
+                           float* d_pose6, hipStream_t st);
+hipError_t launch_plain_transform_bwd(const float* mean, const float* quat, const int32_t* inst,
+                                      const float* pose, int n, int S, const int32_t* tsteps,
+                                      int n_ts, const float* d_mean_w, const float* d_rot_w,
+                                      float* d_mean, float* d_quat, float* d_pose,
+                                      float* d_pose6, hipStream_t st);
+
+// visibility.hip
+hipError_t launch_visibility(float* life_s, float* life_e, float* vis_s, float* vis_e,
+                             const uint32_t* mask, const float* t_norm, int nv, int64_t n,
+                             int mode, float margin, hipStream_t st);
+
+}  // namespace s3r

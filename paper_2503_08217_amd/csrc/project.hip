@@ -1,0 +1,371 @@
+// Front end of the per-view step (Sec. 3.3): instance cameras, temporal
+// selection, projection (Eq. 1), frustum mask M_t, LOD cull, SH colour of the
+// survivors, and compaction of the survivors into records.
+//
+// k_project is a single pass over the Gaussians.  Each workgroup owns 256
+// consecutive Gaussians (in the order it took its ticket) and loops over the
+// views of the batch, so a Gaussian's 44 bytes of geometry are read once per
+// batch however many views there are.  Survivors are compacted with wave
+// ballots and a decoupled look-back across workgroups, which gives every
+// record a deterministic slot (Gaussian block, then view, then Gaussian) in
+// one pass with no second read of the Gaussians.
+#include "internal.hpp"
+
+namespace s3r {
+
+// ---------------------------------------------------------------------------
+// a1: instance cameras P_{v,k} = W_v G_{tau_v,k} (FP64, rounded once) and the
+//     normalised time of each view.
+// ---------------------------------------------------------------------------
+__global__ void k_compose(const float* __restrict__ W, const int32_t* __restrict__ tstep,
+                          const float* __restrict__ pose, int S, int T, int nv,
+                          float* __restrict__ cam, float* __restrict__ cen,
+                          float* __restrict__ t_norm) {
+  const int v = blockIdx.x;
+  const int tau = clampi(tstep[v], 0, T - 1);
+  if (threadIdx.x == 0) {
+    t_norm[v] = (T > 1) ? (float)(-1.0 + (2.0 * (double)tau) / (double)(T - 1)) : 0.0f;
+  }
+  double w[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) w[q] = (double)W[v * 12 + q];
+  for (int k = threadIdx.x; k < S; k += blockDim.x) {
+    const float* G = pose + ((size_t)tau * S + k) * 12;
+    double g[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) g[q] = (double)G[q];
+    double P[12];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double acc = w[r * 4 + 0] * g[0 * 4 + c];
+        acc = acc + w[r * 4 + 1] * g[1 * 4 + c];
+        acc = acc + w[r * 4 + 2] * g[2 * 4 + c];
+        acc = acc + w[r * 4 + 3] * (c == 3 ? 1.0 : 0.0);
+        P[r * 4 + c] = acc;
+      }
+    }
+    float* o = cam + ((size_t)v * S + k) * 12;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) o[q] = (float)P[q];
+    float* ce = cen + ((size_t)v * S + k) * 4;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double s = (P[0 * 4 + j] * P[3] + P[1 * 4 + j] * P[7]) + P[2 * 4 + j] * P[11];
+      ce[j] = (float)(-s);
+    }
+    ce[3] = 0.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// p1: conventional local->global transform (plain route): for each timestep
+//     slot s, mean_w = R_G mean + t_G and rot_w = R_G R(q).
+// ---------------------------------------------------------------------------
+struct TsList {
+  int32_t tau[kMaxViews];
+};
+
+__global__ __launch_bounds__(256) void k_plain_transform(
+    const float* __restrict__ mean, const float* __restrict__ quat,
+    const int32_t* __restrict__ inst, const float* __restrict__ pose, int n, int S, TsList ts,
+    int n_ts, float* __restrict__ mean_w, float* __restrict__ rot_w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float mx = mean[3 * i], my = mean[3 * i + 1], mz = mean[3 * i + 2];
+  const float4 q = reinterpret_cast<const float4*>(quat)[i];
+  float Rq[9];
+  quat_rot(q.x, q.y, q.z, q.w, Rq);
+  const int k = clampi(inst[i], 0, S - 1);
+  for (int s = 0; s < n_ts; ++s) {
+    const float* G = pose + ((size_t)ts.tau[s] * S + k) * 12;
+    float g[12];
+#pragma unroll
+    for (int t = 0; t < 12; ++t) g[t] = G[t];
+    float* mw = mean_w + ((size_t)s * n + i) * 3;
+    mw[0] = ((g[0] * mx + g[1] * my) + g[2] * mz) + g[3];
+    mw[1] = ((g[4] * mx + g[5] * my) + g[6] * mz) + g[7];
+    mw[2] = ((g[8] * mx + g[9] * my) + g[10] * mz) + g[11];
+    float* rw = rot_w + ((size_t)s * n + i) * 9;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        rw[r * 3 + c] = (g[r * 4 + 0] * Rq[0 * 3 + c] + g[r * 4 + 1] * Rq[1 * 3 + c]) +
+                        g[r * 4 + 2] * Rq[2 * 3 + c];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a2-a5: temporal test, projection, M_t, LOD, colour, compaction.
+// ---------------------------------------------------------------------------
+constexpr int kProjBlock = 256;
+constexpr int kProjWaves = kProjBlock / kWave;
+
+struct Loaded {
+  float mx, my, mz;
+  float R[9];  // the Gaussian's rotation (local, or world for the plain route)
+  float s0, s1, s2;
+  int k;
+};
+
+__device__ __forceinline__ void load_camera(const float* __restrict__ cam, int v, int S, int slot,
+                                            float P[12]) {
+  const float4* c4 = reinterpret_cast<const float4*>(cam + ((size_t)v * S + slot) * 12);
+  float4 a = c4[0], b = c4[1], c = c4[2];
+  P[0] = a.x; P[1] = a.y; P[2] = a.z; P[3] = a.w;
+  P[4] = b.x; P[5] = b.y; P[6] = b.z; P[7] = b.w;
+  P[8] = c.x; P[9] = c.y; P[10] = c.z; P[11] = c.w;
+}
+
+__device__ __forceinline__ void view_geometry(const ProjArgs& a, int v, const Loaded& g,
+                                              bool plain, int i, Loaded& eff, float P[12],
+                                              float& fx, float& fy, float& cx, float& cy, int& W,
+                                              int& H) {
+  const float4 kv = reinterpret_cast<const float4*>(a.Kv)[v];
+  fx = kv.x; fy = kv.y; cx = kv.z; cy = kv.w;
+  W = a.wh[2 * v];
+  H = a.wh[2 * v + 1];
+  eff = g;
+  if (plain) {
+    const int slot = a.plain_slot[v];
+    const float* mw = a.mean_w + ((size_t)slot * a.n + i) * 3;
+    eff.mx = mw[0]; eff.my = mw[1]; eff.mz = mw[2];
+    const float* rw = a.rot_w + ((size_t)slot * a.n + i) * 9;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) eff.R[t] = rw[t];
+    load_camera(a.cam, v, a.n_slots, 0, P);
+  } else {
+    load_camera(a.cam, v, a.n_slots, g.k, P);
+  }
+}
+
+__global__ __launch_bounds__(kProjBlock) void k_project(ProjArgs a) {
+  __shared__ int s_vb;
+  __shared__ uint64_t s_ball[kMaxViews][kProjWaves];
+  __shared__ int s_ct[kMaxViews][kProjWaves];
+  __shared__ int s_cf[kMaxViews][kProjWaves];
+  __shared__ uint32_t s_off[kMaxViews][kProjWaves];
+  __shared__ uint32_t s_excl;
+
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  if (tid == 0) s_vb = atomicAdd(&a.counters[S3R_CNT_TICKET], 1);
+  __syncthreads();
+  const int vb = s_vb;
+  const int i = vb * kProjBlock + tid;
+  const bool valid = i < a.n;
+  const bool plain = (a.kp.flags & S3R_PLAIN) != 0;
+  const bool temporal = (a.kp.flags & S3R_TEMPORAL) != 0;
+
+  // temporal selection first: a Gaussian whose interval excludes every view's
+  // time is never read further (Sec. 3.3, select before projecting)
+  uint64_t pass_bits = 0;
+  if (valid) {
+    if (temporal) {
+      const float vs = a.vis_s[i];
+      const float ve = a.vis_e[i];
+      for (int v = 0; v < a.nv; ++v) {
+        const float t = a.t_norm[v];
+        if ((vs <= t) && (t <= ve)) pass_bits |= 1ull << v;
+      }
+    } else {
+      pass_bits = (a.nv >= 64) ? ~0ull : ((1ull << a.nv) - 1ull);
+    }
+  }
+  Loaded g;
+  g.mx = g.my = g.mz = 0.f;
+  g.s0 = g.s1 = g.s2 = 0.f;
+  g.k = 0;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) g.R[t] = 0.f;
+  if (pass_bits) {
+    g.mx = a.mean[3 * i]; g.my = a.mean[3 * i + 1]; g.mz = a.mean[3 * i + 2];
+    g.s0 = a.scale[3 * i]; g.s1 = a.scale[3 * i + 1]; g.s2 = a.scale[3 * i + 2];
+    g.k = clampi(a.inst[i], 0, a.n_slots - 1);
+    if (!plain) {
+      const float4 q = reinterpret_cast<const float4*>(a.quat)[i];
+      quat_rot(q.x, q.y, q.z, q.w, g.R);
+    }
+  }
+
+  // ---- phase A: decisions for every view ----
+  for (int v = 0; v < a.nv; ++v) {
+    const bool pass_t = (pass_bits >> v) & 1ull;
+    bool vis = false, surv = false;
+    if (pass_t) {
+      Loaded e;
+      float P[12], fx, fy, cx, cy;
+      int W, H;
+      view_geometry(a, v, g, plain, i, e, P, fx, fy, cx, cy, W, H);
+      Proj o;
+      project_canonical(P, e.mx, e.my, e.mz, e.R, e.s0, e.s1, e.s2, fx, fy, cx, cy, W, H, a.kp, o);
+      vis = o.visible;
+      surv = vis && o.keep;
+    }
+    const uint64_t bt = ballot(pass_t);
+    const uint64_t bf = ballot(vis);
+    const uint64_t bs = ballot(surv);
+    if (lane == 0) {
+      const int gw = vb * kProjWaves + wave;
+      if ((int64_t)gw * kWave < a.n) {
+        uint32_t* m = a.mask + (size_t)v * a.mask_words + 2 * (size_t)gw;
+        m[0] = (uint32_t)bf;
+        m[1] = (uint32_t)(bf >> 32);
+      }
+      s_ball[v][wave] = bs;
+      s_ct[v][wave] = __popcll(bt);
+      s_cf[v][wave] = __popcll(bf);
+    }
+  }
+  __syncthreads();
+
+  // ---- block aggregate, per-(view, wave) offsets, look-back ----
+  if (wave == 0) {
+    uint32_t agg_l = 0;
+    if (lane == 0) {
+      for (int v = 0; v < a.nv; ++v) {
+        int nt = 0, nf = 0, nr = 0;
+        for (int w = 0; w < kProjWaves; ++w) {
+          s_off[v][w] = agg_l;
+          const int c = __popcll(s_ball[v][w]);
+          agg_l += c;
+          nr += c;
+          nt += s_ct[v][w];
+          nf += s_cf[v][w];
+        }
+        int32_t* bs = a.bstat + ((size_t)vb * a.nv + v) * 4;
+        bs[0] = nt; bs[1] = nf; bs[2] = nr; bs[3] = 0;
+      }
+      st_release(a.flags + vb, ((uint64_t)(vb == 0 ? 2u : 1u) << 32) | agg_l);
+    }
+    const uint32_t agg = __shfl(agg_l, 0, kWave);
+    uint32_t excl = 0;
+    if (vb > 0) excl = lookback(a.flags, vb, a.counters + S3R_CNT_SPIN);
+    if (lane == 0) {
+      if (vb > 0) st_release(a.flags + vb, (2ull << 32) | (uint64_t)(excl + agg));
+      s_excl = excl;
+      if (vb == a.nblk - 1) {
+        const int64_t total = (int64_t)excl + agg;
+        a.counters[S3R_CNT_SURV] = (int32_t)(total < a.kp.cap_surv ? total : a.kp.cap_surv);
+        a.counters[S3R_CNT_OVF_SURV] =
+            (int32_t)(total > a.kp.cap_surv ? total - a.kp.cap_surv : 0);
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t excl = s_excl;
+
+  // ---- phase C: records of the survivors ----
+  const int B = (a.sh_deg + 1) * (a.sh_deg + 1);
+  for (int v = 0; v < a.nv; ++v) {
+    const uint64_t bs = s_ball[v][wave];
+    if (!((bs >> lane) & 1ull)) continue;
+    const int64_t slot = (int64_t)excl + s_off[v][wave] + lane_rank(bs);
+    if (slot >= a.kp.cap_surv) continue;
+    Loaded e;
+    float P[12], fx, fy, cx, cy;
+    int W, H;
+    view_geometry(a, v, g, plain, i, e, P, fx, fy, cx, cy, W, H);
+    Proj o;
+    project_canonical(P, e.mx, e.my, e.mz, e.R, e.s0, e.s1, e.s2, fx, fy, cx, cy, W, H, a.kp, o);
+
+    // viewing direction in the instance-local frame
+    float dx, dy, dz;
+    if (plain) {
+      const float4 cw = reinterpret_cast<const float4*>(a.cen)[(size_t)v * a.n_slots];
+      const float wx = e.mx - cw.x, wy = e.my - cw.y, wz = e.mz - cw.z;
+      const float* G = a.pose + ((size_t)clampi(a.tstep[v], 0, a.n_ts - 1) * a.n_slots + g.k) * 12;
+      dx = (G[0] * wx + G[4] * wy) + G[8] * wz;
+      dy = (G[1] * wx + G[5] * wy) + G[9] * wz;
+      dz = (G[2] * wx + G[6] * wy) + G[10] * wz;
+    } else {
+      const float4 ce = reinterpret_cast<const float4*>(a.cen)[(size_t)v * a.n_slots + g.k];
+      dx = g.mx - ce.x; dy = g.my - ce.y; dz = g.mz - ce.z;
+    }
+    const float nrm = sqrtf((dx * dx + dy * dy) + dz * dz);
+    dx = dx / nrm; dy = dy / nrm; dz = dz / nrm;
+    float Y[16];
+    sh_basis(a.sh_deg, dx, dy, dz, Y);
+    const float* f = a.sh + (size_t)i * B * 3;
+    float r = 0.f, gg = 0.f, bb = 0.f;
+    for (int q = 0; q < B; ++q) {
+      r = fmaf(Y[q], f[3 * q], r);
+      gg = fmaf(Y[q], f[3 * q + 1], gg);
+      bb = fmaf(Y[q], f[3 * q + 2], bb);
+    }
+    r = fmaxf(r + 0.5f, 0.f);
+    gg = fmaxf(gg + 0.5f, 0.f);
+    bb = fmaxf(bb + 0.5f, 0.f);
+
+    a.rec_gid[slot] = i;
+    a.rec_view[slot] = v;
+    a.rec_geo[slot] = make_float4(o.u, o.v, a.opac[i], o.pz);
+    a.rec_conic[slot] = make_float4(o.c / o.det, (-o.b) / o.det, o.a / o.det, 0.f);
+    a.rec_rgb[slot] = make_float4(r, gg, bb, 0.f);
+    a.rec_rect[slot] = make_int4(o.x0, o.y0, o.x1, o.y1);
+    const int gxv = (W + a.kp.tile - 1) / a.kp.tile;
+    int32_t* tc = a.tile_count + a.tile_offset[v];
+    for (int ty = o.y0; ty < o.y1; ++ty)
+      for (int tx = o.x0; tx < o.x1; ++tx) atomicAdd(tc + ty * gxv + tx, 1);
+  }
+}
+
+// per-view totals of the per-block statistics
+__global__ __launch_bounds__(256) void k_stats(const int32_t* __restrict__ bstat, int nblk, int nv,
+                                               int32_t* __restrict__ stats) {
+  const int v = blockIdx.x;
+  __shared__ int s[3][4];
+  int acc[3] = {0, 0, 0};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    const int32_t* p = bstat + ((size_t)b * nv + v) * 4;
+    acc[0] += p[0]; acc[1] += p[1]; acc[2] += p[2];
+  }
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  for (int q = 0; q < 3; ++q) {
+    uint32_t t = wave_sum_u32((uint32_t)acc[q]);
+    if (lane == 0) s[q][wave] = (int)t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    int t = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += s[threadIdx.x][w];
+    stats[v * 4 + threadIdx.x] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_compose(const float* W, const int32_t* tstep, const float* pose, int S, int T,
+                          int nv, float* cam, float* cen, float* t_norm, hipStream_t st) {
+  hipLaunchKernelGGL(k_compose, dim3(nv), dim3(128), 0, st, W, tstep, pose, S, T, nv, cam, cen,
+                     t_norm);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_transform(const float* mean, const float* quat, const int32_t* inst,
+                                  const float* pose, int n, int S, const int32_t* tsteps, int n_ts,
+                                  float* mean_w, float* rot_w, hipStream_t st) {
+  TsList ts;
+  for (int s = 0; s < kMaxViews; ++s) ts.tau[s] = s < n_ts ? tsteps[s] : 0;
+  const int grid = (n + 255) / 256;
+  if (grid > 0)
+    hipLaunchKernelGGL(k_plain_transform, dim3(grid), dim3(256), 0, st, mean, quat, inst, pose, n,
+                       S, ts, n_ts, mean_w, rot_w);
+  return hipGetLastError();
+}
+
+int project_blocks(int64_t n) { return (int)((n + kProjBlock - 1) / kProjBlock); }
+
+hipError_t launch_project(const ProjArgs& a, int32_t* stats, hipStream_t st) {
+  if (a.nblk > 0) hipLaunchKernelGGL(k_project, dim3(a.nblk), dim3(kProjBlock), 0, st, a);
+  hipLaunchKernelGGL(k_stats, dim3(a.nv), dim3(256), 0, st, a.bstat, a.nblk, a.nv, stats);
+  return hipGetLastError();
+}
+
+}  // namespace s3r

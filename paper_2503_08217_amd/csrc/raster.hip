@@ -1,0 +1,151 @@
+// Front-to-back alpha blending of Eq. (2) over every tile of every view in
+// one launch.
+//
+// One workgroup per tile, one thread per pixel (a 16x16 tile is four wave64s).
+// The tile's sorted list is consumed in batches: each thread stages one record
+// (mean, conic, opacity, colour: 40 bytes) in LDS, then every thread blends the
+// whole batch into its pixel.  A batch loop ends as soon as every pixel of the
+// tile has reached the transmittance floor.  The pixel is sampled at integer
+// coordinates (x, y).
+#include "internal.hpp"
+
+namespace s3r {
+
+template <int TS>
+__global__ __launch_bounds__(TS* TS) void k_raster_fwd(RasterArgs a) {
+  constexpr int NT = TS * TS;
+  __shared__ float2 s_uv[NT];
+  __shared__ float4 s_con[NT];  // A, B, C, opacity
+  __shared__ float4 s_rgb[NT];
+  const int tid = threadIdx.x;
+  const int t = blockIdx.x;
+  const int v = find_view(a.tile_offset, a.nv, t);
+  const int lt = t - a.tile_offset[v];
+  const int W = a.wh[2 * v], H = a.wh[2 * v + 1];
+  const int gx = (W + TS - 1) / TS;
+  const int px = (lt % gx) * TS + tid % TS;
+  const int py = (lt / gx) * TS + tid / TS;
+  const bool inside = (px < W) && (py < H);
+  const float fxp = (float)px, fyp = (float)py;
+  const int64_t s = a.tile_start[t];
+  const int64_t e = min((int64_t)a.tile_start[t + 1], a.kp.cap_dup);
+
+  float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f;
+  bool done = !inside;
+  int last = 0;
+  for (int64_t b0 = s; b0 < e; b0 += NT) {
+    if (__syncthreads_count(done) == NT) break;
+    const int64_t idx = b0 + tid;
+    if (idx < e) {
+      const uint32_t r = a.vals[idx];
+      const float4 g = a.rec_geo[r];
+      const float4 c = a.rec_conic[r];
+      s_uv[tid] = make_float2(g.x, g.y);
+      s_con[tid] = make_float4(c.x, c.y, c.z, g.z);
+      s_rgb[tid] = a.rec_rgb[r];
+    }
+    __syncthreads();
+    const int nb = (int)min((int64_t)NT, e - b0);
+    if (!done) {
+      for (int j = 0; j < nb; ++j) {
+        const float2 uv = s_uv[j];
+        const float4 con = s_con[j];
+        const float dx = uv.x - fxp;
+        const float dy = uv.y - fyp;
+        const float power = fmaf(-0.5f, fmaf(con.x * dx, dx, con.z * dy * dy), -con.y * dx * dy);
+        if (-power > a.kp.cutoff) continue;
+        const float alpha = fminf(a.kp.alpha_max, con.w * __expf(power));
+        if (alpha < a.kp.alpha_min) continue;
+        const float Tn = T * (1.0f - alpha);
+        if (Tn < a.kp.t_min) {
+          done = true;
+          break;
+        }
+        const float4 col = s_rgb[j];
+        const float w = alpha * T;
+        cr = fmaf(col.x, w, cr);
+        cg = fmaf(col.y, w, cg);
+        cb = fmaf(col.z, w, cb);
+        T = Tn;
+        last = (int)(b0 - s) + j + 1;
+      }
+    }
+  }
+  if (inside) {
+    const int64_t npx = (int64_t)W * H;
+    const int64_t p = (int64_t)py * W + px;
+    const int64_t base = 3 * a.px_offset[v];
+    a.color[base + p] = fmaf(T, a.kp.bg0, cr);
+    a.color[base + npx + p] = fmaf(T, a.kp.bg1, cg);
+    a.color[base + 2 * npx + p] = fmaf(T, a.kp.bg2, cb);
+    a.T_final[a.px_offset[v] + p] = T;
+    a.last[a.px_offset[v] + p] = last;
+  }
+}
+
+hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st) {
+  if (a.total_tiles <= 0) return hipSuccess;
+  switch (a.kp.tile) {
+    case 8:
+      hipLaunchKernelGGL(k_raster_fwd<8>, dim3(a.total_tiles), dim3(64), 0, st, a);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_raster_fwd<16>, dim3(a.total_tiles), dim3(256), 0, st, a);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_raster_fwd<32>, dim3(a.total_tiles), dim3(1024), 0, st, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// per-view mean absolute error and its gradient
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_l1(const float* __restrict__ color,
+                                            const float* __restrict__ target,
+                                            const int64_t* __restrict__ pxo,
+                                            const int32_t* __restrict__ wh, int nv, int64_t total,
+                                            float* __restrict__ loss, float* __restrict__ dcol) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int v = 0;
+  float acc = 0.f;
+  if (i < total) {
+    while (v + 1 < nv && pxo[v + 1] <= i) ++v;
+    const int64_t npx = (int64_t)wh[2 * v] * wh[2 * v + 1];
+    const int64_t loc = i - pxo[v];
+    const float inv = 1.0f / (3.0f * (float)npx);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t q = 3 * pxo[v] + c * npx + loc;
+      const float d = color[q] - target[q];
+      acc += fabsf(d);
+      dcol[q] = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+    }
+    acc *= inv;
+  }
+  const int v0 = __shfl(v, 0, kWave);
+  const bool uniform = ballot(v != v0 && i < total) == 0ull;
+  if (uniform) {
+    const float w = wave_sum(acc);
+    if (lane_id() == 0 && w != 0.f) atomicAdd(loss + v0, w);
+  } else if (i < total) {
+    atomicAdd(loss + v, acc);
+  }
+}
+
+hipError_t launch_l1_loss(const float* color, const float* target, const int64_t* px_offset,
+                          const int32_t* wh, int nv, int64_t total_px, float* loss,
+                          float* d_color, hipStream_t st) {
+  hipError_t e = launch_zero(loss, (size_t)nv * 4, nullptr, 0, nullptr, 0, nullptr, 0, st);
+  if (e != hipSuccess) return e;
+  const int64_t grid = (total_px + 255) / 256;
+  if (grid > 0)
+    hipLaunchKernelGGL(k_l1, dim3((unsigned)grid), dim3(256), 0, st, color, target, px_offset, wh,
+                       nv, total_px, loss, d_color);
+  return hipGetLastError();
+}
+
+}  // namespace s3r

@@ -1,0 +1,346 @@
+"""Device buffers and calls of the per-view rendering step (PyTorch for memory
+and streams only; every step runs in libs3r.so).
+
+`Renderer` owns the device copies of a scene and of a batch of views plus all
+capacity-sized buffers, and exposes the C entry points one by one
+(`project_cull`, `sort`, `raster_fwd`, `l1_loss`, `raster_bwd`,
+`update_visibility`, `plain_transform`, `plain_transform_bwd`) and composed
+(`forward`, `step`).  `RenderFn` wraps forward/backward as a
+torch.autograd.Function.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def tile_layout(wh, tile):
+    """Exclusive prefixes of tiles and pixels per view (host bookkeeping)."""
+    wh = np.asarray(wh, np.int64).reshape(-1, 2)
+    g = ((wh[:, 0] + tile - 1) // tile) * ((wh[:, 1] + tile - 1) // tile)
+    toff = np.concatenate([[0], np.cumsum(g)]).astype(np.int32)
+    poff = np.concatenate([[0], np.cumsum(wh[:, 0] * wh[:, 1])]).astype(np.int64)
+    return toff, poff
+
+
+class Renderer:
+    def __init__(self, scene, views, params, *, device="cuda", plain=False, cap_surv=None,
+                 cap_dup=None, requires_grad=False):
+        A.load()
+        self.dev = torch.device(device)
+        self.params = dict(params)
+        self.plain = bool(plain)
+        self.V = int(views.n_views)
+        self.n = int(scene.mean.shape[0])
+        self.T = int(scene.pose.shape[0])
+        self.S = int(scene.pose.shape[1])
+        self.sh_degree = int(scene.sh_degree)
+        self.B = (self.sh_degree + 1) ** 2
+        d = self.dev
+        f32 = torch.float32
+
+        def up(x, dt=f32):
+            return torch.as_tensor(np.ascontiguousarray(x)).to(device=d, dtype=dt).contiguous()
+
+        self.mean = up(scene.mean)
+        self.scale = up(scene.scale)
+        self.quat = up(scene.quat)
+        self.opacity = up(scene.opacity)
+        self.sh = up(scene.sh).reshape(self.n, self.B, 3)
+        self.inst = up(scene.inst, torch.int32)
+        self.vis_s = up(scene.vis_s)
+        self.vis_e = up(scene.vis_e)
+        self.life_s = up(scene.life_s)
+        self.life_e = up(scene.life_e)
+        self.pose = up(np.asarray(scene.pose).reshape(self.T, self.S, 12))
+        self.set_views(views)
+        self.cap_surv = int(cap_surv) if cap_surv else max(1, self.n * self.V)
+        self.cap_dup = int(cap_dup) if cap_dup else max(1024, 4 * self.cap_surv)
+        self._alloc()
+
+    # ------------------------------------------------------------------ views
+    def _upload_views(self, views):
+        d = self.dev
+        tile = int(self.params["tile"])
+        vs = {}
+        vs["wh_np"] = np.asarray(views.wh, np.int32).reshape(-1, 2)
+        vs["tstep_np"] = np.asarray(views.tstep, np.int32)
+        toff, poff = tile_layout(vs["wh_np"], tile)
+        vs["toff_np"], vs["poff_np"] = toff, poff
+        vs["total_tiles"] = int(toff[-1])
+        vs["total_px"] = int(poff[-1])
+        vs["W"] = torch.as_tensor(np.asarray(views.W, np.float32).reshape(-1, 12)).to(d).contiguous()
+        vs["K"] = torch.as_tensor(np.asarray(views.K, np.float32).reshape(-1, 4)).to(d).contiguous()
+        vs["wh"] = torch.as_tensor(vs["wh_np"]).to(d).contiguous()
+        vs["tstep"] = torch.as_tensor(vs["tstep_np"]).to(d).contiguous()
+        vs["tile_offset"] = torch.as_tensor(toff).to(d).contiguous()
+        vs["px_offset"] = torch.as_tensor(poff).to(d).contiguous()
+        ts = sorted(set(int(t) for t in vs["tstep_np"]))
+        vs["plain_ts"] = np.asarray(ts, np.int32)
+        slot = np.asarray([ts.index(int(t)) for t in vs["tstep_np"]], np.int32)
+        vs["plain_slot"] = torch.as_tensor(slot).to(d).contiguous()
+        vs["c_views"] = A.S3RViews(
+            _ptr(vs["W"]), _ptr(vs["K"]), _ptr(vs["wh"]), _ptr(vs["tstep"]), _ptr(vs["tile_offset"]),
+            _ptr(vs["px_offset"]), _ptr(vs["plain_slot"]), int(len(vs["wh_np"])), vs["total_tiles"],
+            vs["total_px"])
+        vs["c_ts"] = (C.c_int32 * len(ts))(*ts)
+        return vs
+
+    def _use(self, vs):
+        self._vs = vs
+        for k in ("wh_np", "tstep_np", "toff_np", "poff_np", "total_tiles", "total_px", "W", "K",
+                  "wh", "tstep", "tile_offset", "px_offset", "plain_ts", "plain_slot", "c_views",
+                  "c_ts"):
+            setattr(self, k, vs[k])
+
+    def set_views(self, views):
+        self._use(self._upload_views(views))
+
+    def prepare_views(self, view_sets):
+        """Upload several batches of views (each no larger than the first one
+        the buffers were sized for); returns handles for `use_views`."""
+        out = []
+        for views in view_sets:
+            vs = self._upload_views(views)
+            if (vs["total_tiles"] > self.total_tiles or vs["total_px"] > self.total_px
+                    or len(vs["wh_np"]) != self.V or len(vs["plain_ts"]) > len(self.plain_ts)):
+                raise ValueError("view set larger than the allocated buffers")
+            out.append(vs)
+        return out
+
+    def use_views(self, handle):
+        self._use(handle)
+
+    # ---------------------------------------------------------------- buffers
+    def _alloc(self):
+        d, f32, i32 = self.dev, torch.float32, torch.int32
+        V, S, n = self.V, self.S, self.n
+        cs, cd = self.cap_surv, self.cap_dup
+        self.mask_words = ((n + 63) // 64) * 2
+        self.cam = torch.zeros(V, S, 12, device=d, dtype=f32)
+        self.cen = torch.zeros(V, S, 4, device=d, dtype=f32)
+        self.t_norm = torch.zeros(V, device=d, dtype=f32)
+        self.mask = torch.zeros(V, self.mask_words, device=d, dtype=i32)
+        self.rec_gid = torch.zeros(cs, device=d, dtype=i32)
+        self.rec_view = torch.zeros(cs, device=d, dtype=i32)
+        self.rec_geo = torch.zeros(cs, 4, device=d, dtype=f32)
+        self.rec_conic = torch.zeros(cs, 4, device=d, dtype=f32)
+        self.rec_rgb = torch.zeros(cs, 4, device=d, dtype=f32)
+        self.rec_rect = torch.zeros(cs, 4, device=d, dtype=i32)
+        self.counters = torch.zeros(16, device=d, dtype=i32)
+        self.stats = torch.zeros(V, 4, device=d, dtype=i32)
+        self.tile_count = torch.zeros(self.total_tiles, device=d, dtype=i32)
+        self.tile_start = torch.zeros(self.total_tiles + 1, device=d, dtype=i32)
+        self.vals = torch.zeros(cd, device=d, dtype=i32)
+        self.color = torch.zeros(3 * self.total_px, device=d, dtype=f32)
+        self.T_final = torch.zeros(self.total_px, device=d, dtype=f32)
+        self.last = torch.zeros(self.total_px, device=d, dtype=i32)
+        self.d_color = torch.zeros(3 * self.total_px, device=d, dtype=f32)
+        self.loss_v = torch.zeros(max(V, 4), device=d, dtype=f32)
+        n_ts = len(self.plain_ts)
+        if self.plain:
+            self.mean_w = torch.zeros(n_ts, n, 3, device=d, dtype=f32)
+            self.rot_w = torch.zeros(n_ts, n, 9, device=d, dtype=f32)
+        else:
+            self.mean_w = self.rot_w = None
+        # gradients
+        self.g_mean = torch.zeros(n, 3, device=d, dtype=f32)
+        self.g_scale = torch.zeros(n, 3, device=d, dtype=f32)
+        self.g_quat = torch.zeros(n, 4, device=d, dtype=f32)
+        self.g_opacity = torch.zeros(n, device=d, dtype=f32)
+        self.g_sh = torch.zeros(n, self.B, 3, device=d, dtype=f32)
+        self.g_pose = torch.zeros(self.T, S, 12, device=d, dtype=f32)
+        self.g_pose6 = torch.zeros(self.T, S, 6, device=d, dtype=f32)
+        if self.plain:
+            self.g_mean_w = torch.zeros(n_ts, n, 3, device=d, dtype=f32)
+            self.g_rot_w = torch.zeros(n_ts, n, 9, device=d, dtype=f32)
+        else:
+            self.g_mean_w = self.g_rot_w = None
+        # workspaces
+        lib = A.load()
+        z = A.S3RSizes(n, V, self.total_tiles, cs, cd, S, 0)
+        self.ws = {}
+        for which in (A.S3R_WS_PROJECT, A.S3R_WS_SORT, A.S3R_WS_BACKWARD):
+            nb = C.c_size_t(0)
+            A.check(lib.s3r_workspace_size(C.byref(z), which, C.byref(nb)), "s3r_workspace_size")
+            self.ws[which] = (torch.zeros(max(256, nb.value), device=d, dtype=torch.uint8),
+                              nb.value)
+        self._build_structs()
+
+    def _build_structs(self):
+        self.c_params = self.make_params()
+        self.c_scene = A.S3RScene(
+            _ptr(self.mean), _ptr(self.scale), _ptr(self.quat), _ptr(self.opacity), _ptr(self.sh),
+            _ptr(self.inst), _ptr(self.vis_s), _ptr(self.vis_e), _ptr(self.pose), _ptr(self.mean_w),
+            _ptr(self.rot_w), self.n, self.sh_degree, self.S, self.T, 0)
+        self.c_proj = A.S3RProjected(
+            _ptr(self.cam), _ptr(self.cen), _ptr(self.t_norm), _ptr(self.mask), _ptr(self.rec_gid),
+            _ptr(self.rec_view), _ptr(self.rec_geo), _ptr(self.rec_conic), _ptr(self.rec_rgb),
+            _ptr(self.rec_rect), _ptr(self.counters), _ptr(self.stats), _ptr(self.tile_count))
+        self.c_bins = A.S3RBins(_ptr(self.tile_start), _ptr(self.vals))
+        self.c_img = A.S3RImage(_ptr(self.color), _ptr(self.T_final), _ptr(self.last))
+        self.c_grads = A.S3RGrads(
+            _ptr(self.g_mean), _ptr(self.g_scale), _ptr(self.g_quat), _ptr(self.g_opacity),
+            _ptr(self.g_sh), _ptr(self.g_pose), _ptr(self.g_pose6), _ptr(self.g_mean_w),
+            _ptr(self.g_rot_w))
+
+    def make_params(self):
+        p = self.params
+        flags = 0
+        if p.get("temporal", False):
+            flags |= A.S3R_TEMPORAL
+        if p.get("lod", False):
+            flags |= A.S3R_LOD
+        if self.plain:
+            flags |= A.S3R_PLAIN
+        bg = (C.c_float * 3)(*[float(x) for x in p["bg"]])
+        return A.S3RParams(int(p["tile"]), flags, float(p["lod_r"]), float(p["z_near"]),
+                           float(p["z_far"]), float(p["eps2d"]), float(p["alpha_min"]),
+                           float(p["alpha_max"]), float(p["t_min"]), float(p["cutoff"]),
+                           float(p["jac_clamp"]), bg, self.cap_surv, self.cap_dup)
+
+    def set_flags(self, **over):
+        self.params.update(over)
+        self.c_params = self.make_params()
+
+    # ------------------------------------------------------------ entry points
+    def plain_transform(self):
+        A.check(A.load().s3r_plain_transform(C.byref(self.c_scene), self.c_ts, len(self.plain_ts),
+                                             _ptr(self.mean_w), _ptr(self.rot_w), _stream()),
+                "s3r_plain_transform")
+
+    def project_cull(self):
+        ws, nb = self.ws[A.S3R_WS_PROJECT]
+        A.check(A.load().s3r_project_cull(C.byref(self.c_scene), C.byref(self.c_views),
+                                          C.byref(self.c_params), C.byref(self.c_proj), _ptr(ws),
+                                          nb, _stream()), "s3r_project_cull")
+
+    def sort(self):
+        ws, nb = self.ws[A.S3R_WS_SORT]
+        A.check(A.load().s3r_sort(C.byref(self.c_proj), C.byref(self.c_views),
+                                  C.byref(self.c_params), C.byref(self.c_bins), _ptr(ws), nb,
+                                  _stream()), "s3r_sort")
+
+    def raster_fwd(self):
+        A.check(A.load().s3r_raster_fwd(C.byref(self.c_proj), C.byref(self.c_bins),
+                                        C.byref(self.c_views), C.byref(self.c_params),
+                                        C.byref(self.c_img), _stream()), "s3r_raster_fwd")
+
+    def l1_loss(self, target):
+        A.check(A.load().s3r_l1_loss(C.byref(self.c_img), _ptr(target), C.byref(self.c_views),
+                                     _ptr(self.loss_v), _ptr(self.d_color), _stream()),
+                "s3r_l1_loss")
+
+    def zero_grads(self):
+        for t in (self.g_mean, self.g_scale, self.g_quat, self.g_opacity, self.g_sh, self.g_pose,
+                  self.g_pose6, self.g_mean_w, self.g_rot_w):
+            if t is not None:
+                t.zero_()
+
+    def raster_bwd(self, d_color=None):
+        dc = self.d_color if d_color is None else d_color
+        ws, nb = self.ws[A.S3R_WS_BACKWARD]
+        A.check(A.load().s3r_raster_bwd(C.byref(self.c_scene), C.byref(self.c_views),
+                                        C.byref(self.c_params), C.byref(self.c_proj),
+                                        C.byref(self.c_bins), C.byref(self.c_img), _ptr(dc),
+                                        C.byref(self.c_grads), _ptr(ws), nb, _stream()),
+                "s3r_raster_bwd")
+        if self.plain:
+            A.check(A.load().s3r_plain_transform_bwd(C.byref(self.c_scene), self.c_ts,
+                                                     len(self.plain_ts), C.byref(self.c_grads),
+                                                     _stream()), "s3r_plain_transform_bwd")
+
+    def update_visibility(self, mode, margin=None):
+        m = float(self.params.get("margin", 0.1) if margin is None else margin)
+        A.check(A.load().s3r_update_visibility(
+            _ptr(self.life_s), _ptr(self.life_e), _ptr(self.vis_s), _ptr(self.vis_e),
+            _ptr(self.mask), _ptr(self.t_norm), self.V, self.n, int(mode), m, _stream()),
+            "s3r_update_visibility")
+
+    # --------------------------------------------------------------- composed
+    def forward(self):
+        if self.plain:
+            self.plain_transform()
+        self.project_cull()
+        self.sort()
+        self.raster_fwd()
+
+    def step(self, target, update_visibility=True):
+        """One training step of the batch: forward, L1 loss, backward and
+        point-life update (Eq. 5)."""
+        self.forward()
+        self.l1_loss(target)
+        self.zero_grads()
+        self.raster_bwd()
+        if update_visibility and not self.plain:
+            self.update_visibility(A.S3R_VIS_UPDATE)
+
+    # ---------------------------------------------------------------- helpers
+    def read_counters(self):
+        torch.cuda.synchronize()
+        c = self.counters.cpu().numpy()
+        return dict(n_surv=int(c[A.CNT_SURV]), ovf_surv=int(c[A.CNT_OVF_SURV]),
+                    n_dup=int(c[A.CNT_DUP]), ovf_dup=int(c[A.CNT_OVF_DUP]),
+                    spin=int(c[A.CNT_SPIN]))
+
+    def fit_capacity(self, margin=1.25):
+        """Run the forward once and grow the capacities until nothing overflows."""
+        for _ in range(8):
+            self.forward()
+            c = self.read_counters()
+            if c["spin"]:
+                raise A.S3RError("a bounded device wait gave up")
+            need_s = c["n_surv"] + c["ovf_surv"]
+            need_d = c["n_dup"] + c["ovf_dup"]
+            if c["ovf_surv"] == 0 and c["ovf_dup"] == 0:
+                return c
+            self.cap_surv = max(self.cap_surv, int(math.ceil(need_s * margin)) + 1024)
+            self.cap_dup = max(self.cap_dup, int(math.ceil(need_d * margin)) + 4096)
+            self._alloc()
+        raise A.S3RError("capacities did not converge")
+
+    def image(self, v):
+        """(3, h, w) view of the colour buffer for view v."""
+        w, h = int(self.wh_np[v, 0]), int(self.wh_np[v, 1])
+        o = int(self.poff_np[v])
+        return self.color[3 * o: 3 * o + 3 * w * h].view(3, h, w)
+
+    def view_slice(self, buf, v, channels=1):
+        w, h = int(self.wh_np[v, 0]), int(self.wh_np[v, 1])
+        o = int(self.poff_np[v])
+        return buf[channels * o: channels * (o + w * h)].view(*(() if channels == 1 else (channels,)), h, w)
+
+
+class RenderFn(torch.autograd.Function):
+    """Image of every view of `renderer` as a function of the scene parameters.
+
+    The renderer's own tensors are the parameters (they are passed in so that
+    autograd tracks them); backward returns the library's gradients."""
+
+    @staticmethod
+    def forward(ctx, renderer, mean, scale, quat, opacity, sh, pose):
+        renderer.forward()
+        ctx.renderer = renderer
+        return renderer.color.clone()
+
+    @staticmethod
+    def backward(ctx, d_color):
+        r = ctx.renderer
+        r.zero_grads()
+        r.raster_bwd(d_color.contiguous())
+        return (None, r.g_mean.clone(), r.g_scale.clone(), r.g_quat.clone(),
+                r.g_opacity.clone(), r.g_sh.clone(), r.g_pose.view(r.T, r.S, 12).clone())

@@ -22,7 +22,8 @@ Attribute conventions consumed by the renderer:
   inst    (N,)  i32  0 = static, k in 1..K = instance k
   vis_s, vis_e (N,) f32   temporal visibility, initial (-1, 1)
   life_s, life_e (N,) f32 point life, initial (1, -1)
-Static Gaussians come first, then each instance's Gaussians contiguously.
+Static Gaussians come first, sorted along the road (x ascending), then each
+instance's Gaussians contiguously.
 """
 
 from __future__ import annotations
@@ -172,7 +173,10 @@ def _corridor_static(rng, n, length, half_width=20.0, height=10.0, mean_off=8.0)
     ay = -mean_off * np.log1p(-u * a)          # truncated exponential
     y = ay * rng.choice([-1.0, 1.0], size=n)
     z = rng.uniform(0.0, height, size=n)
-    return np.stack([x, y, z], axis=1)
+    xyz = np.stack([x, y, z], axis=1)
+    # stored in corridor order (ascending x): Gaussians seen over the same
+    # stretch of the drive are neighbours in memory
+    return xyz[np.argsort(x, kind="stable")]
 
 
 def _assemble(rng, static_xyz, inst_local, sh_degree, sh_sigma, poses):

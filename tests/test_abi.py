@@ -1,0 +1,118 @@
+"""The C-ABI library loads, exports every entry point of include/s3r.h, and
+rejects bad arguments on the host with the documented status codes (no GPU
+work is issued on these paths)."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2503_08217_amd import _abi as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "s3r.h")
+
+
+def header_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(s3r_\w+)\(", txt, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(A.LIB_PATH):
+        pytest.fail("libs3r.so is not built (run __graft_entry__.build())")
+    return A.load()
+
+
+def test_every_header_symbol_is_exported(lib):
+    syms = header_symbols()
+    assert len(syms) >= 11
+    for s in syms:
+        assert hasattr(lib, s), s
+        assert s in A.SIGNATURES, s
+
+
+def test_version_and_status(lib):
+    assert lib.s3r_abi_version() == 1
+    assert lib.s3r_status_string(0) == b"ok"
+    assert b"aligned" in lib.s3r_status_string(-2)
+
+
+def test_struct_sizes_match_c_layout():
+    assert C.sizeof(A.S3RParams) == 72
+    assert C.sizeof(A.S3RScene) == 11 * 8 + 8 + 16
+    assert C.sizeof(A.S3RViews) == 7 * 8 + 16
+    assert C.sizeof(A.S3RProjected) == 13 * 8
+    assert C.sizeof(A.S3RGrads) == 9 * 8
+    assert C.sizeof(A.S3RSizes) == 40
+
+
+def test_workspace_sizes(lib):
+    z = A.S3RSizes(2_000_000, 1, 8160, 400_000, 2_000_000, 31, 0)
+    got = {}
+    for w in (0, 1, 2):
+        nb = C.c_size_t(0)
+        assert lib.s3r_workspace_size(C.byref(z), w, C.byref(nb)) == 0
+        got[w] = nb.value
+    assert got[1] >= 16 * 2_000_000         # two key buffers
+    assert got[2] >= 48 * 400_000           # per-record 2D gradients
+    nb = C.c_size_t(0)
+    assert lib.s3r_workspace_size(C.byref(z), 7, C.byref(nb)) == -6
+    bad = A.S3RSizes(10, 0, 1, 1, 1, 1, 0)
+    assert lib.s3r_workspace_size(C.byref(bad), 0, C.byref(nb)) == -3
+
+
+def _params(**kw):
+    p = dict(tile=16, flags=0, lod_r=0.0, z_near=0.2, z_far=1e30, eps2d=0.3,
+             alpha_min=1 / 255, alpha_max=0.99, t_min=1e-4, cutoff=4.5, jac_clamp=1.3)
+    p.update(kw)
+    return A.S3RParams(p["tile"], p["flags"], p["lod_r"], p["z_near"], p["z_far"], p["eps2d"],
+                       p["alpha_min"], p["alpha_max"], p["t_min"], p["cutoff"], p["jac_clamp"],
+                       (C.c_float * 3)(0, 0, 0), p.get("cap_surv", 16), p.get("cap_dup", 64))
+
+
+def test_host_validation_codes(lib):
+    buf = (C.c_float * 64)()
+    base = C.addressof(buf)
+    al = base + (16 - base % 16) % 16
+    ptr = C.c_void_p(al)
+    scene = A.S3RScene(*([ptr] * 9), C.c_void_p(0), C.c_void_p(0), 4, 0, 1, 1, 0)
+    views = A.S3RViews(*([ptr] * 6), C.c_void_p(0), 1, 1, 64)
+    proj = A.S3RProjected(*([ptr] * 13))
+    p = _params()
+    ws = C.c_void_p(al)
+    # NULL scene
+    assert lib.s3r_project_cull(None, C.byref(views), C.byref(p), C.byref(proj), ws, 1 << 20,
+                                None) == -1
+    # bad tile size
+    p_bad = _params(tile=12)
+    assert lib.s3r_project_cull(C.byref(scene), C.byref(views), C.byref(p_bad), C.byref(proj),
+                                ws, 1 << 20, None) == -3
+    # misaligned array
+    scene_mis = A.S3RScene(C.c_void_p(al + 4), *([ptr] * 8), C.c_void_p(0), C.c_void_p(0),
+                           4, 0, 1, 1, 0)
+    assert lib.s3r_project_cull(C.byref(scene_mis), C.byref(views), C.byref(p), C.byref(proj),
+                                ws, 1 << 20, None) == -2
+    # SH degree out of range
+    scene_deg = A.S3RScene(*([ptr] * 9), C.c_void_p(0), C.c_void_p(0), 4, 5, 1, 1, 0)
+    assert lib.s3r_project_cull(C.byref(scene_deg), C.byref(views), C.byref(p), C.byref(proj),
+                                ws, 1 << 20, None) == -3
+    # workspace too small
+    assert lib.s3r_project_cull(C.byref(scene), C.byref(views), C.byref(p), C.byref(proj), ws,
+                                8, None) == -4
+    # plain route without world-frame arrays
+    p_plain = _params(flags=A.S3R_PLAIN)
+    assert lib.s3r_project_cull(C.byref(scene), C.byref(views), C.byref(p_plain), C.byref(proj),
+                                ws, 1 << 20, None) == -1
+    # too many views
+    views_many = A.S3RViews(*([ptr] * 6), C.c_void_p(0), 65, 1, 64)
+    assert lib.s3r_project_cull(C.byref(scene), C.byref(views_many), C.byref(p), C.byref(proj),
+                                ws, 1 << 20, None) == -3
+    # visibility: bad mode, NULL mask for UPDATE
+    assert lib.s3r_update_visibility(ptr, ptr, ptr, ptr, ptr, ptr, 1, 10, 9, 0.1, None) == -6
+    assert lib.s3r_update_visibility(ptr, ptr, ptr, ptr, None, ptr, 1, 10, 0, 0.1, None) == -1
+    # plain transform: timestep out of range
+    ts = (C.c_int32 * 1)(5)
+    assert lib.s3r_plain_transform(C.byref(scene), ts, 1, ptr, ptr, None) == -6

@@ -1,0 +1,107 @@
+"""GPU gradients vs the oracle's FP64 autograd (normwise 1e-3 per tensor), and
+the temporal-visibility update vs the oracle (exact)."""
+
+import numpy as np
+import pytest
+
+import scenes
+from oracle import grad as ograd
+from oracle import render, visibility
+
+from gpu_util import banner, make_renderer, mask_bits, needs_gpu
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+torch = pytest.importorskip("torch")
+
+
+def flat_targets(tg):
+    return torch.as_tensor(np.concatenate([t.ravel() for t in tg])).cuda().contiguous()
+
+
+def gpu_grads(r, tg_list):
+    r.forward()
+    r.l1_loss(flat_targets(tg_list))
+    r.zero_grads()
+    r.raster_bwd()
+    torch.cuda.synchronize()
+    g = dict(mean=r.g_mean, scale=r.g_scale, quat=r.g_quat, opacity=r.g_opacity, sh=r.g_sh,
+             pose=r.g_pose.view(r.T, r.S, 3, 4), pose6=r.g_pose6)
+    return float(r.loss_v[:r.V].sum()), {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+
+
+def compare(g, ref, keys, rel=1e-3):
+    for k in keys:
+        a, b = g[k].ravel(), ref[k].ravel()
+        nb = np.linalg.norm(b)
+        err = np.linalg.norm(a - b)
+        assert err <= rel * max(nb, 1e-12), (k, err, nb)
+
+
+def oracle_grads(scene, views, params, tg, plain=False):
+    orders = {}
+    for v in range(views.n_views):
+        o = render.render_view(scene, views, v, params, plain=plain, with_image=False)
+        from oracle import order
+        orders[v] = order.global_order(o["ids"], o["dec"]["depth_bits"])
+    return ograd.loss_and_grads(scene, views, list(range(views.n_views)), orders, params, tg,
+                                route="conventional" if plain else "instance")
+
+
+KEYS = ("mean", "scale", "quat", "opacity", "sh", "pose", "pose6")
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_grads_config1(plain):
+    c = scenes.make_config(1)
+    tg = scenes.targets(1, c.views)
+    banner(f"grads config1 plain={plain}")
+    r = make_renderer(c.scene, c.views, c.params, plain=plain)
+    loss, g = gpu_grads(r, tg)
+    lref, _, ref = oracle_grads(c.scene, c.views, c.params, tg, plain=plain)
+    assert abs(loss - lref) <= 1e-4 * abs(lref)
+    compare(g, ref, KEYS)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_grads_micro(seed):
+    scene, views = scenes.micro_scene(seed, n=60, width=40, height=30, n_inst=2,
+                                      sh_degree=seed % 4)
+    p = scenes.default_params(tile=16)
+    rng = np.random.default_rng(seed)
+    tg = [rng.uniform(0, 1, (3, 30, 40)).astype(np.float32) for _ in range(views.n_views)]
+    banner(f"grads micro seed={seed}")
+    r = make_renderer(scene, views, p)
+    loss, g = gpu_grads(r, tg)
+    lref, _, ref = oracle_grads(scene, views, p, tg)
+    assert abs(loss - lref) <= 1e-4 * abs(lref)
+    compare(g, ref, KEYS)
+
+
+def test_visibility_update_fold_reset():
+    c = scenes.make_config(2, scale_n=0.05)
+    p = dict(c.params, temporal=True)
+    views = c.views.subset([3, 19, 33, 47])
+    banner("visibility lifecycle")
+    r = make_renderer(c.scene, views, p)
+    r.forward()
+    masks = mask_bits(r)
+    from paper_2503_08217_amd import S3R_VIS_FOLD, S3R_VIS_RESET, S3R_VIS_UPDATE
+    r.update_visibility(S3R_VIS_UPDATE)
+    t = r.t_norm.cpu().numpy()
+    ls, le = visibility.update(c.scene.life_s, c.scene.life_e, masks, t)
+    np.testing.assert_array_equal(r.life_s.cpu().numpy(), ls)
+    np.testing.assert_array_equal(r.life_e.cpu().numpy(), le)
+    r.update_visibility(S3R_VIS_UPDATE)      # idempotent
+    np.testing.assert_array_equal(r.life_s.cpu().numpy(), ls)
+    r.update_visibility(S3R_VIS_FOLD)
+    vs, ve = visibility.fold(ls, le)
+    np.testing.assert_array_equal(r.vis_s.cpu().numpy(), vs)
+    np.testing.assert_array_equal(r.vis_e.cpu().numpy(), ve)
+    # after the fold every Gaussian in M at time t passes the temporal test at t
+    r.forward()
+    m2 = mask_bits(r)
+    np.testing.assert_array_equal(m2, masks)
+    r.update_visibility(S3R_VIS_RESET)
+    np.testing.assert_array_equal(r.vis_s.cpu().numpy(), -1.0)
+    np.testing.assert_array_equal(r.life_e.cpu().numpy(), -1.0)

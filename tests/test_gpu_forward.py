@@ -1,0 +1,151 @@
+"""GPU parity of the forward path against the oracle (through the C ABI).
+
+Decisions (M_t, survivor sets, footprint rectangles, depth keys, per-tile
+order) must match bit for bit; projected attributes that feed decisions
+(u, v, depth) too; colours within 1e-5; blended pixels within 1e-4 absolute
+except pixels the FP64 oracle flags as within rounding distance of a
+blending threshold (bounded by 0.03 x the largest colour, counted)."""
+
+import numpy as np
+import pytest
+
+import scenes
+from oracle import decide32, render
+
+from gpu_util import banner, image_np, make_renderer, mask_bits, needs_gpu, records, T_np, \
+    tile_lists_gpu
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def check_view(scene, views, params, r, rec, v, plain=False, region=None, full_lists=True):
+    o = render.render_view(scene, views, v, params, plain=plain, region=region)
+    d = o["dec"]
+    gm = mask_bits(r)[v]
+    np.testing.assert_array_equal(gm, d["visible"], err_msg=f"M_t view {v}")
+    sel = rec["view"] == v
+    gid = rec["gid"][sel]
+    assert np.all(np.diff(gid) > 0), "records of a view must be in Gaussian order"
+    np.testing.assert_array_equal(gid, np.nonzero(d["surv"])[0], err_msg=f"survivors view {v}")
+    geo = rec["geo"][sel]
+    np.testing.assert_array_equal(geo[:, 0].view(np.uint32), d["u"][gid].view(np.uint32))
+    np.testing.assert_array_equal(geo[:, 1].view(np.uint32), d["v"][gid].view(np.uint32))
+    np.testing.assert_array_equal(geo[:, 3].view(np.uint32), d["depth_bits"][gid])
+    np.testing.assert_array_equal(geo[:, 2], scene.opacity[gid])
+    rect = rec["rect"][sel]
+    np.testing.assert_array_equal(rect[:, 0], d["x0"][gid])
+    np.testing.assert_array_equal(rect[:, 1], d["y0"][gid])
+    np.testing.assert_array_equal(rect[:, 2], d["x1"][gid])
+    np.testing.assert_array_equal(rect[:, 3], d["y1"][gid])
+    con = rec["conic"][sel][:, :3]
+    ref = np.stack([d["conic_a"], d["conic_b"], d["conic_c"]], 1)[gid]
+    np.testing.assert_array_equal(con.view(np.uint32), ref.view(np.uint32))
+    np.testing.assert_allclose(rec["rgb"][sel][:, :3], o["rgb"][gid], atol=1e-5, rtol=0)
+    st = rec["stats"][v]
+    assert st[1] == d["visible"].sum() and st[2] == d["surv"].sum()
+    if params.get("temporal"):
+        assert st[0] == d["pass_t"].sum()
+    if full_lists:
+        a = render.tile_lists_of(d, np.nonzero(d["surv"])[0], params)
+        g = tile_lists_gpu(r, rec)[v]
+        np.testing.assert_array_equal(g[0], a[0])
+        np.testing.assert_array_equal(g[1], a[1])
+    img = image_np(r, v)
+    T = T_np(r, v)
+    if region is not None:
+        x0, y0, x1, y1 = region
+        img = img[:, y0:y1, x0:x1]
+        T = T[y0:y1, x0:x1]
+    ok = ~o["flag"]
+    err = np.abs(img - o["image"])
+    assert err[:, ok].max(initial=0) <= 1e-4, (v, err[:, ok].max())
+    cmax = max(1e-6, o["rgb"].max())
+    assert err.max(initial=0) <= 0.03 * cmax
+    assert np.abs(T - o["T"])[ok].max(initial=0) <= 1e-4
+    return o
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_config1_all_views(plain):
+    c = scenes.make_config(1)
+    banner(f"config1 plain={plain}")
+    r = make_renderer(c.scene, c.views, c.params, plain=plain)
+    r.forward()
+    rec = records(r)
+    assert rec["counters"]["spin"] == 0 and rec["counters"]["ovf_surv"] == 0
+    np.testing.assert_array_equal(r.t_norm.cpu().numpy(), np.float32([-1, 0, 1]))
+    for v in range(3):
+        o = check_view(c.scene, c.views, c.params, r, rec, v, plain=plain)
+        cam = r.cam[v].cpu().numpy().reshape(-1, 3, 4)
+        np.testing.assert_array_equal(cam.view(np.uint32), o["dec"]["cam"].view(np.uint32))
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_micro_scenes_ragged(tile):
+    """Odd image sizes (ragged tiles), N not a multiple of a workgroup."""
+    for seed in range(4):
+        scene, views = scenes.micro_scene(seed, n=300 + 37 * seed, width=70, height=50,
+                                          n_inst=2, sh_degree=seed % 4)
+        p = scenes.default_params(tile=tile)
+        banner(f"micro seed={seed} tile={tile}")
+        r = make_renderer(scene, views, p)
+        r.forward()
+        rec = records(r)
+        for v in range(views.n_views):
+            check_view(scene, views, p, r, rec, v)
+
+
+def test_tile_size_invariance():
+    c = scenes.make_config(2, scale_n=0.1)
+    views = c.views.subset([5, 25])
+    imgs = []
+    for tile in (8, 16, 32):
+        p = dict(c.params, tile=tile)
+        banner(f"tile invariance tile={tile}")
+        r = make_renderer(c.scene, views, p)
+        r.forward()
+        imgs.append(r.color.cpu().numpy())
+    np.testing.assert_array_equal(imgs[0], imgs[1])
+    np.testing.assert_array_equal(imgs[0], imgs[2])
+
+
+def test_config2_full_size_sampled():
+    c = scenes.make_config(2)
+    views = c.views.subset([0, 17, 41])
+    banner("config2 full size, 3 views")
+    r = make_renderer(c.scene, views, c.params, cap_surv=c.scene.n * 3)
+    r.forward()
+    rec = records(r)
+    rng = np.random.default_rng(2)
+    for v in range(3):
+        x0 = int(rng.integers(0, 960 - 32))
+        y0 = int(rng.integers(0, 640 - 32))
+        check_view(c.scene, views, c.params, r, rec, v, region=(x0, y0, x0 + 32, y0 + 32))
+
+
+def test_empty_and_fully_culled():
+    scene, views = scenes.micro_scene(0, n=50, width=32, height=32)
+    views.W[:, :, :3] = -views.W[:, :, :3]      # every camera looks backwards
+    p = scenes.default_params(tile=16)
+    banner("fully culled")
+    r = make_renderer(scene, views, p)
+    r.forward()
+    rec = records(r)
+    assert rec["n"] == 0 and rec["counters"]["n_dup"] == 0
+    assert np.all(r.color.cpu().numpy() == 0.0) and np.all(r.T_final.cpu().numpy() == 1.0)
+
+
+def test_batched_uneven_views_equal_single_views():
+    """A batch of views of different sizes and timesteps renders exactly like
+    the views one at a time."""
+    c = scenes.make_config(4, scale_n=0.01)
+    idx = [i for i in range(c.views.n_views) if 20 <= c.views.tstep[i] <= 21]
+    views = c.views.subset(idx)
+    banner(f"batched {len(idx)} views")
+    rb = make_renderer(c.scene, views, c.params)
+    rb.forward()
+    for j in (0, 3, 7, 11):
+        rs = make_renderer(c.scene, views.subset([j]), c.params)
+        rs.forward()
+        np.testing.assert_array_equal(image_np(rb, j), image_np(rs, 0))
+        np.testing.assert_array_equal(mask_bits(rb)[j], mask_bits(rs)[0])

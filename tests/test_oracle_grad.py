@@ -102,3 +102,15 @@ def test_pose6_matches_exponential_map_differences():
                 vals.append(_loss(scene, views, p, orders, tg, f)[0])
             fd = (vals[0] - vals[1]) / (2 * h)
             assert abs(fd - g["pose6"][tau, k, j]) <= 1e-6 * max(1e-3, abs(fd)) + 1e-9
+
+
+def test_routes_agree_on_6dof_pose_gradient():
+    """Instance-frame direction through P = W G vs R_G^T (mu_g - c_W): the same
+    function on rigid poses, so every gradient but the raw pose one agrees,
+    and the 6-DoF pose gradients agree."""
+    scene, views, p, orders, tg = _setup(5, n=15, sh_degree=3)
+    _, _, a = grad.loss_and_grads(scene, views, list(orders), orders, p, tg, route="instance")
+    _, _, b = grad.loss_and_grads(scene, views, list(orders), orders, p, tg, route="conventional")
+    for k in ("mean", "scale", "quat", "opacity", "sh", "pose6"):
+        np.testing.assert_allclose(a[k], b[k], rtol=1e-5, atol=1e-7 * np.abs(b[k]).max())
+    assert np.abs(a["pose"] - b["pose"]).max() > 1e-9     # raw pose gradients differ

@@ -62,6 +62,9 @@ extern "C" {
 
 #define S3R_ABI_VERSION 1
 
+/* Gaussians per block of s3r_project_cull (sizes S3RProjected.blocks) */
+#define S3R_PROJECT_BLOCK 256
+
 enum {
   S3R_OK = 0,
   S3R_E_NULL = -1,      /* a required pointer is NULL                     */
@@ -157,10 +160,13 @@ typedef struct S3RProjected {
   int32_t* counters;  /* [16] see S3R_CNT_*                                   */
   int32_t* stats;     /* [V][4] N_t (temporal pass), N_f (= |M_t|), N_r (records),
                          N_dup (pairs, written by s3r_sort)                     */
-  int32_t* tile_count;/* [total_tiles] number of records covering each tile     */
+  int32_t* blocks;    /* [ceil(N/S3R_PROJECT_BLOCK)][V][4] per Gaussian block and
+                         view: N_t, N_f, N_r and the first record index; read by
+                         s3r_sort to bin records view by view                   */
 } S3RProjected;
 
 typedef struct S3RBins {
+  int32_t* tile_count; /* [total_tiles] number of records covering each tile */
   int32_t* tile_start; /* [total_tiles+1] start of each tile's list          */
   uint32_t* vals;      /* [cap_dup] record index of each list entry, sorted  */
 } S3RBins;
@@ -220,12 +226,13 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
 
 /*
  * s3r_sort -- builds per-tile contributor lists ordered by (depth bits,
- * Gaussian index), the blending order of Eq. (2), bit-exactly: exclusive scan
- * of the tile counts, key emission, per-tile sort.  Reads the records of
- * s3r_project_cull; `ws` holds s3r_workspace_size(S3R_WS_SORT) bytes.
+ * Gaussian index), the blending order of Eq. (2), bit-exactly: per-tile pair
+ * counts, exclusive scan, key emission, per-tile sort.  Reads the records and
+ * block ranges of s3r_project_cull (only scene->n is read from `scene`);
+ * `ws` holds s3r_workspace_size(S3R_WS_SORT) bytes.
  */
-int s3r_sort(const S3RProjected* proj, const S3RViews* views, const S3RParams* params,
-             S3RBins* bins, void* ws, size_t ws_bytes, void* stream);
+int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* views,
+             const S3RParams* params, S3RBins* bins, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * s3r_raster_fwd -- front-to-back alpha blending of Eq. (2) for every pixel of
@@ -279,6 +286,19 @@ int s3r_plain_transform(const S3RScene* scene, const int32_t* tsteps, int32_t n_
  */
 int s3r_plain_transform_bwd(const S3RScene* scene, const int32_t* tsteps, int32_t n_ts,
                             S3RGrads* g, void* stream);
+
+/*
+ * Opt-in per-kernel timing (tracing): when enabled, every kernel the library
+ * enqueues is bracketed by HIP events on its stream.  s3r_profile_read()
+ * waits for the recorded events and returns the accumulated milliseconds and
+ * launch count of kernel `id` (0 <= id < s3r_profile_kernels(), named by
+ * s3r_profile_name()).  Not for use while a stream is being captured.
+ */
+int s3r_profile_enable(int on);
+int s3r_profile_reset(void);
+int s3r_profile_read(int32_t id, double* total_ms, int64_t* count);
+const char* s3r_profile_name(int32_t id);
+int s3r_profile_kernels(void);
 
 int s3r_abi_version(void);
 const char* s3r_status_string(int code);

@@ -20,6 +20,7 @@ S3R_WS_PROJECT, S3R_WS_SORT, S3R_WS_BACKWARD = 0, 1, 2
 CNT_SURV, CNT_OVF_SURV, CNT_DUP, CNT_OVF_DUP, CNT_SPIN = 0, 1, 2, 3, 4
 
 P = C.c_void_p
+PROJECT_BLOCK = 256
 
 
 class S3RParams(C.Structure):
@@ -46,11 +47,11 @@ class S3RViews(C.Structure):
 class S3RProjected(C.Structure):
     _fields_ = [("cam", P), ("cen", P), ("t_norm", P), ("mask", P), ("rec_gid", P),
                 ("rec_view", P), ("rec_geo", P), ("rec_conic", P), ("rec_rgb", P),
-                ("rec_rect", P), ("counters", P), ("stats", P), ("tile_count", P)]
+                ("rec_rect", P), ("counters", P), ("stats", P), ("blocks", P)]
 
 
 class S3RBins(C.Structure):
-    _fields_ = [("tile_start", P), ("vals", P)]
+    _fields_ = [("tile_count", P), ("tile_start", P), ("vals", P)]
 
 
 class S3RImage(C.Structure):
@@ -74,8 +75,8 @@ SIGNATURES = {
     "s3r_workspace_size": ([C.POINTER(S3RSizes), C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
     "s3r_project_cull": ([C.POINTER(S3RScene), C.POINTER(S3RViews), C.POINTER(S3RParams),
                           C.POINTER(S3RProjected), P, C.c_size_t, P], C.c_int),
-    "s3r_sort": ([C.POINTER(S3RProjected), C.POINTER(S3RViews), C.POINTER(S3RParams),
-                  C.POINTER(S3RBins), P, C.c_size_t, P], C.c_int),
+    "s3r_sort": ([C.POINTER(S3RScene), C.POINTER(S3RProjected), C.POINTER(S3RViews),
+                  C.POINTER(S3RParams), C.POINTER(S3RBins), P, C.c_size_t, P], C.c_int),
     "s3r_raster_fwd": ([C.POINTER(S3RProjected), C.POINTER(S3RBins), C.POINTER(S3RViews),
                         C.POINTER(S3RParams), C.POINTER(S3RImage), P], C.c_int),
     "s3r_l1_loss": ([C.POINTER(S3RImage), P, C.POINTER(S3RViews), P, P, P], C.c_int),
@@ -88,7 +89,24 @@ SIGNATURES = {
                             C.c_int),
     "s3r_plain_transform_bwd": ([C.POINTER(S3RScene), C.POINTER(C.c_int32), C.c_int32,
                                  C.POINTER(S3RGrads), P], C.c_int),
+    "s3r_profile_enable": ([C.c_int], C.c_int),
+    "s3r_profile_reset": ([], C.c_int),
+    "s3r_profile_read": ([C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
+    "s3r_profile_name": ([C.c_int32], C.c_char_p),
+    "s3r_profile_kernels": ([], C.c_int),
 }
+
+
+def profile_table():
+    """{kernel name: (total ms, launches)} since the last reset."""
+    lib = load()
+    out = {}
+    for i in range(lib.s3r_profile_kernels()):
+        ms, n = C.c_double(0), C.c_int64(0)
+        check(lib.s3r_profile_read(i, C.byref(ms), C.byref(n)), "s3r_profile_read")
+        if n.value:
+            out[lib.s3r_profile_name(i).decode()] = (ms.value, n.value)
+    return out
 
 _LIB = None
 

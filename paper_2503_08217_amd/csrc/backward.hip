@@ -30,6 +30,7 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(BwdArgs a) {
   __shared__ float4 s_con[NT];
   __shared__ float4 s_rgb[NT];
   __shared__ uint32_t s_rec[NT];
+  __shared__ float s_g[NT][9];
   __shared__ int s_max[NW];
   const int tid = threadIdx.x;
   const int lane = tid % kWave, wave = tid / kWave;
@@ -83,6 +84,8 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(BwdArgs a) {
       s_rgb[tid] = a.rec_rgb[r];
       s_rec[tid] = r;
     }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s_g[tid][q] = 0.f;
     __syncthreads();
     for (int j = (int)(b_end - b0) - 1; j >= 0; --j) {
       const int pos = (int)(b0 - s) + j;
@@ -129,15 +132,29 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(BwdArgs a) {
         }
       }
       if (ballot(contrib) != 0ull) {
-        g_u = wave_sum(g_u); g_v = wave_sum(g_v); g_A = wave_sum(g_A);
-        g_B = wave_sum(g_B); g_C = wave_sum(g_C); g_o = wave_sum(g_o);
-        g_r = wave_sum(g_r); g_g = wave_sum(g_g); g_b = wave_sum(g_b);
-        if (lane == 0) {
-          float* G = reinterpret_cast<float*>(a.g2d + 3 * (size_t)s_rec[j]);
+        g_u = wave_sum_dpp(g_u); g_v = wave_sum_dpp(g_v); g_A = wave_sum_dpp(g_A);
+        g_B = wave_sum_dpp(g_B); g_C = wave_sum_dpp(g_C); g_o = wave_sum_dpp(g_o);
+        g_r = wave_sum_dpp(g_r); g_g = wave_sum_dpp(g_g); g_b = wave_sum_dpp(g_b);
+        if (lane == kWave - 1) {
+          float* G = s_g[j];
           atomicAdd(G + 0, g_u); atomicAdd(G + 1, g_v); atomicAdd(G + 2, g_A);
           atomicAdd(G + 3, g_B); atomicAdd(G + 4, g_C); atomicAdd(G + 5, g_o);
           atomicAdd(G + 6, g_r); atomicAdd(G + 7, g_g); atomicAdd(G + 8, g_b);
         }
+      }
+    }
+    __syncthreads();
+    // one set of global atomics per record and tile
+    if (idx < b_end) {
+      const float* G = s_g[tid];
+      bool any = false;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) any |= (G[q] != 0.f);
+      if (any) {
+        float* D = reinterpret_cast<float*>(a.g2d + 3 * (size_t)s_rec[tid]);
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+          if (G[q] != 0.f) atomicAdd(D + q, G[q]);
       }
     }
   }
@@ -183,8 +200,16 @@ __device__ __forceinline__ void wave_segmented_add(int key, const float val[12],
   }
 }
 
+// Accumulate into a per-Gaussian gradient.  With one view per batch every
+// Gaussian owns at most one record, so a plain read-modify-write suffices.
+__device__ __forceinline__ void acc(float* p, float v, bool exclusive) {
+  if (exclusive) *p += v;
+  else atomicAdd(p, v);
+}
+
 __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
   const int nrec = a.counters[S3R_CNT_SURV];
+  const bool ex = a.nv == 1;
   const bool plain = (a.kp.flags & S3R_PLAIN) != 0;
   const int B = (a.sh_deg + 1) * (a.sh_deg + 1);
   const int stride = gridDim.x * blockDim.x;
@@ -385,9 +410,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
       float* dsh = a.d_sh + (size_t)i * B * 3;
       for (int b = 0; b < B; ++b) {
         gb[b] = f[3 * b] * dr[0] + f[3 * b + 1] * dr[1] + f[3 * b + 2] * dr[2];
-        atomicAdd(dsh + 3 * b, Y[b] * dr[0]);
-        atomicAdd(dsh + 3 * b + 1, Y[b] * dr[1]);
-        atomicAdd(dsh + 3 * b + 2, Y[b] * dr[2]);
+        acc(dsh + 3 * b, Y[b] * dr[0], ex);
+        acc(dsh + 3 * b + 1, Y[b] * dr[1], ex);
+        acc(dsh + 3 * b + 2, Y[b] * dr[2], ex);
       }
       float ddir[3];
       sh_basis_grad(a.sh_deg, dir[0], dir[1], dir[2], gb, ddir[0], ddir[1], ddir[2]);
@@ -396,9 +421,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) ddl[c] = (ddir[c] - dir[c] * dd) / nrm;
 
-      atomicAdd(a.d_opac + i, dO);
+      acc(a.d_opac + i, dO, ex);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) atomicAdd(a.d_scale + 3 * i + c, dsc[c]);
+      for (int c = 0; c < 3; ++c) acc(a.d_scale + 3 * i + c, dsc[c], ex);
       if (plain) {
         // dl = R_G^T w, w = mu_w - c_w
         float dw[3];
@@ -406,10 +431,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
         for (int ii = 0; ii < 3; ++ii) dw[ii] = Gp[ii * 4] * ddl[0] + Gp[ii * 4 + 1] * ddl[1] + Gp[ii * 4 + 2] * ddl[2];
         float* dmw = a.d_mean_w + ((size_t)slot * a.n + i) * 3;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) atomicAdd(dmw + c, dmu[c] + dw[c]);
+        for (int c = 0; c < 3; ++c) acc(dmw + c, dmu[c] + dw[c], ex);
         float* drw = a.d_rot_w + ((size_t)slot * a.n + i) * 9;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) atomicAdd(drw + t, dRg[t]);
+        for (int t = 0; t < 9; ++t) acc(drw + t, dRg[t], ex);
         if (k > 0) {
           // dR_G[j][i] += w_j ddl_i (rotation part of the pose)
 #pragma unroll
@@ -430,11 +455,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
           dtau[ii] += -(P[ii * 4] * dcen[0] + P[ii * 4 + 1] * dcen[1] + P[ii * 4 + 2] * dcen[2]);
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) atomicAdd(a.d_mean + 3 * i + c, dmu[c]);
+        for (int c = 0; c < 3; ++c) acc(a.d_mean + 3 * i + c, dmu[c], ex);
         float dq[4];
         quat_rot_bwd(q, dRg, dq);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) atomicAdd(a.d_quat + 4 * i + c, dq[c]);
+        for (int c = 0; c < 4; ++c) acc(a.d_quat + 4 * i + c, dq[c], ex);
         if (k > 0) {
 #pragma unroll
           for (int ii = 0; ii < 3; ++ii) {
@@ -577,17 +602,17 @@ __global__ __launch_bounds__(256) void k_zero_g2d(float4* __restrict__ g2d,
 }
 
 hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_g2d, dim3(1024), dim3(256), 0, st, a.g2d, a.counters);
+  S3R_LAUNCH(K_ZERO_G2D, k_zero_g2d, dim3(1024), dim3(256), 0, st, a.g2d, a.counters);
   if (a.total_tiles <= 0) return hipGetLastError();
   switch (a.kp.tile) {
     case 8:
-      hipLaunchKernelGGL(k_raster_bwd<8>, dim3(a.total_tiles), dim3(64), 0, st, a);
+      S3R_LAUNCH(K_RASTER_BWD, k_raster_bwd<8>, dim3(a.total_tiles), dim3(64), 0, st, a);
       break;
     case 16:
-      hipLaunchKernelGGL(k_raster_bwd<16>, dim3(a.total_tiles), dim3(256), 0, st, a);
+      S3R_LAUNCH(K_RASTER_BWD, k_raster_bwd<16>, dim3(a.total_tiles), dim3(256), 0, st, a);
       break;
     case 32:
-      hipLaunchKernelGGL(k_raster_bwd<32>, dim3(a.total_tiles), dim3(1024), 0, st, a);
+      S3R_LAUNCH(K_RASTER_BWD, k_raster_bwd<32>, dim3(a.total_tiles), dim3(1024), 0, st, a);
       break;
     default:
       return hipErrorInvalidValue;
@@ -598,7 +623,7 @@ hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st) {
 hipError_t launch_project_bwd(const ProjBwdArgs& a, int64_t cap_surv, hipStream_t st) {
   const int64_t want = (cap_surv + 255) / 256;
   const int grid = (int)(want < 2048 ? (want > 0 ? want : 1) : 2048);
-  hipLaunchKernelGGL(k_project_bwd, dim3(grid), dim3(256), 0, st, a);
+  S3R_LAUNCH(K_PROJECT_BWD, k_project_bwd, dim3(grid), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -607,11 +632,11 @@ hipError_t launch_pose_bwd(const float* W, const int32_t* tstep, const float* po
                            float* d_pose6, hipStream_t st) {
   const int nvs = nv * S;
   if (d_cam != nullptr && nvs > 0)
-    hipLaunchKernelGGL(k_pose_bwd, dim3((nvs + 127) / 128), dim3(128), 0, st, W, tstep, d_cam, nv,
+    S3R_LAUNCH(K_POSE_BWD, k_pose_bwd, dim3((nvs + 127) / 128), dim3(128), 0, st, W, tstep, d_cam, nv,
                        S, T, d_pose);
   const int ts = T * S;
   if (d_pose6 != nullptr && ts > 0)
-    hipLaunchKernelGGL(k_pose6, dim3((ts + 127) / 128), dim3(128), 0, st, pose, d_pose, ts, S,
+    S3R_LAUNCH(K_POSE6, k_pose6, dim3((ts + 127) / 128), dim3(128), 0, st, pose, d_pose, ts, S,
                        d_pose6);
   return hipGetLastError();
 }
@@ -625,7 +650,7 @@ hipError_t launch_plain_transform_bwd(const float* mean, const float* quat, cons
   for (int s = 0; s < kMaxViews; ++s) ts.tau[s] = s < n_ts ? tsteps[s] : 0;
   const int64_t want = ((int64_t)n + 255) / 256;
   const int grid = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
-  hipLaunchKernelGGL(k_plain_transform_bwd, dim3(grid), dim3(256), 0, st, mean, quat, inst, pose,
+  S3R_LAUNCH(K_PLAIN_TRANSFORM_BWD, k_plain_transform_bwd, dim3(grid), dim3(256), 0, st, mean, quat, inst, pose,
                      n, S, ts, n_ts, d_mean_w, d_rot_w, d_mean, d_quat, d_pose);
   return hipGetLastError();
 }

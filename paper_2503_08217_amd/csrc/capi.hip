@@ -24,13 +24,13 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 struct WsProject {
   uint64_t* flags;
-  int32_t* bstat;
 };
 struct WsSort {
   uint64_t* keys;
   uint64_t* keys_alt;
   int32_t* cursor;
   uint64_t* scan_flags;
+  int32_t* big;
 };
 struct WsBwd {
   float4* g2d;
@@ -42,8 +42,6 @@ size_t ws_project(const S3RSizes& z, WsProject* w, char* base) {
   size_t off = 0;
   if (w) w->flags = reinterpret_cast<uint64_t*>(base + off);
   off += align_up((size_t)nblk * 8 + 8);
-  if (w) w->bstat = reinterpret_cast<int32_t*>(base + off);
-  off += align_up((size_t)nblk * z.n_views * 16 + 16);
   return off;
 }
 
@@ -57,6 +55,8 @@ size_t ws_sort(const S3RSizes& z, WsSort* w, char* base) {
   off += align_up((size_t)z.total_tiles * 4 + 4);
   if (w) w->scan_flags = reinterpret_cast<uint64_t*>(base + off);
   off += align_up((size_t)scan_blocks(z.total_tiles) * 8 + 8);
+  if (w) w->big = reinterpret_cast<int32_t*>(base + off);
+  off += align_up(sort_big_words(z.total_tiles) * 4);
   return off;
 }
 
@@ -203,7 +203,7 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
   S3R_REQUIRE(out->rec_rect);
   S3R_REQUIRE(out->counters);
   S3R_REQUIRE(out->stats);
-  S3R_REQUIRE(out->tile_count);
+  S3R_REQUIRE(out->blocks);
   const S3RSizes z = sizes_of(scene, views, params);
   if (!ws && ws_bytes) return S3R_E_NULL;
   if (ws_bytes < ws_project(z, nullptr, nullptr) || !ws) return S3R_E_WORKSPACE;
@@ -213,8 +213,8 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
   const hipStream_t st = as_stream(stream);
   const int nblk = project_blocks(scene->n);
 
-  S3R_HIP(launch_zero(out->counters, 64, out->tile_count, (size_t)views->total_tiles * 4,
-                      w.flags, (size_t)nblk * 8, out->stats, (size_t)views->n_views * 16, st));
+  S3R_HIP(launch_zero(out->counters, 64, w.flags, (size_t)nblk * 8, out->stats,
+                      (size_t)views->n_views * 16, nullptr, 0, st));
   S3R_HIP(launch_compose(views->W, views->tstep, scene->pose, scene->n_slots, scene->n_timesteps,
                          views->n_views, out->cam, out->cen, out->t_norm, st));
   ProjArgs a{};
@@ -251,27 +251,27 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
   a.rec_rgb = reinterpret_cast<float4*>(out->rec_rgb);
   a.rec_rect = reinterpret_cast<int4*>(out->rec_rect);
   a.counters = out->counters;
-  a.tile_count = out->tile_count;
+  a.bstat = out->blocks;
   a.flags = w.flags;
-  a.bstat = w.bstat;
   a.nblk = nblk;
   a.kp = kparams(*params);
   S3R_HIP(launch_project(a, out->stats, st));
   return S3R_OK;
 }
 
-int s3r_sort(const S3RProjected* proj, const S3RViews* views, const S3RParams* params,
-             S3RBins* bins, void* ws, size_t ws_bytes, void* stream) {
+int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* views,
+             const S3RParams* params, S3RBins* bins, void* ws, size_t ws_bytes, void* stream) {
   int rc = check_params(params);
   if (rc) return rc;
   if ((rc = check_views(views))) return rc;
-  if (!proj || !bins) return S3R_E_NULL;
+  if (!scene || !proj || !bins) return S3R_E_NULL;
+  if (scene->n < 0 || scene->n >= (int64_t(1) << 31)) return S3R_E_SIZE;
   S3R_REQUIRE(proj->rec_geo);
   S3R_REQUIRE(proj->rec_rect);
-  S3R_REQUIRE(proj->rec_view);
   S3R_REQUIRE(proj->counters);
   S3R_REQUIRE(proj->stats);
-  S3R_REQUIRE(proj->tile_count);
+  S3R_REQUIRE(proj->blocks);
+  S3R_REQUIRE(bins->tile_count);
   S3R_REQUIRE(bins->tile_start);
   S3R_REQUIRE(bins->vals);
   const S3RSizes z = sizes_of(nullptr, views, params);
@@ -279,12 +279,29 @@ int s3r_sort(const S3RProjected* proj, const S3RViews* views, const S3RParams* p
   if (!aligned16(ws)) return S3R_E_ALIGN;
   WsSort w;
   ws_sort(z, &w, static_cast<char*>(ws));
-  S3R_HIP(launch_sort(proj->tile_count, views->total_tiles, views->tile_offset, views->n_views,
-                      views->wh, params->tile, reinterpret_cast<const int4*>(proj->rec_rect),
-                      reinterpret_cast<const float4*>(proj->rec_geo), proj->rec_view,
-                      proj->counters, proj->stats, bins->tile_start, bins->vals, w.keys,
-                      w.keys_alt, w.cursor, w.scan_flags, params->cap_dup, params->cap_surv,
-                      as_stream(stream)));
+  SortArgs a{};
+  a.rec_rect = reinterpret_cast<const int4*>(proj->rec_rect);
+  a.rec_geo = reinterpret_cast<const float4*>(proj->rec_geo);
+  a.blocks = proj->blocks;
+  a.nblk = project_blocks(scene->n);
+  a.nv = views->n_views;
+  a.total_tiles = views->total_tiles;
+  a.tile = params->tile;
+  a.tile_offset = views->tile_offset;
+  a.wh = views->wh;
+  a.counters = proj->counters;
+  a.stats = proj->stats;
+  a.tile_count = bins->tile_count;
+  a.tile_start = bins->tile_start;
+  a.vals = bins->vals;
+  a.keys = w.keys;
+  a.keys_alt = w.keys_alt;
+  a.cursor = w.cursor;
+  a.scan_flags = w.scan_flags;
+  a.big = w.big;
+  a.cap_dup = params->cap_dup;
+  a.cap_surv = params->cap_surv;
+  S3R_HIP(launch_sort(a, as_stream(stream)));
   return S3R_OK;
 }
 

@@ -37,6 +37,22 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Sum over the 64 lanes with DPP row operations; the total is valid in lane 63.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float x) {
+  const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, true);
+  return x + __int_as_float(y);
+}
+__device__ __forceinline__ float wave_sum_dpp(float x) {
+  x = dpp_add<0xB1, 0xf>(x);   // quad_perm [1,0,3,2]
+  x = dpp_add<0x4E, 0xf>(x);   // quad_perm [2,3,0,1]
+  x = dpp_add<0x124, 0xf>(x);  // row_ror:4
+  x = dpp_add<0x128, 0xf>(x);  // row_ror:8  -> every lane holds its row's sum
+  x = dpp_add<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = dpp_add<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);

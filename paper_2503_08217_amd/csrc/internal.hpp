@@ -6,6 +6,22 @@
 
 namespace s3r {
 
+// kernels timed by the opt-in profiler (names in profile.hip)
+enum KernelId {
+  K_COMPOSE, K_PLAIN_TRANSFORM, K_PROJECT, K_STATS, K_BIN_COUNT, K_SCAN_TILES, K_DUP_STATS,
+  K_BIN_EMIT, K_TILE_SORT, K_BIG_PREFIX, K_BIG_CHUNKS, K_BIG_MERGE, K_BIG_FINAL, K_RASTER_FWD,
+  K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PROJECT_BWD, K_POSE_BWD, K_POSE6, K_PLAIN_TRANSFORM_BWD,
+  K_VISIBILITY, K_ZERO, K_COUNT
+};
+void prof_begin(int id, hipStream_t st);
+void prof_end(int id, hipStream_t st);
+#define S3R_LAUNCH(ID, ...)        \
+  do {                             \
+    ::s3r::prof_begin(ID, st);     \
+    hipLaunchKernelGGL(__VA_ARGS__); \
+    ::s3r::prof_end(ID, st);       \
+  } while (0)
+
 struct ProjArgs {
   // scene
   const float* mean;
@@ -41,10 +57,10 @@ struct ProjArgs {
   float4* rec_rgb;
   int4* rec_rect;
   int32_t* counters;
-  int32_t* tile_count;
+  // per (block, view): N_t, N_f, N_r, first record
+  int32_t* bstat;
   // workspace
   uint64_t* flags;
-  int32_t* bstat;
   int nblk;
   KParams kp;
 };
@@ -138,12 +154,28 @@ hipError_t launch_zero(void* p0, size_t b0, void* p1, size_t b1, void* p2, size_
 
 // sort.hip
 int scan_blocks(int64_t n);
-hipError_t launch_sort(const int32_t* tile_count, int total_tiles, const int32_t* tile_offset,
-                       int nv, const int32_t* wh, int tile, const int4* rec_rect,
-                       const float4* rec_geo, const int32_t* rec_view, int32_t* counters,
-                       int32_t* stats, int32_t* tile_start, uint32_t* vals, uint64_t* keys,
-                       uint64_t* keys_alt, int32_t* cursor, uint64_t* scan_flags,
-                       int64_t cap_dup, int64_t cap_surv, hipStream_t st);
+struct SortArgs {
+  const int4* rec_rect;
+  const float4* rec_geo;
+  const int32_t* blocks;  // [nblk][nv][4]
+  int nblk, nv, total_tiles, tile;
+  const int32_t* tile_offset;
+  const int32_t* wh;
+  int32_t* counters;
+  int32_t* stats;
+  int32_t* tile_count;
+  int32_t* tile_start;
+  uint32_t* vals;
+  // workspace
+  uint64_t* keys;
+  uint64_t* keys_alt;
+  int32_t* cursor;
+  uint64_t* scan_flags;
+  int32_t* big;  // [total_tiles + 1] big-tile list, [total_tiles+2] chunk offsets, misc
+  int64_t cap_dup, cap_surv;
+};
+size_t sort_big_words(int total_tiles);
+hipError_t launch_sort(const SortArgs& a, hipStream_t st);
 
 // raster.hip
 hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st);

@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kProjBlock) void k_project(ProjArgs a) {
           nf += s_cf[v][w];
         }
         int32_t* bs = a.bstat + ((size_t)vb * a.nv + v) * 4;
-        bs[0] = nt; bs[1] = nf; bs[2] = nr; bs[3] = 0;
+        bs[0] = nt; bs[1] = nf; bs[2] = nr; bs[3] = (int32_t)s_off[v][0];
       }
       st_release(a.flags + vb, ((uint64_t)(vb == 0 ? 2u : 1u) << 32) | agg_l);
     }
@@ -259,6 +259,12 @@ __global__ __launch_bounds__(kProjBlock) void k_project(ProjArgs a) {
   }
   __syncthreads();
   const uint32_t excl = s_excl;
+  // record range of every view of this block: [excl + s_off[v][0], + count)
+  if (tid < a.nv) {
+    int32_t* bs = a.bstat + ((size_t)vb * a.nv + tid) * 4;
+    const int64_t st = (int64_t)excl + bs[3];
+    bs[3] = (int32_t)(st < a.kp.cap_surv ? st : a.kp.cap_surv);
+  }
 
   // ---- phase C: records of the survivors ----
   const int B = (a.sh_deg + 1) * (a.sh_deg + 1);
@@ -308,10 +314,6 @@ __global__ __launch_bounds__(kProjBlock) void k_project(ProjArgs a) {
     a.rec_conic[slot] = make_float4(o.c / o.det, (-o.b) / o.det, o.a / o.det, 0.f);
     a.rec_rgb[slot] = make_float4(r, gg, bb, 0.f);
     a.rec_rect[slot] = make_int4(o.x0, o.y0, o.x1, o.y1);
-    const int gxv = (W + a.kp.tile - 1) / a.kp.tile;
-    int32_t* tc = a.tile_count + a.tile_offset[v];
-    for (int ty = o.y0; ty < o.y1; ++ty)
-      for (int tx = o.x0; tx < o.x1; ++tx) atomicAdd(tc + ty * gxv + tx, 1);
   }
 }
 
@@ -343,7 +345,7 @@ __global__ __launch_bounds__(256) void k_stats(const int32_t* __restrict__ bstat
 // ---------------------------------------------------------------------------
 hipError_t launch_compose(const float* W, const int32_t* tstep, const float* pose, int S, int T,
                           int nv, float* cam, float* cen, float* t_norm, hipStream_t st) {
-  hipLaunchKernelGGL(k_compose, dim3(nv), dim3(128), 0, st, W, tstep, pose, S, T, nv, cam, cen,
+  S3R_LAUNCH(K_COMPOSE, k_compose, dim3(nv), dim3(128), 0, st, W, tstep, pose, S, T, nv, cam, cen,
                      t_norm);
   return hipGetLastError();
 }
@@ -355,7 +357,7 @@ hipError_t launch_plain_transform(const float* mean, const float* quat, const in
   for (int s = 0; s < kMaxViews; ++s) ts.tau[s] = s < n_ts ? tsteps[s] : 0;
   const int grid = (n + 255) / 256;
   if (grid > 0)
-    hipLaunchKernelGGL(k_plain_transform, dim3(grid), dim3(256), 0, st, mean, quat, inst, pose, n,
+    S3R_LAUNCH(K_PLAIN_TRANSFORM, k_plain_transform, dim3(grid), dim3(256), 0, st, mean, quat, inst, pose, n,
                        S, ts, n_ts, mean_w, rot_w);
   return hipGetLastError();
 }
@@ -363,8 +365,8 @@ hipError_t launch_plain_transform(const float* mean, const float* quat, const in
 int project_blocks(int64_t n) { return (int)((n + kProjBlock - 1) / kProjBlock); }
 
 hipError_t launch_project(const ProjArgs& a, int32_t* stats, hipStream_t st) {
-  if (a.nblk > 0) hipLaunchKernelGGL(k_project, dim3(a.nblk), dim3(kProjBlock), 0, st, a);
-  hipLaunchKernelGGL(k_stats, dim3(a.nv), dim3(256), 0, st, a.bstat, a.nblk, a.nv, stats);
+  if (a.nblk > 0) S3R_LAUNCH(K_PROJECT, k_project, dim3(a.nblk), dim3(kProjBlock), 0, st, a);
+  S3R_LAUNCH(K_STATS, k_stats, dim3(a.nv), dim3(256), 0, st, a.bstat, a.nblk, a.nv, stats);
   return hipGetLastError();
 }
 

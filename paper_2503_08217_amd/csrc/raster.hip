@@ -87,13 +87,13 @@ hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st) {
   if (a.total_tiles <= 0) return hipSuccess;
   switch (a.kp.tile) {
     case 8:
-      hipLaunchKernelGGL(k_raster_fwd<8>, dim3(a.total_tiles), dim3(64), 0, st, a);
+      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<8>, dim3(a.total_tiles), dim3(64), 0, st, a);
       break;
     case 16:
-      hipLaunchKernelGGL(k_raster_fwd<16>, dim3(a.total_tiles), dim3(256), 0, st, a);
+      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<16>, dim3(a.total_tiles), dim3(256), 0, st, a);
       break;
     case 32:
-      hipLaunchKernelGGL(k_raster_fwd<32>, dim3(a.total_tiles), dim3(1024), 0, st, a);
+      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<32>, dim3(a.total_tiles), dim3(1024), 0, st, a);
       break;
     default:
       return hipErrorInvalidValue;
@@ -109,31 +109,37 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ color,
                                             const int64_t* __restrict__ pxo,
                                             const int32_t* __restrict__ wh, int nv, int64_t total,
                                             float* __restrict__ loss, float* __restrict__ dcol) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int v = 0;
+  __shared__ float s_loss[kMaxViews];
+  for (int v = threadIdx.x; v < nv; v += blockDim.x) s_loss[v] = 0.f;
+  __syncthreads();
+  int cur = -1;
   float acc = 0.f;
-  if (i < total) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    int v = 0;
     while (v + 1 < nv && pxo[v + 1] <= i) ++v;
+    if (v != cur) {
+      if (cur >= 0) atomicAdd(&s_loss[cur], acc);
+      cur = v;
+      acc = 0.f;
+    }
     const int64_t npx = (int64_t)wh[2 * v] * wh[2 * v + 1];
     const int64_t loc = i - pxo[v];
     const float inv = 1.0f / (3.0f * (float)npx);
+    float a = 0.f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t q = 3 * pxo[v] + c * npx + loc;
       const float d = color[q] - target[q];
-      acc += fabsf(d);
+      a += fabsf(d);
       dcol[q] = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
     }
-    acc *= inv;
+    acc += a * inv;
   }
-  const int v0 = __shfl(v, 0, kWave);
-  const bool uniform = ballot(v != v0 && i < total) == 0ull;
-  if (uniform) {
-    const float w = wave_sum(acc);
-    if (lane_id() == 0 && w != 0.f) atomicAdd(loss + v0, w);
-  } else if (i < total) {
-    atomicAdd(loss + v, acc);
-  }
+  if (cur >= 0) atomicAdd(&s_loss[cur], acc);
+  __syncthreads();
+  for (int v = threadIdx.x; v < nv; v += blockDim.x)
+    if (s_loss[v] != 0.f) atomicAdd(loss + v, s_loss[v]);
 }
 
 hipError_t launch_l1_loss(const float* color, const float* target, const int64_t* px_offset,
@@ -141,9 +147,10 @@ hipError_t launch_l1_loss(const float* color, const float* target, const int64_t
                           float* d_color, hipStream_t st) {
   hipError_t e = launch_zero(loss, (size_t)nv * 4, nullptr, 0, nullptr, 0, nullptr, 0, st);
   if (e != hipSuccess) return e;
-  const int64_t grid = (total_px + 255) / 256;
+  int64_t grid = (total_px + 255) / 256;
+  if (grid > 1024) grid = 1024;
   if (grid > 0)
-    hipLaunchKernelGGL(k_l1, dim3((unsigned)grid), dim3(256), 0, st, color, target, px_offset, wh,
+    S3R_LAUNCH(K_L1, k_l1, dim3((unsigned)grid), dim3(256), 0, st, color, target, px_offset, wh,
                        nv, total_px, loss, d_color);
   return hipGetLastError();
 }

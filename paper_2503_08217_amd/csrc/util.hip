@@ -34,7 +34,7 @@ hipError_t launch_zero(void* p0, size_t b0, void* p1, size_t b1, void* p2, size_
   if (most == 0) return hipSuccess;
   size_t blocks = (most + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, z);
+  S3R_LAUNCH(K_ZERO, k_zero, dim3((unsigned)blocks), dim3(256), 0, st, z);
   return hipGetLastError();
 }
 

@@ -51,7 +51,7 @@ hipError_t launch_visibility(float* life_s, float* life_e, float* vis_s, float* 
   if (n <= 0) return hipSuccess;
   const int64_t words = ((n + 63) / 64) * 2;
   const int64_t grid = (n + 255) / 256;
-  hipLaunchKernelGGL(k_visibility, dim3((unsigned)grid), dim3(256), 0, st, life_s, life_e, vis_s,
+  S3R_LAUNCH(K_VISIBILITY, k_visibility, dim3((unsigned)grid), dim3(256), 0, st, life_s, life_e, vis_s,
                      vis_e, mask, t_norm, nv, n, words, mode, margin);
   return hipGetLastError();
 }

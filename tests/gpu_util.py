@@ -21,6 +21,8 @@ def banner(msg):
 def make_renderer(scene, views, params, plain=False, **kw):
     from paper_2503_08217_amd.renderer import Renderer
     r = Renderer(scene, views, params, plain=plain, **kw)
+    c = r.fit_capacity()
+    assert c["spin"] == 0 and c["ovf_surv"] == 0 and c["ovf_dup"] == 0, c
     return r
 
 

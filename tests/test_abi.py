@@ -28,7 +28,7 @@ def lib():
 
 def test_every_header_symbol_is_exported(lib):
     syms = header_symbols()
-    assert len(syms) >= 11
+    assert len(syms) >= 16
     for s in syms:
         assert hasattr(lib, s), s
         assert s in A.SIGNATURES, s
@@ -45,6 +45,7 @@ def test_struct_sizes_match_c_layout():
     assert C.sizeof(A.S3RScene) == 11 * 8 + 8 + 16
     assert C.sizeof(A.S3RViews) == 7 * 8 + 16
     assert C.sizeof(A.S3RProjected) == 13 * 8
+    assert C.sizeof(A.S3RBins) == 3 * 8
     assert C.sizeof(A.S3RGrads) == 9 * 8
     assert C.sizeof(A.S3RSizes) == 40
 

@@ -105,3 +105,16 @@ def test_visibility_update_fold_reset():
     r.update_visibility(S3R_VIS_RESET)
     np.testing.assert_array_equal(r.vis_s.cpu().numpy(), -1.0)
     np.testing.assert_array_equal(r.life_e.cpu().numpy(), -1.0)
+
+
+def test_grads_single_view_config2_subset():
+    """One view per batch takes the exclusive (non-atomic) accumulation path."""
+    c = scenes.make_config(2, scale_n=0.02)
+    views = c.views.subset([12])
+    tg = scenes.targets(2, views)
+    banner("grads single view")
+    r = make_renderer(c.scene, views, c.params)
+    loss, g = gpu_grads(r, tg)
+    lref, _, ref = oracle_grads(c.scene, views, c.params, tg)
+    assert abs(loss - lref) <= 1e-4 * abs(lref)
+    compare(g, ref, KEYS)

@@ -149,3 +149,19 @@ def test_batched_uneven_views_equal_single_views():
         rs.forward()
         np.testing.assert_array_equal(image_np(rb, j), image_np(rs, 0))
         np.testing.assert_array_equal(mask_bits(rb)[j], mask_bits(rs)[0])
+
+
+@pytest.mark.parametrize("n", [9000, 30000])
+def test_crowded_tiles_sorted_exactly(n):
+    """Tens of thousands of Gaussians pile into a few tiles: lists longer than
+    the LDS sort take the chunk-sort + merge-pass path and must still match
+    the oracle's order bit for bit."""
+    scene, views = scenes.micro_scene(11, n=n, width=64, height=48, n_inst=0, spread=0.05, T=1)
+    p = scenes.default_params(tile=16)
+    banner(f"crowded tiles n={n}")
+    r = make_renderer(scene, views, p)
+    r.forward()
+    rec = records(r)
+    counts = r.tile_count.cpu().numpy()
+    assert counts.max() > 4096
+    check_view(scene, views, p, r, rec, 0, region=(16, 16, 48, 40))

@@ -1,15 +1,21 @@
 """Throughput of the per-view fwd+bwd step: streamlined vs plain, same GPU.
 
-Workload (default): the 2M-Gaussian, 1 km corridor with 30 instances,
-1920x1080 forward camera, SH degree 3, LOD threshold 1 px, temporal
-visibility on after a warm-up pass (UPDATE over all 50 timesteps, then FOLD).
-A step is one view: project/cull, sort, raster, L1 loss, backward and the
-point-life update.  Steps cycle over 8 evenly spaced timesteps.  The plain
-(conventional) pipeline -- transform every Gaussian to the world frame,
-project everything, no temporal filter, no LOD -- is timed the same way on
-the same GPU.
+Workload (default, the 2M-Gaussian corridor): 1.7M static Gaussians along a
+1 km corridor plus 30 instances of 10k, 1920x1080 forward camera, SH degree 3,
+LOD threshold 1 px, temporal visibility on after one warm-up pass (UPDATE over
+all 50 timesteps, then FOLD).  A step renders one view: project/cull, sort,
+raster, L1 loss against a seeded target, backward, point-life update.  Steps
+cycle over 8 evenly spaced timesteps.  The plain (conventional) pipeline --
+transform every Gaussian to the world frame, project all of them, no temporal
+filter and no LOD -- runs the same steps on the same GPU.
 
-Prints one JSON line.  Only one GPU is used (--gpus above 1 is refused).
+Inputs are resident in HBM before the timed region; the timed region is the K
+steps between two synchronisations.  Every kernel of the timed steps is
+bracketed by HIP events on its stream (the library's opt-in profiler); the
+kernel with the largest total time is the one the roofline entry describes.
+
+Prints one JSON line on stdout.  Only one GPU is used (--gpus above 1 is
+refused).
 """
 
 from __future__ import annotations
@@ -27,23 +33,27 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
+METRIC = "fwd+bwd views/s at 1080p, 2M Gaussians: streamlined vs plain, same GPU"
+
+# algorithmic work per unit (see the design notes)
+FLOP_FWD_PAIR = 22.0     # blending one (pixel, list entry) pair
+FLOP_BWD_PAIR = 60.0     # replaying one (pixel, list entry) pair backwards
+REC_BYTES = 72           # record written per survivor (gid, view, geo, conic, rgb, rect)
+GEOM_BYTES = 44          # mean, scale, quat, instance id of a Gaussian that passes
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def build_renderer(cfg, plain, torch):
+def make_renderer(cfg, plain):
     from paper_2503_08217_amd.renderer import Renderer
-    import scenes
-    c = cfg
-    params = dict(c.params)
+    params = dict(cfg.params)
     if plain:
         params.update(temporal=False, lod=False, lod_r=0.0)
-    first = c.views.subset([c.timed_views[0]])
-    r = Renderer(c.scene, first, params, plain=plain, cap_surv=max(1024, c.scene.n // 2),
-                 cap_dup=max(4096, 2 * c.scene.n))
-    return r
+    first = cfg.views.subset([cfg.timed_views[0]])
+    return Renderer(cfg.scene, first, params, plain=plain, cap_surv=max(1024, cfg.scene.n // 2),
+                    cap_dup=max(4096, 2 * cfg.scene.n))
 
 
 def warmup_temporal(r, cfg, torch):
@@ -62,50 +72,127 @@ def warmup_temporal(r, cfg, torch):
     torch.cuda.synchronize()
 
 
-def time_steps(r, handles, targets, steps, warmup, torch):
-    ev = {}
+def view_units(r, handles, targets, torch):
+    """Per timed view: stats and the algorithmic units of each kernel."""
+    out = []
+    for h, tg in zip(handles, targets):
+        r.use_views(h)
+        r.forward()
+        torch.cuda.synchronize()
+        st = r.stats.cpu().numpy()[0].astype(np.int64)
+        last = r.last[: r.total_px].to(torch.int64).sum().item()
+        out.append(dict(N_t=int(st[0]), N_f=int(st[1]), N_r=int(st[2]), N_dup=int(st[3]),
+                        pairs_last=int(last)))
+    return out
 
-    def mark(name):
-        e = torch.cuda.Event(enable_timing=True)
-        e.record()
-        ev.setdefault(name, []).append(e)
 
+def timed(r, handles, targets, steps, warmup, torch, profile=True):
+    from paper_2503_08217_amd import _abi
+    lib = _abi.load()
     for i in range(warmup):
         h = i % len(handles)
         r.use_views(handles[h])
         r.step(targets[h])
     torch.cuda.synchronize()
+    if profile:
+        _abi.check(lib.s3r_profile_reset(), "profile reset")
+        _abi.check(lib.s3r_profile_enable(1), "profile enable")
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
         h = i % len(handles)
         r.use_views(handles[h])
-        mark("a")
-        if r.plain:
-            r.plain_transform()
-        r.project_cull()
-        mark("b")
-        r.sort()
-        mark("c")
-        r.raster_fwd()
-        mark("d")
-        r.l1_loss(targets[h])
-        r.zero_grads()
-        mark("e")
-        r.raster_bwd()
-        mark("f")
-        if not r.plain:
-            from paper_2503_08217_amd import S3R_VIS_UPDATE
-            r.update_visibility(S3R_VIS_UPDATE)
-        mark("g")
+        r.step(targets[h])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    seg = {}
-    names = ["a", "b", "c", "d", "e", "f", "g"]
-    labels = ["project", "sort", "raster_fwd", "loss", "backward", "visibility"]
-    for j, lab in enumerate(labels):
-        s, e = ev[names[j]], ev[names[j + 1]]
-        seg[lab] = float(np.mean([s[i].elapsed_time(e[i]) for i in range(steps)]))
-    return (t1 - t0), seg
+    table = {}
+    if profile:
+        table = _abi.profile_table()
+        _abi.check(lib.s3r_profile_enable(0), "profile disable")
+    return t1 - t0, table
+
+
+def kernel_roofline(name, total_ms, launches, units, steps, sh_degree, n):
+    """Algorithmic work of the timed steps for kernel `name` -> roofline entry."""
+    nviews = len(units)
+    # the timed steps cycle over the views: work of step i is that of view i % nviews
+    per = [units[i % nviews] for i in range(steps)]
+    sh_bytes = 12 * (sh_degree + 1) ** 2
+    if name == "raster_bwd":
+        work = sum(u["pairs_last"] for u in per) * FLOP_BWD_PAIR
+        return "alu", work / (total_ms * 1e-3) / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s", \
+            f"{FLOP_BWD_PAIR:.0f} FLOP per replayed (pixel, entry) pair, pairs = sum of last"
+    if name == "raster_fwd":
+        work = sum(u["pairs_last"] for u in per) * FLOP_FWD_PAIR
+        return "alu", work / (total_ms * 1e-3) / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s", \
+            f"{FLOP_FWD_PAIR:.0f} FLOP per blended (pixel, entry) pair, pairs = sum of last"
+    if name == "project":
+        b = sum(8 * n + GEOM_BYTES * u["N_t"] + n / 8 + (4 + sh_bytes + REC_BYTES) * u["N_r"]
+                for u in per)
+        return "hbm", b / (total_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", \
+            "8 N + 44 N_t + N/8 + (4 + 12(L+1)^2 + 72) N_r bytes"
+    if name in ("tile_sort", "bin_emit", "bin_count"):
+        b = sum(12 * u["N_dup"] for u in per)
+        return "hbm", b / (total_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", "12 N_dup bytes"
+    if name == "project_bwd":
+        b = sum((48 + 4 + 2 * sh_bytes + 40 + 48) * u["N_r"] for u in per)
+        return "hbm", b / (total_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", \
+            "(read 48 + 4 + 12(L+1)^2 + g2d 48, write 40 + 12(L+1)^2) N_r bytes"
+    return None
+
+
+def pcs_bytes(units, steps, sh_degree, n):
+    """Algorithmic HBM bytes of project/cull/sort over the timed steps."""
+    sh_bytes = 12 * (sh_degree + 1) ** 2
+    per = [units[i % len(units)] for i in range(steps)]
+    return sum(8 * n + GEOM_BYTES * u["N_t"] + n / 8 + (4 + sh_bytes + REC_BYTES) * u["N_r"]
+               + 12 * u["N_dup"] + 24 * u["N_dup"] for u in per)
+
+
+def cpu_baseline(cfg, n_tiles_sample=48):
+    """The oracle as it stands, on a bounded sample of one view of the same
+    workload: the binary32 decision layer and colours over all N Gaussians,
+    then FP64 blending + autograd backward of `n_tiles_sample` random 16x16
+    tiles, scaled to a whole view."""
+    import torch
+
+    from oracle import grad as ograd
+    from oracle import order, render
+    threads = len(os.sched_getaffinity(0))
+    torch.set_num_threads(threads)
+    v = cfg.timed_views[len(cfg.timed_views) // 2]
+    t0 = time.perf_counter()
+    o = render.render_view(cfg.scene, cfg.views, v, cfg.params, with_image=False)
+    t_dec = time.perf_counter() - t0
+    d = o["dec"]
+    w, h = int(cfg.views.wh[v, 0]), int(cfg.views.wh[v, 1])
+    ts = int(cfg.params["tile"])
+    gx, gy = (w + ts - 1) // ts, (h + ts - 1) // ts
+    rng = np.random.default_rng(7)
+    pt = ograd.to_torch_params(cfg.scene)
+    t1 = time.perf_counter()
+    tg = np.asarray(rng.uniform(0, 1, (3, ts, ts)))
+    for _ in range(n_tiles_sample):
+        tx, ty = int(rng.integers(gx)), int(rng.integers(gy))
+        reg = (tx * ts, ty * ts, min(w, tx * ts + ts), min(h, ty * ts + ts))
+        ids = o["ids"]
+        uu, vv = d["u"][ids].astype(np.float64), d["v"][ids].astype(np.float64)
+        ddx = np.maximum(0.0, np.maximum(reg[0] - uu, uu - (reg[2] - 1)))
+        ddy = np.maximum(0.0, np.maximum(reg[1] - vv, vv - (reg[3] - 1)))
+        lim = 2.0 * cfg.params["cutoff"] * d["lam_d"][ids].astype(np.float64) * 1.0001
+        cand = order.global_order(ids[ddx * ddx + ddy * ddy <= lim], d["depth_bits"])
+        img, _ = ograd.render_t(pt, cfg.scene, cfg.views, v, cand, cfg.params, region=reg)
+        loss = ograd.l1_loss_t(img, tg[:, : reg[3] - reg[1], : reg[2] - reg[0]])
+        loss.backward()
+    t_tiles = time.perf_counter() - t1
+    per_view = t_dec + t_tiles / n_tiles_sample * gx * gy
+    return {"value": 1.0 / per_view, "unit": "views/s", "cores": int(torch.get_num_threads()),
+            "kind": "oracle",
+            "sample": (f"one {w}x{h} view of the same workload: binary32 decisions + SH colours over "
+                       f"all {cfg.scene.n} Gaussians without the temporal pre-filter (same survivors, "
+                       f"more projections; {t_dec:.1f}s, single-threaded numpy), FP64 "
+                       f"blending + autograd backward of {n_tiles_sample} random {ts}x{ts} tiles "
+                       f"({t_tiles:.1f}s, torch CPU), scaled to the view's {gx * gy} tiles")}
 
 
 def main():
@@ -118,11 +205,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
-              "(the path would shard views across GPUs; see the design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported here "
+              "(views would be sharded across GPUs with a gradient all-reduce)", file=sys.stderr)
         sys.exit(2)
 
     import torch
+
     import scenes
 
     t_gen = time.perf_counter()
@@ -135,40 +223,48 @@ def main():
     results = {}
     for plain in ([False] if a.no_plain else [False, True]):
         name = "plain" if plain else "streamlined"
-        r = build_renderer(cfg, plain, torch)
+        r = make_renderer(cfg, plain)
         if cfg.warmup_fold and not plain:
             warmup_temporal(r, cfg, torch)
             log("temporal warm-up done")
         handles = r.prepare_views([cfg.views.subset([v]) for v in cfg.timed_views])
-        # size capacities on the heaviest timed view
         for h in handles:
             r.use_views(h)
             r.fit_capacity()
         handles = r.prepare_views([cfg.views.subset([v]) for v in cfg.timed_views])
-        stats = []
-        for h in handles:
-            r.use_views(h)
-            r.forward()
-            torch.cuda.synchronize()
-            stats.append(r.stats.cpu().numpy()[0].tolist())
-        log(f"{name}: per-view [N_t, N_f, N_r, N_dup] = {stats}")
-        elapsed, seg = time_steps(r, handles, targets, a.steps, a.warmup, torch)
+        units = view_units(r, handles, targets, torch)
+        log(f"{name}: per view {[(u['N_t'], u['N_f'], u['N_r'], u['N_dup']) for u in units]}")
+        elapsed, table = timed(r, handles, targets, a.steps, a.warmup, torch)
         vps = a.steps / elapsed
-        log(f"{name}: {vps:.1f} views/s, {1000 * elapsed / a.steps:.3f} ms/step, segments(ms)={seg}")
-        results[name] = dict(views_per_s=vps, ms_per_step=1000 * elapsed / a.steps, seg=seg,
-                             stats=stats)
+        log(f"{name}: {vps:.1f} views/s, {1000 * elapsed / a.steps:.3f} ms/step")
+        for k, (ms, cnt) in sorted(table.items(), key=lambda kv: -kv[1][0]):
+            log(f"   {k:22s} {1000 * ms / cnt:9.1f} us x {cnt}")
+        results[name] = dict(vps=vps, ms=1000 * elapsed / a.steps, table=table, units=units)
         del r
         torch.cuda.empty_cache()
 
     s = results["streamlined"]
+    table, units = s["table"], s["units"]
+    dom = max(table.items(), key=lambda kv: kv[1][0])
+    dname, (dms, dcnt) = dom
+    rl = kernel_roofline(dname, dms, dcnt, units, a.steps, cfg.scene.sh_degree, cfg.scene.n)
+    roof = None
+    if rl:
+        bound, ach, peak, unit, basis = rl
+        roof = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+                "traffic": None, "kernel": dname, "avg_us": 1000 * dms / dcnt, "work": basis}
+    pcs_names = ("compose", "project", "stats", "bin_count", "scan_tiles", "dup_stats", "bin_emit",
+                 "tile_sort", "big_prefix", "big_chunks", "big_merge", "big_final")
+    pcs_ms = sum(table[k][0] for k in pcs_names if k in table)
+    pcs_gbs = pcs_bytes(units, a.steps, cfg.scene.sh_degree, cfg.scene.n) / (pcs_ms * 1e-3) / 1e9
     out = {
-        "metric": "fwd+bwd views/s at 1080p, 2M Gaussians: streamlined vs plain, same GPU",
-        "value": s["views_per_s"],
+        "metric": METRIC,
+        "value": s["vps"],
         "unit": "views/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": s["ms_per_step"],
+        "ms_per_step": s["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -177,12 +273,21 @@ def main():
         "config": {"workload": cfg.name, "gaussians": int(cfg.scene.n), "instances": 30,
                    "resolution": "1920x1080", "views_per_step": 1, "sh_degree": 3,
                    "lod_r_px": 1.0, "temporal": "on (after warm-up fold)"},
-        "segments_ms": s["seg"],
+        "roofline": roof,
+        "project_cull_sort_hbm": {"achieved": pcs_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": pcs_gbs / HBM_PEAK_GBS, "ms_per_step": pcs_ms / a.steps},
+        "kernels_us": {k: 1000 * ms / cnt for k, (ms, cnt) in table.items()},
     }
     if "plain" in results:
-        out["plain_views_per_s"] = results["plain"]["views_per_s"]
-        out["speedup_vs_plain"] = s["views_per_s"] / results["plain"]["views_per_s"]
-        out["plain_segments_ms"] = results["plain"]["seg"]
+        p = results["plain"]
+        out["plain_views_per_s"] = p["vps"]
+        out["speedup_vs_plain"] = s["vps"] / p["vps"]
+        out["plain_kernels_us"] = {k: 1000 * ms / cnt for k, (ms, cnt) in p["table"].items()}
+    if not a.no_cpu:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(cfg)
+        log(f"cpu baseline {out['cpu_baseline']['value']:.5f} views/s "
+            f"({time.perf_counter() - t0:.1f}s)")
     print(json.dumps(out), flush=True)
 
 

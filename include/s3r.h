@@ -79,8 +79,11 @@ enum {
 enum {
   S3R_TEMPORAL = 1, /* apply the temporal-visibility test (Sec. 3.3)       */
   S3R_LOD = 2,      /* apply the LOD cull with threshold lod_r (Sec. 3.3)  */
-  S3R_PLAIN = 4     /* project the world-frame arrays of s3r_plain_transform
+  S3R_PLAIN = 4,    /* project the world-frame arrays of s3r_plain_transform
                        with the view camera (conventional route, Sec. 3.1) */
+  S3R_LOD_STOCHASTIC = 8 /* Eq. (7): drop a sub-threshold Gaussian with
+                       probability p = p_max + (p_max - 0.01) min(0, (d - D)/D)
+                       instead of always (needs S3R_LOD)                   */
 };
 
 /* modes of s3r_update_visibility */
@@ -109,6 +112,14 @@ typedef struct S3RParams {
   float bg[3];        /* background colour                                  */
   int64_t cap_surv;   /* capacity of the survivor-record arrays             */
   int64_t cap_dup;    /* capacity of the (tile, record) pair arrays         */
+  /* stochastic LOD drop (S3R_LOD_STOCHASTIC): the draw of Gaussian i in view v
+     is Philox4x32-10 with counter (i, v, step, 0) and key (seed low, seed
+     high); u = (first word >> 8) 2^-24 and the Gaussian is dropped if u < p */
+  uint64_t seed;
+  float lod_pmax;     /* p_max of Eq. (7)                                   */
+  float lod_D;        /* D of Eq. (7), camera-space depth                   */
+  uint32_t step;      /* training-step counter of the draw                  */
+  uint32_t pad_;
 } S3RParams;
 
 typedef struct S3RScene {

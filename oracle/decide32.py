@@ -95,7 +95,17 @@ def lam_max32(a, c, det):
     return m + np.sqrt(np.maximum(disc, _f(0.0)))
 
 
-def project_cull32(scene, W34, Kv, wh, tau, params, plain=False):
+def lod_drop_probability32(depth, pmax, D):
+    """Eq. (7): p = p_max + (p_max - 0.01) min(0, (d - D) / D), binary32 in
+    this order."""
+    d = np.asarray(depth, F)
+    t1 = d - _f(D)
+    t2 = t1 / _f(D)
+    t3 = np.minimum(_f(0.0), t2)
+    return _f(pmax) + (_f(pmax) - _f(0.01)) * t3
+
+
+def project_cull32(scene, W34, Kv, wh, tau, params, plain=False, view_index=0):
     """Decisions and projected attributes of one view, binary32.
 
     Returns a dict of (N,) arrays (values of Gaussians that fail an earlier
@@ -200,7 +210,16 @@ def project_cull32(scene, W34, Kv, wh, tau, params, plain=False):
         visible = pass_t & depth_ok & (det > _f(0.0)) & (x1 > x0) & (y1 > y0)
         r = _f(params["lod_r"])
         if params.get("lod", False) and r > 0:
-            keep = ~(lam_raw <= r * r)
+            drop = lam_raw <= r * r
+            if params.get("lod_stochastic", False):
+                # Eq. (7): a sub-threshold Gaussian is dropped with probability
+                # p(depth); the draw is the counter-based generator of `rng`
+                from . import rng
+                p = lod_drop_probability32(pz, params["lod_pmax"], params["lod_D"])
+                u = rng.uniform(np.arange(N), view_index, params.get("step", 0),
+                                params.get("seed", 0))
+                drop = drop & (u < p)
+            keep = ~drop
         else:
             keep = np.ones(N, bool)
         surv = visible & keep

@@ -36,7 +36,7 @@ def survivor_colours(scene, d, ids):
 
 def render_view(scene, views, v, params, plain=False, region=None, with_image=True):
     W34, Kv, wh, tau = views.W[v], views.K[v], views.wh[v], int(views.tstep[v])
-    d = decide32.project_cull32(scene, W34, Kv, wh, tau, params, plain=plain)
+    d = decide32.project_cull32(scene, W34, Kv, wh, tau, params, plain=plain, view_index=v)
     ids = np.nonzero(d["surv"])[0]
     N = scene.n
     rgb = np.zeros((N, 3))

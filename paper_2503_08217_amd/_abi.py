@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libs3r.so")
 
 S3R_OK = 0
-S3R_TEMPORAL, S3R_LOD, S3R_PLAIN = 1, 2, 4
+S3R_TEMPORAL, S3R_LOD, S3R_PLAIN, S3R_LOD_STOCHASTIC = 1, 2, 4, 8
 S3R_VIS_UPDATE, S3R_VIS_FOLD, S3R_VIS_RESET = 0, 1, 2
 S3R_WS_PROJECT, S3R_WS_SORT, S3R_WS_BACKWARD = 0, 1, 2
 CNT_SURV, CNT_OVF_SURV, CNT_DUP, CNT_OVF_DUP, CNT_SPIN = 0, 1, 2, 3, 4
@@ -28,7 +28,9 @@ class S3RParams(C.Structure):
                 ("z_near", C.c_float), ("z_far", C.c_float), ("eps2d", C.c_float),
                 ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
                 ("cutoff", C.c_float), ("jac_clamp", C.c_float), ("bg", C.c_float * 3),
-                ("cap_surv", C.c_int64), ("cap_dup", C.c_int64)]
+                ("cap_surv", C.c_int64), ("cap_dup", C.c_int64), ("seed", C.c_uint64),
+                ("lod_pmax", C.c_float), ("lod_D", C.c_float), ("step", C.c_uint32),
+                ("pad_", C.c_uint32)]
 
 
 class S3RScene(C.Structure):

@@ -87,6 +87,10 @@ KParams kparams(const S3RParams& p) {
   k.bg2 = p.bg[2];
   k.cap_surv = p.cap_surv;
   k.cap_dup = p.cap_dup;
+  k.seed = p.seed;
+  k.lod_pmax = p.lod_pmax;
+  k.lod_D = p.lod_D;
+  k.step = p.step;
   return k;
 }
 
@@ -96,6 +100,7 @@ int check_params(const S3RParams* p) {
   if (p->cap_surv <= 0 || p->cap_surv >= (int64_t(1) << 31)) return S3R_E_SIZE;
   if (p->cap_dup <= 0 || p->cap_dup >= (int64_t(1) << 31)) return S3R_E_SIZE;
   if (!(p->alpha_max > 0.f) || !(p->alpha_max < 1.f) || !(p->t_min > 0.f)) return S3R_E_ARG;
+  if ((p->flags & S3R_LOD_STOCHASTIC) && !(p->lod_D > 0.f)) return S3R_E_ARG;
   return S3R_OK;
 }
 

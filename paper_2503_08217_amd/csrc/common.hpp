@@ -68,7 +68,30 @@ struct KParams {
   float lod_r, z_near, z_far, eps2d, alpha_min, alpha_max, t_min, cutoff, jac_clamp;
   float bg0, bg1, bg2;
   int64_t cap_surv, cap_dup;
+  uint64_t seed;
+  float lod_pmax, lod_D;
+  uint32_t step;
 };
+
+// Philox4x32-10 (Salmon et al., SC'11): first output word of counter
+// (c0, c1, c2, c3) under key (k0, k1).
+__device__ __forceinline__ uint32_t philox_first(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+  }
+  return c0;
+}
 
 // ---------------------------------------------------------------------------
 // canonical binary32 projection of one Gaussian into one view
@@ -111,7 +134,8 @@ __device__ __forceinline__ float clamp_nan(float v, float hi) {
 __device__ __forceinline__ void project_canonical(const float P[12], float mx, float my, float mz,
                                                   const float Rg[9], float s0, float s1, float s2,
                                                   float fx, float fy, float cx, float cy, int W,
-                                                  int H, const KParams& kp, Proj& o) {
+                                                  int H, const KParams& kp, Proj& o, int gid = 0,
+                                                  int view = 0) {
   o.px = ((P[0] * mx + P[1] * my) + P[2] * mz) + P[3];
   o.py = ((P[4] * mx + P[5] * my) + P[6] * mz) + P[7];
   o.pz = ((P[8] * mx + P[9] * my) + P[10] * mz) + P[11];
@@ -182,7 +206,19 @@ __device__ __forceinline__ void project_canonical(const float P[12], float mx, f
   o.visible = o.depth_ok && (o.det > 0.0f) && (o.x1 > o.x0) && (o.y1 > o.y0);
   const float r = kp.lod_r;
   const bool lod = (kp.flags & S3R_LOD) && (r > 0.0f);
-  o.keep = !(lod && (o.lam_raw <= r * r));
+  bool drop = lod && (o.lam_raw <= r * r);
+  if (drop && (kp.flags & S3R_LOD_STOCHASTIC)) {
+    // Eq. (7): drop probability grows with depth from 0.01 to p_max at D
+    const float t1 = o.pz - kp.lod_D;
+    const float t2 = t1 / kp.lod_D;
+    const float t3 = fminf(0.0f, t2);
+    const float p = kp.lod_pmax + (kp.lod_pmax - 0.01f) * t3;
+    const uint32_t x = philox_first((uint32_t)gid, (uint32_t)view, kp.step, 0u,
+                                    (uint32_t)kp.seed, (uint32_t)(kp.seed >> 32));
+    const float u = (float)(x >> 8) * 5.9604644775390625e-08f;
+    drop = u < p;
+  }
+  o.keep = !drop;
 }
 
 // ---------------------------------------------------------------------------

@@ -203,7 +203,8 @@ __global__ __launch_bounds__(kProjBlock) void k_project(ProjArgs a) {
       int W, H;
       view_geometry(a, v, g, plain, i, e, P, fx, fy, cx, cy, W, H);
       Proj o;
-      project_canonical(P, e.mx, e.my, e.mz, e.R, e.s0, e.s1, e.s2, fx, fy, cx, cy, W, H, a.kp, o);
+      project_canonical(P, e.mx, e.my, e.mz, e.R, e.s0, e.s1, e.s2, fx, fy, cx, cy, W, H, a.kp, o,
+                        i, v);
       vis = o.visible;
       surv = vis && o.keep;
     }
@@ -278,7 +279,8 @@ __global__ __launch_bounds__(kProjBlock) void k_project(ProjArgs a) {
     int W, H;
     view_geometry(a, v, g, plain, i, e, P, fx, fy, cx, cy, W, H);
     Proj o;
-    project_canonical(P, e.mx, e.my, e.mz, e.R, e.s0, e.s1, e.s2, fx, fy, cx, cy, W, H, a.kp, o);
+    project_canonical(P, e.mx, e.my, e.mz, e.R, e.s0, e.s1, e.s2, fx, fy, cx, cy, W, H, a.kp, o,
+                      i, v);
 
     // viewing direction in the instance-local frame
     float dx, dy, dz;

@@ -209,11 +209,16 @@ class Renderer:
             flags |= A.S3R_LOD
         if self.plain:
             flags |= A.S3R_PLAIN
+        if p.get("lod_stochastic", False):
+            flags |= A.S3R_LOD_STOCHASTIC
         bg = (C.c_float * 3)(*[float(x) for x in p["bg"]])
         return A.S3RParams(int(p["tile"]), flags, float(p["lod_r"]), float(p["z_near"]),
                            float(p["z_far"]), float(p["eps2d"]), float(p["alpha_min"]),
                            float(p["alpha_max"]), float(p["t_min"]), float(p["cutoff"]),
-                           float(p["jac_clamp"]), bg, self.cap_surv, self.cap_dup)
+                           float(p["jac_clamp"]), bg, self.cap_surv, self.cap_dup,
+                           int(p.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF,
+                           float(p.get("lod_pmax", 1.0)), float(p.get("lod_D", 1.0)),
+                           int(p.get("step", 0)) & 0xFFFFFFFF, 0)
 
     def set_flags(self, **over):
         self.params.update(over)
@@ -290,6 +295,24 @@ class Renderer:
         self.raster_bwd()
         if update_visibility and not self.plain:
             self.update_visibility(A.S3R_VIS_UPDATE)
+
+    def capture_step(self, target, update_visibility=True):
+        """Record one whole `step` (forward, loss, backward, point-life update)
+        into a HIP graph; `graph.replay()` then runs it with one launch.  The
+        library records only kernel nodes (its buffers are zeroed by fill
+        kernels, never memset nodes) and allocates nothing, so the captured
+        step reuses this renderer's buffers on every replay."""
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.step(target, update_visibility)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            self.step(target, update_visibility)
+        torch.cuda.synchronize()
+        return graph
 
     # ---------------------------------------------------------------- helpers
     def read_counters(self):

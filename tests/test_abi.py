@@ -41,7 +41,7 @@ def test_version_and_status(lib):
 
 
 def test_struct_sizes_match_c_layout():
-    assert C.sizeof(A.S3RParams) == 72
+    assert C.sizeof(A.S3RParams) == 96
     assert C.sizeof(A.S3RScene) == 11 * 8 + 8 + 16
     assert C.sizeof(A.S3RViews) == 7 * 8 + 16
     assert C.sizeof(A.S3RProjected) == 13 * 8

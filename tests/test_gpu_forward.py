@@ -165,3 +165,18 @@ def test_crowded_tiles_sorted_exactly(n):
     counts = r.tile_count.cpu().numpy()
     assert counts.max() > 4096
     check_view(scene, views, p, r, rec, 0, region=(16, 16, 48, 40))
+
+
+def test_stochastic_lod_parity():
+    """Eq. (7) drop with the counter-based generator: the GPU keeps exactly
+    the Gaussians the oracle keeps, in every view of a batch."""
+    c = scenes.make_config(2, scale_n=0.05)
+    views = c.views.subset([4, 22, 39])
+    p = dict(c.params, lod_r=2.0, lod_stochastic=True, lod_pmax=0.85, lod_D=40.0, seed=987654321,
+             step=3)
+    banner("stochastic LOD")
+    r = make_renderer(c.scene, views, p)
+    r.forward()
+    rec = records(r)
+    for v in range(3):
+        check_view(c.scene, views, p, r, rec, v, region=(400, 280, 432, 312))

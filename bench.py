@@ -131,9 +131,15 @@ def kernel_roofline(name, total_ms, launches, units, steps, sh_degree, n):
                 for u in per)
         return "hbm", b / (total_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", \
             "8 N + 44 N_t + N/8 + (4 + 12(L+1)^2 + 72) N_r bytes"
-    if name in ("tile_sort", "bin_emit", "bin_count"):
-        b = sum(12 * u["N_dup"] for u in per)
-        return "hbm", b / (total_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", "12 N_dup bytes"
+    if name == "radix":
+        passes = launches // steps // 2
+        b = sum((8 + 24) * passes * u["N_dup"] for u in per)
+        return "hbm", b / (total_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", \
+            "per radix pass 8 B read (histogram) + 12 B read + 12 B written per pair"
+    if name == "records":
+        b = sum((GEOM_BYTES + 4 + sh_bytes + REC_BYTES + 4) * u["N_r"] for u in per)
+        return "hbm", b / (total_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", \
+            "(44 + 4 + 12(L+1)^2 + 76) N_r bytes"
     if name == "project_bwd":
         b = sum((48 + 4 + 2 * sh_bytes + 40 + 48) * u["N_r"] for u in per)
         return "hbm", b / (total_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", \
@@ -142,7 +148,10 @@ def kernel_roofline(name, total_ms, launches, units, steps, sh_degree, n):
 
 
 def pcs_bytes(units, steps, sh_degree, n):
-    """Algorithmic HBM bytes of project/cull/sort over the timed steps."""
+    """Algorithmic HBM bytes of project/cull/sort over the timed steps: the
+    Gaussians' visibility interval, the geometry of those that pass, the M_t
+    bits, SH + opacity + record of the survivors, and every (tile, record)
+    pair written once and read + written once by a sort."""
     sh_bytes = 12 * (sh_degree + 1) ** 2
     per = [units[i % len(units)] for i in range(steps)]
     return sum(8 * n + GEOM_BYTES * u["N_t"] + n / 8 + (4 + sh_bytes + REC_BYTES) * u["N_r"]
@@ -253,8 +262,8 @@ def main():
         bound, ach, peak, unit, basis = rl
         roof = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
                 "traffic": None, "kernel": dname, "avg_us": 1000 * dms / dcnt, "work": basis}
-    pcs_names = ("compose", "project", "stats", "bin_count", "scan_tiles", "dup_stats", "bin_emit",
-                 "tile_sort", "big_prefix", "big_chunks", "big_merge", "big_final")
+    pcs_names = ("compose", "project", "block_offsets", "records", "scan", "emit_pairs", "radix",
+                 "tile_ranges", "dup_stats")
     pcs_ms = sum(table[k][0] for k in pcs_names if k in table)
     pcs_gbs = pcs_bytes(units, a.steps, cfg.scene.sh_degree, cfg.scene.n) / (pcs_ms * 1e-3) / 1e9
     out = {

@@ -62,8 +62,6 @@ extern "C" {
 
 #define S3R_ABI_VERSION 1
 
-/* Gaussians per block of s3r_project_cull (sizes S3RProjected.blocks) */
-#define S3R_PROJECT_BLOCK 256
 
 enum {
   S3R_OK = 0,
@@ -171,9 +169,7 @@ typedef struct S3RProjected {
   int32_t* counters;  /* [16] see S3R_CNT_*                                   */
   int32_t* stats;     /* [V][4] N_t (temporal pass), N_f (= |M_t|), N_r (records),
                          N_dup (pairs, written by s3r_sort)                     */
-  int32_t* blocks;    /* [ceil(N/S3R_PROJECT_BLOCK)][V][4] per Gaussian block and
-                         view: N_t, N_f, N_r and the first record index; read by
-                         s3r_sort to bin records view by view                   */
+  int32_t* rec_npairs;/* [cap_surv] number of tiles each record covers          */
 } S3RProjected;
 
 typedef struct S3RBins {
@@ -237,10 +233,11 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
 
 /*
  * s3r_sort -- builds per-tile contributor lists ordered by (depth bits,
- * Gaussian index), the blending order of Eq. (2), bit-exactly: per-tile pair
- * counts, exclusive scan, key emission, per-tile sort.  Reads the records and
- * block ranges of s3r_project_cull (only scene->n is read from `scene`);
- * `ws` holds s3r_workspace_size(S3R_WS_SORT) bytes.
+ * Gaussian index), the blending order of Eq. (2), bit-exactly: one (tile,
+ * record) pair per tile a record covers, keyed (tile << 32 | depth bits) in
+ * record order, then a stable radix sort on the key.  Reads the records of
+ * s3r_project_cull (only scene->n is read from `scene`); `ws` holds
+ * s3r_workspace_size(S3R_WS_SORT) bytes.
  */
 int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* views,
              const S3RParams* params, S3RBins* bins, void* ws, size_t ws_bytes, void* stream);

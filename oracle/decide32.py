@@ -216,9 +216,9 @@ def project_cull32(scene, W34, Kv, wh, tau, params, plain=False, view_index=0):
                 # p(depth); the draw is the counter-based generator of `rng`
                 from . import rng
                 p = lod_drop_probability32(pz, params["lod_pmax"], params["lod_D"])
-                u = rng.uniform(np.arange(N), view_index, params.get("step", 0),
-                                params.get("seed", 0))
-                drop = drop & (u < p)
+                draw = rng.uniform(np.arange(N), view_index, params.get("step", 0),
+                                   params.get("seed", 0))
+                drop = drop & (draw < p)
             keep = ~drop
         else:
             keep = np.ones(N, bool)

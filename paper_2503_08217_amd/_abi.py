@@ -20,7 +20,6 @@ S3R_WS_PROJECT, S3R_WS_SORT, S3R_WS_BACKWARD = 0, 1, 2
 CNT_SURV, CNT_OVF_SURV, CNT_DUP, CNT_OVF_DUP, CNT_SPIN = 0, 1, 2, 3, 4
 
 P = C.c_void_p
-PROJECT_BLOCK = 256
 
 
 class S3RParams(C.Structure):
@@ -49,7 +48,7 @@ class S3RViews(C.Structure):
 class S3RProjected(C.Structure):
     _fields_ = [("cam", P), ("cen", P), ("t_norm", P), ("mask", P), ("rec_gid", P),
                 ("rec_view", P), ("rec_geo", P), ("rec_conic", P), ("rec_rgb", P),
-                ("rec_rect", P), ("counters", P), ("stats", P), ("blocks", P)]
+                ("rec_rect", P), ("counters", P), ("stats", P), ("rec_npairs", P)]
 
 
 class S3RBins(C.Structure):

@@ -1,4 +1,6 @@
 // extern "C" entry points: argument validation, workspace carving, launches.
+#include <algorithm>
+
 #include "internal.hpp"
 
 using namespace s3r;
@@ -23,14 +25,17 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
   } while (0)
 
 struct WsProject {
-  uint64_t* flags;
+  uint32_t* surv;
+  int32_t* bstat;
 };
 struct WsSort {
   uint64_t* keys;
   uint64_t* keys_alt;
-  int32_t* cursor;
-  uint64_t* scan_flags;
-  int32_t* big;
+  uint32_t* vals;
+  int32_t* pair_off;
+  int32_t* hist;
+  int32_t* sums;
+  int32_t* misc;
 };
 struct WsBwd {
   float4* g2d;
@@ -39,9 +44,12 @@ struct WsBwd {
 
 size_t ws_project(const S3RSizes& z, WsProject* w, char* base) {
   const int nblk = project_blocks(z.n);
+  const size_t words = (size_t)((z.n + 63) / 64) * 2;
   size_t off = 0;
-  if (w) w->flags = reinterpret_cast<uint64_t*>(base + off);
-  off += align_up((size_t)nblk * 8 + 8);
+  if (w) w->surv = reinterpret_cast<uint32_t*>(base + off);
+  off += align_up(words * z.n_views * 4 + 8);
+  if (w) w->bstat = reinterpret_cast<int32_t*>(base + off);
+  off += align_up((size_t)nblk * z.n_views * 16 + 16);
   return off;
 }
 
@@ -51,12 +59,18 @@ size_t ws_sort(const S3RSizes& z, WsSort* w, char* base) {
   off += align_up((size_t)z.cap_dup * 8);
   if (w) w->keys_alt = reinterpret_cast<uint64_t*>(base + off);
   off += align_up((size_t)z.cap_dup * 8);
-  if (w) w->cursor = reinterpret_cast<int32_t*>(base + off);
-  off += align_up((size_t)z.total_tiles * 4 + 4);
-  if (w) w->scan_flags = reinterpret_cast<uint64_t*>(base + off);
-  off += align_up((size_t)scan_blocks(z.total_tiles) * 8 + 8);
-  if (w) w->big = reinterpret_cast<int32_t*>(base + off);
-  off += align_up(sort_big_words(z.total_tiles) * 4);
+  if (w) w->vals = reinterpret_cast<uint32_t*>(base + off);
+  off += align_up((size_t)z.cap_dup * 4);
+  if (w) w->pair_off = reinterpret_cast<int32_t*>(base + off);
+  off += align_up((size_t)z.cap_surv * 4 + 4);
+  const size_t hw = sort_hist_words(z.cap_dup);
+  if (w) w->hist = reinterpret_cast<int32_t*>(base + off);
+  off += align_up(hw * 4 + 4);
+  const int64_t sb = std::max<int64_t>(scan_blocks(z.cap_surv), scan_blocks((int64_t)hw));
+  if (w) w->sums = reinterpret_cast<int32_t*>(base + off);
+  off += align_up((size_t)sb * 4 + 4);
+  if (w) w->misc = reinterpret_cast<int32_t*>(base + off);
+  off += align_up(64);
   return off;
 }
 
@@ -208,7 +222,7 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
   S3R_REQUIRE(out->rec_rect);
   S3R_REQUIRE(out->counters);
   S3R_REQUIRE(out->stats);
-  S3R_REQUIRE(out->blocks);
+  S3R_REQUIRE(out->rec_npairs);
   const S3RSizes z = sizes_of(scene, views, params);
   if (!ws && ws_bytes) return S3R_E_NULL;
   if (ws_bytes < ws_project(z, nullptr, nullptr) || !ws) return S3R_E_WORKSPACE;
@@ -218,8 +232,8 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
   const hipStream_t st = as_stream(stream);
   const int nblk = project_blocks(scene->n);
 
-  S3R_HIP(launch_zero(out->counters, 64, w.flags, (size_t)nblk * 8, out->stats,
-                      (size_t)views->n_views * 16, nullptr, 0, st));
+  S3R_HIP(launch_zero(out->counters, 64, out->stats, (size_t)views->n_views * 16, nullptr, 0,
+                      nullptr, 0, st));
   S3R_HIP(launch_compose(views->W, views->tstep, scene->pose, scene->n_slots, scene->n_timesteps,
                          views->n_views, out->cam, out->cen, out->t_norm, st));
   ProjArgs a{};
@@ -255,9 +269,10 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
   a.rec_conic = reinterpret_cast<float4*>(out->rec_conic);
   a.rec_rgb = reinterpret_cast<float4*>(out->rec_rgb);
   a.rec_rect = reinterpret_cast<int4*>(out->rec_rect);
+  a.rec_npairs = out->rec_npairs;
   a.counters = out->counters;
-  a.bstat = out->blocks;
-  a.flags = w.flags;
+  a.surv = w.surv;
+  a.bstat = w.bstat;
   a.nblk = nblk;
   a.kp = kparams(*params);
   S3R_HIP(launch_project(a, out->stats, st));
@@ -275,7 +290,8 @@ int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* vi
   S3R_REQUIRE(proj->rec_rect);
   S3R_REQUIRE(proj->counters);
   S3R_REQUIRE(proj->stats);
-  S3R_REQUIRE(proj->blocks);
+  S3R_REQUIRE(proj->rec_view);
+  S3R_REQUIRE(proj->rec_npairs);
   S3R_REQUIRE(bins->tile_count);
   S3R_REQUIRE(bins->tile_start);
   S3R_REQUIRE(bins->vals);
@@ -287,8 +303,8 @@ int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* vi
   SortArgs a{};
   a.rec_rect = reinterpret_cast<const int4*>(proj->rec_rect);
   a.rec_geo = reinterpret_cast<const float4*>(proj->rec_geo);
-  a.blocks = proj->blocks;
-  a.nblk = project_blocks(scene->n);
+  a.rec_view = proj->rec_view;
+  a.rec_npairs = proj->rec_npairs;
   a.nv = views->n_views;
   a.total_tiles = views->total_tiles;
   a.tile = params->tile;
@@ -298,12 +314,16 @@ int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* vi
   a.stats = proj->stats;
   a.tile_count = bins->tile_count;
   a.tile_start = bins->tile_start;
-  a.vals = bins->vals;
+  a.pair_off = w.pair_off;
   a.keys = w.keys;
   a.keys_alt = w.keys_alt;
-  a.cursor = w.cursor;
-  a.scan_flags = w.scan_flags;
-  a.big = w.big;
+  // the last radix pass must write the caller's value array
+  const bool odd = (radix_passes(views->total_tiles) & 1) != 0;
+  a.vals0 = odd ? w.vals : bins->vals;
+  a.vals1 = odd ? bins->vals : w.vals;
+  a.hist = w.hist;
+  a.scan_sums = w.sums;
+  a.misc = w.misc;
   a.cap_dup = params->cap_dup;
   a.cap_surv = params->cap_surv;
   S3R_HIP(launch_sort(a, as_stream(stream)));

@@ -8,10 +8,9 @@ namespace s3r {
 
 // kernels timed by the opt-in profiler (names in profile.hip)
 enum KernelId {
-  K_COMPOSE, K_PLAIN_TRANSFORM, K_PROJECT, K_STATS, K_BIN_COUNT, K_SCAN_TILES, K_DUP_STATS,
-  K_BIN_EMIT, K_TILE_SORT, K_BIG_PREFIX, K_BIG_CHUNKS, K_BIG_MERGE, K_BIG_FINAL, K_RASTER_FWD,
-  K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PROJECT_BWD, K_POSE_BWD, K_POSE6, K_PLAIN_TRANSFORM_BWD,
-  K_VISIBILITY, K_ZERO, K_COUNT
+  K_COMPOSE, K_PLAIN_TRANSFORM, K_PROJECT, K_STATS, K_RECORDS, K_SCAN, K_EMIT, K_RADIX,
+  K_TILE_RANGES, K_DUP_STATS, K_RASTER_FWD, K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PROJECT_BWD,
+  K_POSE_BWD, K_POSE6, K_PLAIN_TRANSFORM_BWD, K_VISIBILITY, K_ZERO, K_COUNT
 };
 void prof_begin(int id, hipStream_t st);
 void prof_end(int id, hipStream_t st);
@@ -49,6 +48,7 @@ struct ProjArgs {
   const float* t_norm;
   // outputs
   uint32_t* mask;
+  uint32_t* surv;  // survivor bits, same layout as mask (workspace)
   int64_t mask_words;
   int32_t* rec_gid;
   int32_t* rec_view;
@@ -56,8 +56,9 @@ struct ProjArgs {
   float4* rec_conic;
   float4* rec_rgb;
   int4* rec_rect;
+  int32_t* rec_npairs;
   int32_t* counters;
-  // per (block, view): N_t, N_f, N_r, first record
+  // per (block, view): N_t, N_f, N_r, first record (workspace)
   int32_t* bstat;
   // workspace
   uint64_t* flags;
@@ -157,24 +158,28 @@ int scan_blocks(int64_t n);
 struct SortArgs {
   const int4* rec_rect;
   const float4* rec_geo;
-  const int32_t* blocks;  // [nblk][nv][4]
-  int nblk, nv, total_tiles, tile;
+  const int32_t* rec_view;
+  const int32_t* rec_npairs;
+  int nv, total_tiles, tile;
   const int32_t* tile_offset;
   const int32_t* wh;
   int32_t* counters;
   int32_t* stats;
   int32_t* tile_count;
   int32_t* tile_start;
-  uint32_t* vals;
   // workspace
-  uint64_t* keys;
-  uint64_t* keys_alt;
-  int32_t* cursor;
-  uint64_t* scan_flags;
-  int32_t* big;  // [total_tiles + 1] big-tile list, [total_tiles+2] chunk offsets, misc
+  int32_t* pair_off;   // [cap_surv]
+  uint64_t* keys;      // [cap_dup]
+  uint64_t* keys_alt;  // [cap_dup]
+  uint32_t* vals0;     // [cap_dup]: emitted values; vals1 receives the last pass
+  uint32_t* vals1;
+  int32_t* hist;       // [256 * scan_blocks(cap_dup)]
+  int32_t* scan_sums;
+  int32_t* misc;       // [0] total pairs, [1] histogram total
   int64_t cap_dup, cap_surv;
 };
-size_t sort_big_words(int total_tiles);
+int radix_passes(int total_tiles);
+size_t sort_hist_words(int64_t cap_dup);
 hipError_t launch_sort(const SortArgs& a, hipStream_t st);
 
 // raster.hip

@@ -8,11 +8,10 @@
 namespace s3r {
 
 static const char* kNames[K_COUNT] = {
-    "compose",     "plain_transform", "project",   "stats",        "bin_count",
-    "scan_tiles",  "dup_stats",       "bin_emit",  "tile_sort",    "big_prefix",
-    "big_chunks",  "big_merge",       "big_final", "raster_fwd",   "l1_loss",
-    "zero_g2d",    "raster_bwd",      "project_bwd", "pose_bwd",   "pose6",
-    "plain_transform_bwd", "visibility", "zero"};
+    "compose",    "plain_transform", "project",    "block_offsets", "records",
+    "scan",       "emit_pairs",      "radix",      "tile_ranges",   "dup_stats",
+    "raster_fwd", "l1_loss",         "zero_g2d",   "raster_bwd",    "project_bwd",
+    "pose_bwd",   "pose6",           "plain_transform_bwd", "visibility", "zero"};
 
 namespace {
 struct Pending {

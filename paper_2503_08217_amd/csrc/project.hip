@@ -2,13 +2,18 @@
 // selection, projection (Eq. 1), frustum mask M_t, LOD cull, SH colour of the
 // survivors, and compaction of the survivors into records.
 //
-// k_project is a single pass over the Gaussians.  Each workgroup owns 256
-// consecutive Gaussians (in the order it took its ticket) and loops over the
-// views of the batch, so a Gaussian's 44 bytes of geometry are read once per
-// batch however many views there are.  Survivors are compacted with wave
-// ballots and a decoupled look-back across workgroups, which gives every
-// record a deterministic slot (Gaussian block, then view, then Gaussian) in
-// one pass with no second read of the Gaussians.
+// Three kernels, none of which waits on another workgroup or uses a
+// contended atomic:
+//   k_cull           each workgroup owns 256 consecutive Gaussians and loops
+//                    over the batch's views (a Gaussian's 44 bytes of geometry
+//                    are read once per batch); decisions become M_t bits and
+//                    survivor bits through wave ballots, plus per-(block,
+//                    view) counts
+//   k_block_offsets  one workgroup scans the counts into the first record of
+//                    every (block, view)
+//   k_records        survivors (only) re-project, query their colour and write
+//                    their record at base + rank within the block
+// Records come out ordered by Gaussian block, then view, then Gaussian.
 #include "internal.hpp"
 
 namespace s3r {
@@ -121,6 +126,23 @@ __device__ __forceinline__ void load_camera(const float* __restrict__ cam, int v
   P[8] = c.x; P[9] = c.y; P[10] = c.z; P[11] = c.w;
 }
 
+__device__ __forceinline__ void load_gaussian(const ProjArgs& a, int i, bool need, bool plain,
+                                              Loaded& g) {
+  g.mx = g.my = g.mz = 0.f;
+  g.s0 = g.s1 = g.s2 = 0.f;
+  g.k = 0;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) g.R[t] = 0.f;
+  if (!need) return;
+  g.mx = a.mean[3 * i]; g.my = a.mean[3 * i + 1]; g.mz = a.mean[3 * i + 2];
+  g.s0 = a.scale[3 * i]; g.s1 = a.scale[3 * i + 1]; g.s2 = a.scale[3 * i + 2];
+  g.k = clampi(a.inst[i], 0, a.n_slots - 1);
+  if (!plain) {
+    const float4 q = reinterpret_cast<const float4*>(a.quat)[i];
+    quat_rot(q.x, q.y, q.z, q.w, g.R);
+  }
+}
+
 __device__ __forceinline__ void view_geometry(const ProjArgs& a, int v, const Loaded& g,
                                               bool plain, int i, Loaded& eff, float P[12],
                                               float& fx, float& fy, float& cx, float& cy, int& W,
@@ -143,20 +165,14 @@ __device__ __forceinline__ void view_geometry(const ProjArgs& a, int v, const Lo
   }
 }
 
-__global__ __launch_bounds__(kProjBlock) void k_project(ProjArgs a) {
-  __shared__ int s_vb;
-  __shared__ uint64_t s_ball[kMaxViews][kProjWaves];
-  __shared__ int s_ct[kMaxViews][kProjWaves];
-  __shared__ int s_cf[kMaxViews][kProjWaves];
-  __shared__ uint32_t s_off[kMaxViews][kProjWaves];
-  __shared__ uint32_t s_excl;
-
+// Phase A: decisions of every (view, Gaussian) of the block.  Writes the M_t
+// bits, the survivor bits and the block's per-view counts (N_t, N_f, N_r).
+__global__ __launch_bounds__(kProjBlock) void k_cull(ProjArgs a) {
+  __shared__ int s_cnt[kMaxViews][kProjWaves][3];
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const int lane = tid % kWave;
-  if (tid == 0) s_vb = atomicAdd(&a.counters[S3R_CNT_TICKET], 1);
-  __syncthreads();
-  const int vb = s_vb;
+  const int vb = blockIdx.x;
   const int i = vb * kProjBlock + tid;
   const bool valid = i < a.n;
   const bool plain = (a.kp.flags & S3R_PLAIN) != 0;
@@ -178,22 +194,8 @@ __global__ __launch_bounds__(kProjBlock) void k_project(ProjArgs a) {
     }
   }
   Loaded g;
-  g.mx = g.my = g.mz = 0.f;
-  g.s0 = g.s1 = g.s2 = 0.f;
-  g.k = 0;
-#pragma unroll
-  for (int t = 0; t < 9; ++t) g.R[t] = 0.f;
-  if (pass_bits) {
-    g.mx = a.mean[3 * i]; g.my = a.mean[3 * i + 1]; g.mz = a.mean[3 * i + 2];
-    g.s0 = a.scale[3 * i]; g.s1 = a.scale[3 * i + 1]; g.s2 = a.scale[3 * i + 2];
-    g.k = clampi(a.inst[i], 0, a.n_slots - 1);
-    if (!plain) {
-      const float4 q = reinterpret_cast<const float4*>(a.quat)[i];
-      quat_rot(q.x, q.y, q.z, q.w, g.R);
-    }
-  }
+  load_gaussian(a, i, pass_bits != 0, plain, g);
 
-  // ---- phase A: decisions for every view ----
   for (int v = 0; v < a.nv; ++v) {
     const bool pass_t = (pass_bits >> v) & 1ull;
     bool vis = false, surv = false;
@@ -217,62 +219,122 @@ __global__ __launch_bounds__(kProjBlock) void k_project(ProjArgs a) {
         uint32_t* m = a.mask + (size_t)v * a.mask_words + 2 * (size_t)gw;
         m[0] = (uint32_t)bf;
         m[1] = (uint32_t)(bf >> 32);
+        uint32_t* sb = a.surv + (size_t)v * a.mask_words + 2 * (size_t)gw;
+        sb[0] = (uint32_t)bs;
+        sb[1] = (uint32_t)(bs >> 32);
       }
-      s_ball[v][wave] = bs;
-      s_ct[v][wave] = __popcll(bt);
-      s_cf[v][wave] = __popcll(bf);
+      s_cnt[v][wave][0] = __popcll(bt);
+      s_cnt[v][wave][1] = __popcll(bf);
+      s_cnt[v][wave][2] = __popcll(bs);
     }
   }
   __syncthreads();
+  for (int v = tid; v < a.nv; v += kProjBlock) {
+    int nt = 0, nf = 0, nr = 0;
+    for (int w = 0; w < kProjWaves; ++w) {
+      nt += s_cnt[v][w][0];
+      nf += s_cnt[v][w][1];
+      nr += s_cnt[v][w][2];
+    }
+    int32_t* bs = a.bstat + ((size_t)vb * a.nv + v) * 4;
+    bs[0] = nt; bs[1] = nf; bs[2] = nr;
+  }
+}
 
-  // ---- block aggregate, per-(view, wave) offsets, look-back ----
-  if (wave == 0) {
-    uint32_t agg_l = 0;
-    if (lane == 0) {
-      for (int v = 0; v < a.nv; ++v) {
-        int nt = 0, nf = 0, nr = 0;
-        for (int w = 0; w < kProjWaves; ++w) {
-          s_off[v][w] = agg_l;
-          const int c = __popcll(s_ball[v][w]);
-          agg_l += c;
-          nr += c;
-          nt += s_ct[v][w];
-          nf += s_cf[v][w];
-        }
-        int32_t* bs = a.bstat + ((size_t)vb * a.nv + v) * 4;
-        bs[0] = nt; bs[1] = nf; bs[2] = nr; bs[3] = (int32_t)s_off[v][0];
-      }
-      st_release(a.flags + vb, ((uint64_t)(vb == 0 ? 2u : 1u) << 32) | agg_l);
+// Exclusive scan of the per-(block, view) survivor counts in (block, view)
+// order -> first record of each (block, view); totals -> counters and stats.
+// One workgroup of 1024 threads, each owning a contiguous run of entries.
+__global__ __launch_bounds__(1024) void k_block_offsets(int32_t* __restrict__ bstat, int nblk,
+                                                        int nv, int32_t* __restrict__ counters,
+                                                        int32_t* __restrict__ stats,
+                                                        int64_t cap_surv) {
+  __shared__ uint32_t s_w[16];
+  __shared__ int s_stat[kMaxViews][3];
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  for (int q = tid; q < nv * 3; q += 1024) s_stat[q / 3][q % 3] = 0;
+  __syncthreads();
+  const int64_t total = (int64_t)nblk * nv;
+  const int64_t per = (total + 1023) / 1024;
+  const int64_t e0 = tid * per, e1 = min(total, e0 + per);
+  uint32_t sum = 0;
+  int acc[3] = {0, 0, 0};
+  int cur_v = -1;
+  for (int64_t e = e0; e < e1; ++e) {
+    const int32_t* bs = bstat + e * 4;
+    sum += (uint32_t)bs[2];
+    const int v = (int)(e % nv);
+    if (v != cur_v && cur_v >= 0) {
+      for (int q = 0; q < 3; ++q) atomicAdd(&s_stat[cur_v][q], acc[q]);
+      acc[0] = acc[1] = acc[2] = 0;
     }
-    const uint32_t agg = __shfl(agg_l, 0, kWave);
-    uint32_t excl = 0;
-    if (vb > 0) excl = lookback(a.flags, vb, a.counters + S3R_CNT_SPIN);
-    if (lane == 0) {
-      if (vb > 0) st_release(a.flags + vb, (2ull << 32) | (uint64_t)(excl + agg));
-      s_excl = excl;
-      if (vb == a.nblk - 1) {
-        const int64_t total = (int64_t)excl + agg;
-        a.counters[S3R_CNT_SURV] = (int32_t)(total < a.kp.cap_surv ? total : a.kp.cap_surv);
-        a.counters[S3R_CNT_OVF_SURV] =
-            (int32_t)(total > a.kp.cap_surv ? total - a.kp.cap_surv : 0);
-      }
-    }
+    cur_v = v;
+    acc[0] += bs[0]; acc[1] += bs[1]; acc[2] += bs[2];
+  }
+  if (cur_v >= 0)
+    for (int q = 0; q < 3; ++q) atomicAdd(&s_stat[cur_v][q], acc[q]);
+  // block-wide exclusive scan of the per-thread sums
+  uint32_t incl = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += t;
+  }
+  if (lane == kWave - 1) s_w[wave] = incl;
+  __syncthreads();
+  uint32_t run = incl - sum;
+  for (int w = 0; w < wave; ++w) run += s_w[w];
+  for (int64_t e = e0; e < e1; ++e) {
+    int32_t* bs = bstat + e * 4;
+    const int64_t st = run;
+    bs[3] = (int32_t)(st < cap_surv ? st : cap_surv);
+    run += (uint32_t)bs[2];
   }
   __syncthreads();
-  const uint32_t excl = s_excl;
-  // record range of every view of this block: [excl + s_off[v][0], + count)
-  if (tid < a.nv) {
-    int32_t* bs = a.bstat + ((size_t)vb * a.nv + tid) * 4;
-    const int64_t st = (int64_t)excl + bs[3];
-    bs[3] = (int32_t)(st < a.kp.cap_surv ? st : a.kp.cap_surv);
+  if (tid == 0) {
+    int64_t tot = 0;
+    for (int w = 0; w < 16; ++w) tot += s_w[w];
+    counters[S3R_CNT_SURV] = (int32_t)(tot < cap_surv ? tot : cap_surv);
+    counters[S3R_CNT_OVF_SURV] = (int32_t)(tot > cap_surv ? tot - cap_surv : 0);
   }
+  for (int q = tid; q < nv * 3; q += 1024) stats[(q / 3) * 4 + (q % 3)] = s_stat[q / 3][q % 3];
+}
 
-  // ---- phase C: records of the survivors ----
+// Phase C: records of the survivors, at the slots given by the block offsets.
+__global__ __launch_bounds__(kProjBlock) void k_records(ProjArgs a) {
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int vb = blockIdx.x;
+  const int i = vb * kProjBlock + tid;
+  const bool plain = (a.kp.flags & S3R_PLAIN) != 0;
+  // survivor words of this block's waves, all views
+  uint64_t any = 0;
+  for (int v = 0; v < a.nv; ++v) {
+    const int gw = vb * kProjWaves + wave;
+    if ((int64_t)gw * kWave < a.n) {
+      const uint32_t* sb = a.surv + (size_t)v * a.mask_words + 2 * (size_t)gw;
+      any |= (((uint64_t)sb[1] << 32) | sb[0]);
+    }
+  }
+  if (!((any >> lane) & 1ull)) return;
+  Loaded g;
+  load_gaussian(a, i, true, plain, g);
   const int B = (a.sh_deg + 1) * (a.sh_deg + 1);
   for (int v = 0; v < a.nv; ++v) {
-    const uint64_t bs = s_ball[v][wave];
-    if (!((bs >> lane) & 1ull)) continue;
-    const int64_t slot = (int64_t)excl + s_off[v][wave] + lane_rank(bs);
+    const int4 info = reinterpret_cast<const int4*>(a.bstat)[(size_t)vb * a.nv + v];
+    // survivors of this view in earlier waves of the block, and in this wave
+    int before = 0;
+    uint64_t mine = 0;
+    for (int w = 0; w <= wave; ++w) {
+      const int gw = vb * kProjWaves + w;
+      if ((int64_t)gw * kWave >= a.n) break;
+      const uint32_t* sb = a.surv + (size_t)v * a.mask_words + 2 * (size_t)gw;
+      const uint64_t word = ((uint64_t)sb[1] << 32) | sb[0];
+      if (w < wave) before += __popcll(word);
+      else mine = word;
+    }
+    if (!((mine >> lane) & 1ull)) continue;
+    const int64_t slot = (int64_t)info.w + before + lane_rank(mine);
     if (slot >= a.kp.cap_surv) continue;
     Loaded e;
     float P[12], fx, fy, cx, cy;
@@ -316,29 +378,7 @@ __global__ __launch_bounds__(kProjBlock) void k_project(ProjArgs a) {
     a.rec_conic[slot] = make_float4(o.c / o.det, (-o.b) / o.det, o.a / o.det, 0.f);
     a.rec_rgb[slot] = make_float4(r, gg, bb, 0.f);
     a.rec_rect[slot] = make_int4(o.x0, o.y0, o.x1, o.y1);
-  }
-}
-
-// per-view totals of the per-block statistics
-__global__ __launch_bounds__(256) void k_stats(const int32_t* __restrict__ bstat, int nblk, int nv,
-                                               int32_t* __restrict__ stats) {
-  const int v = blockIdx.x;
-  __shared__ int s[3][4];
-  int acc[3] = {0, 0, 0};
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-    const int32_t* p = bstat + ((size_t)b * nv + v) * 4;
-    acc[0] += p[0]; acc[1] += p[1]; acc[2] += p[2];
-  }
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  for (int q = 0; q < 3; ++q) {
-    uint32_t t = wave_sum_u32((uint32_t)acc[q]);
-    if (lane == 0) s[q][wave] = (int)t;
-  }
-  __syncthreads();
-  if (threadIdx.x < 3) {
-    int t = 0;
-    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += s[threadIdx.x][w];
-    stats[v * 4 + threadIdx.x] = t;
+    a.rec_npairs[slot] = (o.x1 - o.x0) * (o.y1 - o.y0);
   }
 }
 
@@ -367,8 +407,10 @@ hipError_t launch_plain_transform(const float* mean, const float* quat, const in
 int project_blocks(int64_t n) { return (int)((n + kProjBlock - 1) / kProjBlock); }
 
 hipError_t launch_project(const ProjArgs& a, int32_t* stats, hipStream_t st) {
-  if (a.nblk > 0) S3R_LAUNCH(K_PROJECT, k_project, dim3(a.nblk), dim3(kProjBlock), 0, st, a);
-  S3R_LAUNCH(K_STATS, k_stats, dim3(a.nv), dim3(256), 0, st, a.bstat, a.nblk, a.nv, stats);
+  if (a.nblk > 0) S3R_LAUNCH(K_PROJECT, k_cull, dim3(a.nblk), dim3(kProjBlock), 0, st, a);
+  S3R_LAUNCH(K_STATS, k_block_offsets, dim3(1), dim3(1024), 0, st, a.bstat, a.nblk, a.nv,
+             a.counters, stats, a.kp.cap_surv);
+  if (a.nblk > 0) S3R_LAUNCH(K_RECORDS, k_records, dim3(a.nblk), dim3(kProjBlock), 0, st, a);
   return hipGetLastError();
 }
 

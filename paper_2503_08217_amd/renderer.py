@@ -143,8 +143,7 @@ class Renderer:
         self.rec_rect = torch.zeros(cs, 4, device=d, dtype=i32)
         self.counters = torch.zeros(16, device=d, dtype=i32)
         self.stats = torch.zeros(V, 4, device=d, dtype=i32)
-        nblk = (n + A.PROJECT_BLOCK - 1) // A.PROJECT_BLOCK
-        self.blocks = torch.zeros(max(1, nblk) * V * 4, device=d, dtype=i32)
+        self.rec_npairs = torch.zeros(cs, device=d, dtype=i32)
         self.tile_count = torch.zeros(self.total_tiles, device=d, dtype=i32)
         self.tile_start = torch.zeros(self.total_tiles + 1, device=d, dtype=i32)
         self.vals = torch.zeros(cd, device=d, dtype=i32)
@@ -192,7 +191,7 @@ class Renderer:
         self.c_proj = A.S3RProjected(
             _ptr(self.cam), _ptr(self.cen), _ptr(self.t_norm), _ptr(self.mask), _ptr(self.rec_gid),
             _ptr(self.rec_view), _ptr(self.rec_geo), _ptr(self.rec_conic), _ptr(self.rec_rgb),
-            _ptr(self.rec_rect), _ptr(self.counters), _ptr(self.stats), _ptr(self.blocks))
+            _ptr(self.rec_rect), _ptr(self.counters), _ptr(self.stats), _ptr(self.rec_npairs))
         self.c_bins = A.S3RBins(_ptr(self.tile_count), _ptr(self.tile_start), _ptr(self.vals))
         self.c_img = A.S3RImage(_ptr(self.color), _ptr(self.T_final), _ptr(self.last))
         self.c_grads = A.S3RGrads(

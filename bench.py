@@ -212,6 +212,7 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tile", type=int, default=16, choices=(8, 16, 32))
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported here "
@@ -224,8 +225,9 @@ def main():
 
     t_gen = time.perf_counter()
     cfg = scenes.make_config(a.config)
+    cfg.params["tile"] = a.tile
     log(f"config {a.config} ({cfg.name}) generated in {time.perf_counter() - t_gen:.1f}s, "
-        f"N={cfg.scene.n}")
+        f"N={cfg.scene.n}, tile {a.tile}")
     tg_np = scenes.targets(a.config, cfg.views, cfg.timed_views)
     targets = [torch.as_tensor(t.ravel()).cuda().contiguous() for t in tg_np]
 

@@ -7,8 +7,10 @@
 //   dL/dc_i     = alpha_i T_i dL/dC
 //   dL/dalpha_i = T_i c_i . dL/dC - (S_i + T_N bg) . dL/dC / (1 - alpha_i)
 // and alpha_i = min(alpha_max, o_i exp(power_i)) chains to the 2D mean, the
-// conic and the opacity.  Per-record gradients are summed over the wave's 64
-// pixels before one set of atomics per wave.
+// conic and the opacity.  A lane owns four pixels of a 16x16 tile (the tile is
+// one wave64); a record's gradient is summed over the lane's pixels, then over
+// the wave with DPP row operations, and added to the record with one set of
+// global atomics per tile.
 //
 // k_project_bwd chains those 2D gradients through the conic inverse, the EWA
 // covariance J R Sigma R^T J^T (Eq. 1), the quaternion/scale parameterisation,
@@ -23,14 +25,15 @@ namespace s3r {
 // raster backward
 // ---------------------------------------------------------------------------
 template <int TS>
-__global__ __launch_bounds__(TS* TS) void k_raster_bwd(BwdArgs a) {
-  constexpr int NT = TS * TS;
+__global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
+  using Sh = RasterShape<TS>;
+  constexpr int NT = Sh::NT, PPT = Sh::PPT, ROWS = Sh::ROWS;
   constexpr int NW = NT / kWave > 0 ? NT / kWave : 1;
-  __shared__ float2 s_uv[NT];
+  __shared__ float4 s_geo[NT];
   __shared__ float4 s_con[NT];
   __shared__ float4 s_rgb[NT];
   __shared__ uint32_t s_rec[NT];
-  __shared__ float s_g[NT][9];
+  __shared__ float s_g[NW > 1 ? NT : 1][9];
   __shared__ int s_max[NW];
   const int tid = threadIdx.x;
   const int lane = tid % kWave, wave = tid / kWave;
@@ -40,29 +43,35 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(BwdArgs a) {
   const int W = a.wh[2 * v], H = a.wh[2 * v + 1];
   const int gx = (W + TS - 1) / TS;
   const int px = (lt % gx) * TS + tid % TS;
-  const int py = (lt / gx) * TS + tid / TS;
-  const bool inside = (px < W) && (py < H);
-  const float fxp = (float)px, fyp = (float)py;
+  const int py0 = (lt / gx) * TS + tid / TS;
+  const float fxp = (float)px;
   const int64_t s = a.tile_start[t];
   const int64_t e = min((int64_t)a.tile_start[t + 1], a.kp.cap_dup);
+  const int64_t npx = (int64_t)W * H;
+  const int64_t base = 3 * a.px_offset[v];
 
-  float T = 1.f, dCr = 0.f, dCg = 0.f, dCb = 0.f;
-  int last = 0;
-  if (inside) {
-    const int64_t npx = (int64_t)W * H;
-    const int64_t p = (int64_t)py * W + px;
-    const int64_t base = 3 * a.px_offset[v];
-    T = a.T_final[a.px_offset[v] + p];
-    last = a.last[a.px_offset[v] + p];
-    dCr = a.d_color[base + p];
-    dCg = a.d_color[base + npx + p];
-    dCb = a.d_color[base + 2 * npx + p];
+  float T[PPT], dCr[PPT], dCg[PPT], dCb[PPT], bgdot[PPT], Sr[PPT], Sg[PPT], Sb[PPT];
+  int last[PPT];
+  int m = 0;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int py = py0 + k * ROWS;
+    T[k] = 1.f;
+    dCr[k] = dCg[k] = dCb[k] = 0.f;
+    last[k] = 0;
+    Sr[k] = Sg[k] = Sb[k] = 0.f;
+    if (px < W && py < H) {
+      const int64_t p = (int64_t)py * W + px;
+      T[k] = a.T_final[a.px_offset[v] + p];
+      last[k] = a.last[a.px_offset[v] + p];
+      dCr[k] = a.d_color[base + p];
+      dCg[k] = a.d_color[base + npx + p];
+      dCb[k] = a.d_color[base + 2 * npx + p];
+    }
+    bgdot[k] = T[k] * (a.kp.bg0 * dCr[k] + a.kp.bg1 * dCg[k] + a.kp.bg2 * dCb[k]);
+    m = max(m, last[k]);
   }
-  const float bgdot = T * (a.kp.bg0 * dCr + a.kp.bg1 * dCg + a.kp.bg2 * dCb);
-  float Sr = 0.f, Sg = 0.f, Sb = 0.f;
-
   // number of list entries any pixel of the tile needs
-  int m = last;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
   if (lane == 0) s_max[wave] = m;
@@ -77,58 +86,54 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(BwdArgs a) {
     const int64_t idx = b0 + tid;
     if (idx < b_end) {
       const uint32_t r = a.vals[idx];
-      const float4 g = a.rec_geo[r];
-      const float4 c = a.rec_conic[r];
-      s_uv[tid] = make_float2(g.x, g.y);
-      s_con[tid] = make_float4(c.x, c.y, c.z, g.z);
+      s_geo[tid] = a.rec_geo[r];
+      s_con[tid] = a.rec_conic[r];
       s_rgb[tid] = a.rec_rgb[r];
       s_rec[tid] = r;
     }
+    if (NW > 1) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) s_g[tid][q] = 0.f;
+      for (int q = 0; q < 9; ++q) s_g[tid][q] = 0.f;
+    }
     __syncthreads();
     for (int j = (int)(b_end - b0) - 1; j >= 0; --j) {
       const int pos = (int)(b0 - s) + j;
+      const float4 g = s_geo[j];
+      const float4 c = s_con[j];
+      const float4 col = s_rgb[j];
       float g_u = 0.f, g_v = 0.f, g_A = 0.f, g_B = 0.f, g_C = 0.f, g_o = 0.f;
       float g_r = 0.f, g_g = 0.f, g_b = 0.f;
       bool contrib = false;
-      if (pos < last) {
-        const float2 uv = s_uv[j];
-        const float4 con = s_con[j];
-        const float dx = uv.x - fxp;
-        const float dy = uv.y - fyp;
-        const float power =
-            fmaf(-0.5f, fmaf(con.x * dx, dx, con.z * dy * dy), -con.y * dx * dy);
-        if (!(-power > a.kp.cutoff)) {
-          const float ex = __expf(power);
-          const float raw = con.w * ex;
-          const float alpha = fminf(a.kp.alpha_max, raw);
-          if (!(alpha < a.kp.alpha_min)) {
-            contrib = true;
-            const float one_m = 1.0f - alpha;
-            const float Tb = T / one_m;
-            const float wgt = alpha * Tb;
-            const float4 col = s_rgb[j];
-            g_r = wgt * dCr;
-            g_g = wgt * dCg;
-            g_b = wgt * dCb;
-            const float cdot = col.x * dCr + col.y * dCg + col.z * dCb;
-            const float sdot = Sr * dCr + Sg * dCg + Sb * dCb;
-            const float dal = Tb * cdot - (sdot + bgdot) / one_m;
-            Sr = fmaf(col.x, wgt, Sr);
-            Sg = fmaf(col.y, wgt, Sg);
-            Sb = fmaf(col.z, wgt, Sb);
-            T = Tb;
-            if (raw <= a.kp.alpha_max) {
-              const float dpow = dal * alpha;
-              g_o = dal * ex;
-              g_u = -dpow * (con.x * dx + con.y * dy);
-              g_v = -dpow * (con.z * dy + con.y * dx);
-              g_A = -0.5f * dpow * dx * dx;
-              g_B = -dpow * dx * dy;
-              g_C = -0.5f * dpow * dy * dy;
-            }
-          }
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        if (pos >= last[k]) continue;
+        const float py = (float)(py0 + k * ROWS);
+        const Blend bl = blend_eval(g.x, g.y, c.x, c.y, c.z, g.z, fxp, py, a.kp);
+        if (!bl.hit) continue;
+        contrib = true;
+        const float one_m = 1.0f - bl.alpha;
+        const float Tb = T[k] / one_m;
+        const float wgt = bl.alpha * Tb;
+        g_r = fmaf(wgt, dCr[k], g_r);
+        g_g = fmaf(wgt, dCg[k], g_g);
+        g_b = fmaf(wgt, dCb[k], g_b);
+        const float cdot = col.x * dCr[k] + col.y * dCg[k] + col.z * dCb[k];
+        const float sdot = Sr[k] * dCr[k] + Sg[k] * dCg[k] + Sb[k] * dCb[k];
+        const float dal = Tb * cdot - (sdot + bgdot[k]) / one_m;
+        Sr[k] = fmaf(col.x, wgt, Sr[k]);
+        Sg[k] = fmaf(col.y, wgt, Sg[k]);
+        Sb[k] = fmaf(col.z, wgt, Sb[k]);
+        T[k] = Tb;
+        if (bl.raw <= a.kp.alpha_max) {
+          const float dx = g.x - fxp;
+          const float dy = g.y - py;
+          const float dpow = dal * bl.alpha;
+          g_o = fmaf(dal, bl.ex, g_o);
+          g_u -= dpow * (c.x * dx + c.y * dy);
+          g_v -= dpow * (c.z * dy + c.y * dx);
+          g_A -= 0.5f * dpow * dx * dx;
+          g_B -= dpow * dx * dy;
+          g_C -= 0.5f * dpow * dy * dy;
         }
       }
       if (ballot(contrib) != 0ull) {
@@ -136,25 +141,27 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(BwdArgs a) {
         g_B = wave_sum_dpp(g_B); g_C = wave_sum_dpp(g_C); g_o = wave_sum_dpp(g_o);
         g_r = wave_sum_dpp(g_r); g_g = wave_sum_dpp(g_g); g_b = wave_sum_dpp(g_b);
         if (lane == kWave - 1) {
-          float* G = s_g[j];
+          float* G = (NW > 1) ? s_g[j] : reinterpret_cast<float*>(a.g2d + 3 * (size_t)s_rec[j]);
           atomicAdd(G + 0, g_u); atomicAdd(G + 1, g_v); atomicAdd(G + 2, g_A);
           atomicAdd(G + 3, g_B); atomicAdd(G + 4, g_C); atomicAdd(G + 5, g_o);
           atomicAdd(G + 6, g_r); atomicAdd(G + 7, g_g); atomicAdd(G + 8, g_b);
         }
       }
     }
-    __syncthreads();
-    // one set of global atomics per record and tile
-    if (idx < b_end) {
-      const float* G = s_g[tid];
-      bool any = false;
+    if (NW > 1) {
+      __syncthreads();
+      // one set of global atomics per record and tile
+      if (idx < b_end) {
+        const float* G = s_g[tid];
+        bool any = false;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) any |= (G[q] != 0.f);
-      if (any) {
-        float* D = reinterpret_cast<float*>(a.g2d + 3 * (size_t)s_rec[tid]);
+        for (int q = 0; q < 9; ++q) any |= (G[q] != 0.f);
+        if (any) {
+          float* D = reinterpret_cast<float*>(a.g2d + 3 * (size_t)s_rec[tid]);
 #pragma unroll
-        for (int q = 0; q < 9; ++q)
-          if (G[q] != 0.f) atomicAdd(D + q, G[q]);
+          for (int q = 0; q < 9; ++q)
+            if (G[q] != 0.f) atomicAdd(D + q, G[q]);
+        }
       }
     }
   }
@@ -396,23 +403,43 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
       const float dir[3] = {dl[0] / nrm, dl[1] / nrm, dl[2] / nrm};
       float Y[16];
       sh_basis(a.sh_deg, dir[0], dir[1], dir[2], Y);
-      const float* f = a.sh + (size_t)i * B * 3;
+      float f[48];
+      load_sh(a.sh + (size_t)i * B * 3, B, f);
       float raw[3] = {0.5f, 0.5f, 0.5f};
-      for (int b = 0; b < B; ++b) {
-        raw[0] += Y[b] * f[3 * b];
-        raw[1] += Y[b] * f[3 * b + 1];
-        raw[2] += Y[b] * f[3 * b + 2];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        if (b < B) {
+          raw[0] += Y[b] * f[3 * b];
+          raw[1] += Y[b] * f[3 * b + 1];
+          raw[2] += Y[b] * f[3 * b + 2];
+        }
       }
       float dr[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) dr[c] = raw[c] >= 0.f ? drgb[c] : 0.f;
       float gb[16];
       float* dsh = a.d_sh + (size_t)i * B * 3;
-      for (int b = 0; b < B; ++b) {
-        gb[b] = f[3 * b] * dr[0] + f[3 * b + 1] * dr[1] + f[3 * b + 2] * dr[2];
-        acc(dsh + 3 * b, Y[b] * dr[0], ex);
-        acc(dsh + 3 * b + 1, Y[b] * dr[1], ex);
-        acc(dsh + 3 * b + 2, Y[b] * dr[2], ex);
+#pragma unroll
+      for (int b = 0; b < 16; ++b)
+        gb[b] = (b < B) ? f[3 * b] * dr[0] + f[3 * b + 1] * dr[1] + f[3 * b + 2] * dr[2] : 0.f;
+      // dL/df_{b,c} = Y_b dr_c, element q = 3 b + c
+      if (ex && ((3 * B) & 3) == 0) {
+        float4* d4 = reinterpret_cast<float4*>(dsh);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+          if (4 * q < 3 * B) {
+            float4 x = d4[q];
+            x.x += Y[(4 * q) / 3] * dr[(4 * q) % 3];
+            x.y += Y[(4 * q + 1) / 3] * dr[(4 * q + 1) % 3];
+            x.z += Y[(4 * q + 2) / 3] * dr[(4 * q + 2) % 3];
+            x.w += Y[(4 * q + 3) / 3] * dr[(4 * q + 3) % 3];
+            d4[q] = x;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 48; ++q)
+          if (q < 3 * B) acc(dsh + q, Y[q / 3] * dr[q % 3], ex);
       }
       float ddir[3];
       sh_basis_grad(a.sh_deg, dir[0], dir[1], dir[2], gb, ddir[0], ddir[1], ddir[2]);
@@ -606,13 +633,16 @@ hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st) {
   if (a.total_tiles <= 0) return hipGetLastError();
   switch (a.kp.tile) {
     case 8:
-      S3R_LAUNCH(K_RASTER_BWD, k_raster_bwd<8>, dim3(a.total_tiles), dim3(64), 0, st, a);
+      S3R_LAUNCH(K_RASTER_BWD, k_raster_bwd<8>, dim3(a.total_tiles), dim3(RasterShape<8>::NT), 0,
+                 st, a);
       break;
     case 16:
-      S3R_LAUNCH(K_RASTER_BWD, k_raster_bwd<16>, dim3(a.total_tiles), dim3(256), 0, st, a);
+      S3R_LAUNCH(K_RASTER_BWD, k_raster_bwd<16>, dim3(a.total_tiles), dim3(RasterShape<16>::NT),
+                 0, st, a);
       break;
     case 32:
-      S3R_LAUNCH(K_RASTER_BWD, k_raster_bwd<32>, dim3(a.total_tiles), dim3(1024), 0, st, a);
+      S3R_LAUNCH(K_RASTER_BWD, k_raster_bwd<32>, dim3(a.total_tiles), dim3(RasterShape<32>::NT),
+                 0, st, a);
       break;
     default:
       return hipErrorInvalidValue;

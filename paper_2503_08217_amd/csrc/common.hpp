@@ -288,6 +288,63 @@ __device__ __forceinline__ void sh_basis_grad(int deg, float x, float y, float z
 }
 
 // ---------------------------------------------------------------------------
+// blending of one (pixel, record) pair -- shared by the forward and the
+// backward so that both take every skip / clamp / stop decision identically
+// ---------------------------------------------------------------------------
+struct Blend {
+  float power, ex, raw, alpha;
+  bool hit;  // passes the Mahalanobis cut and alpha_min
+};
+
+__device__ __forceinline__ Blend blend_eval(float u, float v, float A, float Bc, float C, float o,
+                                            float px, float py, const KParams& kp) {
+  Blend b;
+  const float dx = u - px;
+  const float dy = v - py;
+  b.power = fmaf(-0.5f, fmaf(A * dx, dx, C * dy * dy), -Bc * dx * dy);
+  b.ex = 0.f;
+  b.raw = 0.f;
+  b.alpha = 0.f;
+  b.hit = false;
+  if (-b.power > kp.cutoff) return b;
+  b.ex = __expf(b.power);
+  b.raw = o * b.ex;
+  b.alpha = fminf(kp.alpha_max, b.raw);
+  b.hit = !(b.alpha < kp.alpha_min);
+  return b;
+}
+
+// pixels per lane of the rasterizer: a 16x16 tile is one wave64 with four
+// pixels per lane (rows y0, y0+4, y0+8, y0+12); 8x8 tiles use one pixel per
+// lane; 32x32 tiles four waves of four pixels
+template <int TS>
+struct RasterShape {
+  static constexpr int PPT = TS >= 16 ? 4 : 1;
+  static constexpr int NT = TS * TS / PPT;
+  static constexpr int ROWS = NT / TS;  // rows covered by one pass of the lanes
+};
+
+// SH coefficients of one Gaussian (B*3 floats) into registers; 16-byte loads
+// when the per-Gaussian stride keeps them aligned (degrees 1 and 3)
+__device__ __forceinline__ void load_sh(const float* __restrict__ f, int B, float out[48]) {
+  const int nf = 3 * B;
+  if ((nf & 3) == 0) {
+    const float4* f4 = reinterpret_cast<const float4*>(f);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      if (4 * q < nf) {
+        const float4 x = f4[q];
+        out[4 * q] = x.x; out[4 * q + 1] = x.y; out[4 * q + 2] = x.z; out[4 * q + 3] = x.w;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 48; ++q)
+      if (q < nf) out[q] = f[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }

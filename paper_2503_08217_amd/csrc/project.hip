@@ -361,12 +361,16 @@ __global__ __launch_bounds__(kProjBlock) void k_records(ProjArgs a) {
     dx = dx / nrm; dy = dy / nrm; dz = dz / nrm;
     float Y[16];
     sh_basis(a.sh_deg, dx, dy, dz, Y);
-    const float* f = a.sh + (size_t)i * B * 3;
+    float f[48];
+    load_sh(a.sh + (size_t)i * B * 3, B, f);
     float r = 0.f, gg = 0.f, bb = 0.f;
-    for (int q = 0; q < B; ++q) {
-      r = fmaf(Y[q], f[3 * q], r);
-      gg = fmaf(Y[q], f[3 * q + 1], gg);
-      bb = fmaf(Y[q], f[3 * q + 2], bb);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (q < B) {
+        r = fmaf(Y[q], f[3 * q], r);
+        gg = fmaf(Y[q], f[3 * q + 1], gg);
+        bb = fmaf(Y[q], f[3 * q + 2], bb);
+      }
     }
     r = fmaxf(r + 0.5f, 0.f);
     gg = fmaxf(gg + 0.5f, 0.f);

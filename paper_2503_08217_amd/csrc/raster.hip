@@ -1,21 +1,23 @@
 // Front-to-back alpha blending of Eq. (2) over every tile of every view in
 // one launch.
 //
-// One workgroup per tile, one thread per pixel (a 16x16 tile is four wave64s).
-// The tile's sorted list is consumed in batches: each thread stages one record
-// (mean, conic, opacity, colour: 40 bytes) in LDS, then every thread blends the
-// whole batch into its pixel.  A batch loop ends as soon as every pixel of the
-// tile has reached the transmittance floor.  The pixel is sampled at integer
+// One workgroup per tile; a 16x16 tile is a single wave64 whose lanes own four
+// pixels each, so every record read from LDS is blended into four pixels.
+// The tile's sorted list is consumed in batches: each lane stages one record
+// (mean, conic, opacity, colour) in LDS, then every lane blends the whole
+// batch into its pixels.  The loop ends as soon as every pixel of the tile
+// has reached the transmittance floor.  Pixels are sampled at integer
 // coordinates (x, y).
 #include "internal.hpp"
 
 namespace s3r {
 
 template <int TS>
-__global__ __launch_bounds__(TS* TS) void k_raster_fwd(RasterArgs a) {
-  constexpr int NT = TS * TS;
-  __shared__ float2 s_uv[NT];
-  __shared__ float4 s_con[NT];  // A, B, C, opacity
+__global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_fwd(RasterArgs a) {
+  using Sh = RasterShape<TS>;
+  constexpr int NT = Sh::NT, PPT = Sh::PPT, ROWS = Sh::ROWS;
+  __shared__ float4 s_geo[NT];  // u, v, opacity
+  __shared__ float4 s_con[NT];  // A, B, C
   __shared__ float4 s_rgb[NT];
   const int tid = threadIdx.x;
   const int t = blockIdx.x;
@@ -24,62 +26,83 @@ __global__ __launch_bounds__(TS* TS) void k_raster_fwd(RasterArgs a) {
   const int W = a.wh[2 * v], H = a.wh[2 * v + 1];
   const int gx = (W + TS - 1) / TS;
   const int px = (lt % gx) * TS + tid % TS;
-  const int py = (lt / gx) * TS + tid / TS;
-  const bool inside = (px < W) && (py < H);
-  const float fxp = (float)px, fyp = (float)py;
+  const int py0 = (lt / gx) * TS + tid / TS;
+  const float fxp = (float)px;
   const int64_t s = a.tile_start[t];
   const int64_t e = min((int64_t)a.tile_start[t + 1], a.kp.cap_dup);
 
-  float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f;
-  bool done = !inside;
-  int last = 0;
+  float T[PPT], cr[PPT], cg[PPT], cb[PPT];
+  int last[PPT];
+  bool done[PPT];
+  bool all_done = true;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    T[k] = 1.f;
+    cr[k] = cg[k] = cb[k] = 0.f;
+    last[k] = 0;
+    done[k] = !(px < W && py0 + k * ROWS < H);
+    all_done = all_done && done[k];
+  }
   for (int64_t b0 = s; b0 < e; b0 += NT) {
-    if (__syncthreads_count(done) == NT) break;
+    if (__syncthreads_count(all_done) == NT) break;
     const int64_t idx = b0 + tid;
     if (idx < e) {
       const uint32_t r = a.vals[idx];
-      const float4 g = a.rec_geo[r];
-      const float4 c = a.rec_conic[r];
-      s_uv[tid] = make_float2(g.x, g.y);
-      s_con[tid] = make_float4(c.x, c.y, c.z, g.z);
+      s_geo[tid] = a.rec_geo[r];
+      s_con[tid] = a.rec_conic[r];
       s_rgb[tid] = a.rec_rgb[r];
     }
     __syncthreads();
     const int nb = (int)min((int64_t)NT, e - b0);
-    if (!done) {
+    if (!all_done) {
       for (int j = 0; j < nb; ++j) {
-        const float2 uv = s_uv[j];
-        const float4 con = s_con[j];
-        const float dx = uv.x - fxp;
-        const float dy = uv.y - fyp;
-        const float power = fmaf(-0.5f, fmaf(con.x * dx, dx, con.z * dy * dy), -con.y * dx * dy);
-        if (-power > a.kp.cutoff) continue;
-        const float alpha = fminf(a.kp.alpha_max, con.w * __expf(power));
-        if (alpha < a.kp.alpha_min) continue;
-        const float Tn = T * (1.0f - alpha);
-        if (Tn < a.kp.t_min) {
-          done = true;
+        const float4 g = s_geo[j];
+        const float4 c = s_con[j];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          if (done[k]) continue;
+          const Blend bl = blend_eval(g.x, g.y, c.x, c.y, c.z, g.z, fxp,
+                                      (float)(py0 + k * ROWS), a.kp);
+          if (!bl.hit) continue;
+          const float Tn = T[k] * (1.0f - bl.alpha);
+          if (Tn < a.kp.t_min) {
+            done[k] = true;
+            continue;
+          }
+          const float4 col = s_rgb[j];
+          const float w = bl.alpha * T[k];
+          cr[k] = fmaf(col.x, w, cr[k]);
+          cg[k] = fmaf(col.y, w, cg[k]);
+          cb[k] = fmaf(col.z, w, cb[k]);
+          T[k] = Tn;
+          last[k] = (int)(b0 - s) + j + 1;
+          any = true;
+        }
+        (void)any;
+        bool dn = true;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) dn = dn && done[k];
+        if (dn) {
+          all_done = true;
           break;
         }
-        const float4 col = s_rgb[j];
-        const float w = alpha * T;
-        cr = fmaf(col.x, w, cr);
-        cg = fmaf(col.y, w, cg);
-        cb = fmaf(col.z, w, cb);
-        T = Tn;
-        last = (int)(b0 - s) + j + 1;
       }
     }
   }
-  if (inside) {
-    const int64_t npx = (int64_t)W * H;
-    const int64_t p = (int64_t)py * W + px;
-    const int64_t base = 3 * a.px_offset[v];
-    a.color[base + p] = fmaf(T, a.kp.bg0, cr);
-    a.color[base + npx + p] = fmaf(T, a.kp.bg1, cg);
-    a.color[base + 2 * npx + p] = fmaf(T, a.kp.bg2, cb);
-    a.T_final[a.px_offset[v] + p] = T;
-    a.last[a.px_offset[v] + p] = last;
+  const int64_t npx = (int64_t)W * H;
+  const int64_t base = 3 * a.px_offset[v];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int py = py0 + k * ROWS;
+    if (px < W && py < H) {
+      const int64_t p = (int64_t)py * W + px;
+      a.color[base + p] = fmaf(T[k], a.kp.bg0, cr[k]);
+      a.color[base + npx + p] = fmaf(T[k], a.kp.bg1, cg[k]);
+      a.color[base + 2 * npx + p] = fmaf(T[k], a.kp.bg2, cb[k]);
+      a.T_final[a.px_offset[v] + p] = T[k];
+      a.last[a.px_offset[v] + p] = last[k];
+    }
   }
 }
 
@@ -87,13 +110,16 @@ hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st) {
   if (a.total_tiles <= 0) return hipSuccess;
   switch (a.kp.tile) {
     case 8:
-      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<8>, dim3(a.total_tiles), dim3(64), 0, st, a);
+      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<8>, dim3(a.total_tiles), dim3(RasterShape<8>::NT), 0,
+                 st, a);
       break;
     case 16:
-      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<16>, dim3(a.total_tiles), dim3(256), 0, st, a);
+      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<16>, dim3(a.total_tiles), dim3(RasterShape<16>::NT),
+                 0, st, a);
       break;
     case 32:
-      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<32>, dim3(a.total_tiles), dim3(1024), 0, st, a);
+      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<32>, dim3(a.total_tiles), dim3(RasterShape<32>::NT),
+                 0, st, a);
       break;
     default:
       return hipErrorInvalidValue;

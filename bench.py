@@ -87,16 +87,24 @@ def view_units(r, handles, targets, torch):
 
 
 def timed(r, handles, targets, steps, warmup, torch, profile=True):
+    """Warm-up steps with every kernel timed (this picks the dominant kernel),
+    then the timed region: `steps` steps with only the dominant kernel
+    bracketed by HIP events.  Returns (seconds, {kernel: (ms, launches)} of
+    the warm-up, (dominant name, ms, launches) of the timed region)."""
     from paper_2503_08217_amd import _abi
     lib = _abi.load()
+    _abi.check(lib.s3r_profile_reset(), "profile reset")
+    _abi.check(lib.s3r_profile_only(-1), "profile only")
+    _abi.check(lib.s3r_profile_enable(1), "profile enable")
     for i in range(warmup):
         h = i % len(handles)
         r.use_views(handles[h])
         r.step(targets[h])
     torch.cuda.synchronize()
-    if profile:
-        _abi.check(lib.s3r_profile_reset(), "profile reset")
-        _abi.check(lib.s3r_profile_enable(1), "profile enable")
+    table = _abi.profile_table()
+    dom = max(table.items(), key=lambda kv: kv[1][0])[0]
+    _abi.check(lib.s3r_profile_reset(), "profile reset")
+    _abi.check(lib.s3r_profile_only(_abi.profile_id(dom)), "profile only")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
@@ -105,11 +113,10 @@ def timed(r, handles, targets, steps, warmup, torch, profile=True):
         r.step(targets[h])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    table = {}
-    if profile:
-        table = _abi.profile_table()
-        _abi.check(lib.s3r_profile_enable(0), "profile disable")
-    return t1 - t0, table
+    live = _abi.profile_table()
+    _abi.check(lib.s3r_profile_enable(0), "profile disable")
+    _abi.check(lib.s3r_profile_only(-1), "profile only")
+    return t1 - t0, table, (dom,) + tuple(live.get(dom, (0.0, 0)))
 
 
 def kernel_roofline(name, total_ms, launches, units, steps, sh_degree, n):
@@ -204,15 +211,120 @@ def cpu_baseline(cfg, n_tiles_sample=48):
                        f"({t_tiles:.1f}s, torch CPU), scaled to the view's {gx * gy} tiles")}
 
 
+def lod_temporal_sweep(cfg, targets, torch, steps=16):
+    """views/s of the streamlined step over LOD threshold x temporal filter."""
+    r = make_renderer(cfg, plain=False)
+    warmup_temporal(r, cfg, torch)
+    handles = r.prepare_views([cfg.views.subset([v]) for v in cfg.timed_views])
+    out = []
+    for temporal in (True, False):
+        for lod_r in (0.0, 0.5, 1.0, 2.0):
+            r.set_flags(temporal=temporal, lod=lod_r > 0, lod_r=lod_r)
+            for h in handles:
+                r.use_views(h)
+                r.fit_capacity()
+            handles = r.prepare_views([cfg.views.subset([v]) for v in cfg.timed_views])
+            for i in range(4):
+                r.use_views(handles[i % len(handles)])
+                r.step(targets[i % len(handles)])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(steps):
+                r.use_views(handles[i % len(handles)])
+                r.step(targets[i % len(handles)])
+            torch.cuda.synchronize()
+            vps = steps / (time.perf_counter() - t0)
+            st = []
+            for h in handles:
+                r.use_views(h)
+                r.forward()
+                torch.cuda.synchronize()
+                st.append(r.stats.cpu().numpy()[0].tolist())
+            mean = np.mean(np.asarray(st, np.float64), 0)
+            out.append({"lod_r": lod_r, "temporal": temporal, "views_per_s": vps,
+                        "mean_N_t": mean[0], "mean_N_r": mean[2], "mean_N_dup": mean[3]})
+            log(f"sweep lod_r={lod_r} temporal={temporal}: {vps:.1f} views/s, "
+                f"N_t {mean[0]:.0f} N_r {mean[2]:.0f} N_dup {mean[3]:.0f}")
+    del r
+    torch.cuda.empty_cache()
+    return out
+
+
+def batched_graph(cfg, torch, replays, tiles):
+    """Batched multi-view step (all timed views of the workload in one batch)
+    captured in a HIP graph; tile size picked by timing each candidate."""
+    from paper_2503_08217_amd import S3R_VIS_FOLD, S3R_VIS_UPDATE
+    from paper_2503_08217_amd.renderer import Renderer
+    import scenes
+    views = cfg.views.subset(cfg.timed_views)
+    tg = scenes.targets(cfg.cfg, views)
+    target = torch.as_tensor(np.concatenate([t.ravel() for t in tg])).cuda()
+    del tg
+    # temporal state: one pass over every timestep with the rig of one timestep
+    rig = sorted(set(int(t) for t in cfg.views.tstep))
+    per_t = [np.nonzero(cfg.views.tstep == t)[0] for t in rig]
+    warm = Renderer(cfg.scene, cfg.views.subset(per_t[0]), dict(cfg.params, temporal=False),
+                    cap_surv=max(1024, cfg.scene.n // 4), cap_dup=max(4096, cfg.scene.n))
+    hs = warm.prepare_views([cfg.views.subset(ix) for ix in per_t])
+    for h in hs:
+        warm.use_views(h)
+        warm.project_cull()
+        warm.update_visibility(S3R_VIS_UPDATE)
+    warm.update_visibility(S3R_VIS_FOLD)
+    torch.cuda.synchronize()
+    vis_s, vis_e = warm.vis_s.clone(), warm.vis_e.clone()
+    del warm, hs
+    torch.cuda.empty_cache()
+    best = None
+    tune = []
+    for tile in tiles:
+        params = dict(cfg.params, tile=tile)
+        r = Renderer(cfg.scene, views, params, cap_surv=max(1024, cfg.scene.n // 2),
+                     cap_dup=max(4096, 2 * cfg.scene.n))
+        r.vis_s.copy_(vis_s)
+        r.vis_e.copy_(vis_e)
+        c = r.fit_capacity()
+        g = r.capture_step(target, update_visibility=True)
+        times = []
+        for i in range(replays):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.replay()
+            e1.record()
+            times.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = np.asarray([a.elapsed_time(b) for a, b in times])
+        st = r.stats.cpu().numpy()
+        res = {"tile": tile, "p50_ms": float(np.percentile(ms, 50)),
+               "p99_ms": float(np.percentile(ms, 99)), "mean_ms": float(ms.mean()),
+               "views_per_s": views.n_views / (ms.mean() * 1e-3),
+               "mean_visible_fraction": float(st[:, 0].mean() / cfg.scene.n),
+               "records": c["n_surv"], "pairs": c["n_dup"]}
+        log(f"batched {cfg.name} tile {tile}: p50 {res['p50_ms']:.2f} ms, p99 "
+            f"{res['p99_ms']:.2f} ms, {res['views_per_s']:.1f} views/s, N_t/N "
+            f"{res['mean_visible_fraction']:.3f}")
+        tune.append(res)
+        if best is None or res["mean_ms"] < best["mean_ms"]:
+            best = res
+        del g, r
+        torch.cuda.empty_cache()
+    return {"workload": cfg.name, "views_per_batch": views.n_views, "replays": replays,
+            "best": best, "autotune": tune}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", type=int, default=16, choices=(8, 16, 32))
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time the LOD threshold x temporal filter grid")
+    ap.add_argument("--replays", type=int, default=100)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported here "
@@ -226,6 +338,11 @@ def main():
     t_gen = time.perf_counter()
     cfg = scenes.make_config(a.config)
     cfg.params["tile"] = a.tile
+    if a.config in (4, 5):
+        out = batched_graph(cfg, torch, a.replays, (8, 16, 32))
+        out["metric"] = "batched fwd+bwd step, hipGraph replay"
+        print(json.dumps(out), flush=True)
+        return
     log(f"config {a.config} ({cfg.name}) generated in {time.perf_counter() - t_gen:.1f}s, "
         f"N={cfg.scene.n}, tile {a.tile}")
     tg_np = scenes.targets(a.config, cfg.views, cfg.timed_views)
@@ -245,19 +362,20 @@ def main():
         handles = r.prepare_views([cfg.views.subset([v]) for v in cfg.timed_views])
         units = view_units(r, handles, targets, torch)
         log(f"{name}: per view {[(u['N_t'], u['N_f'], u['N_r'], u['N_dup']) for u in units]}")
-        elapsed, table = timed(r, handles, targets, a.steps, a.warmup, torch)
+        elapsed, table, live = timed(r, handles, targets, a.steps, a.warmup, torch)
         vps = a.steps / elapsed
-        log(f"{name}: {vps:.1f} views/s, {1000 * elapsed / a.steps:.3f} ms/step")
+        log(f"{name}: {vps:.1f} views/s, {1000 * elapsed / a.steps:.3f} ms/step; dominant "
+            f"{live[0]} {1000 * live[1] / max(live[2], 1):.1f} us x {live[2]} (timed region)")
         for k, (ms, cnt) in sorted(table.items(), key=lambda kv: -kv[1][0]):
-            log(f"   {k:22s} {1000 * ms / cnt:9.1f} us x {cnt}")
-        results[name] = dict(vps=vps, ms=1000 * elapsed / a.steps, table=table, units=units)
+            log(f"   {k:22s} {1000 * ms / cnt:9.1f} us x {cnt}  (warm-up)")
+        results[name] = dict(vps=vps, ms=1000 * elapsed / a.steps, table=table, units=units,
+                             live=live)
         del r
         torch.cuda.empty_cache()
 
     s = results["streamlined"]
     table, units = s["table"], s["units"]
-    dom = max(table.items(), key=lambda kv: kv[1][0])
-    dname, (dms, dcnt) = dom
+    dname, dms, dcnt = s["live"]
     rl = kernel_roofline(dname, dms, dcnt, units, a.steps, cfg.scene.sh_degree, cfg.scene.n)
     roof = None
     if rl:
@@ -266,8 +384,9 @@ def main():
                 "traffic": None, "kernel": dname, "avg_us": 1000 * dms / dcnt, "work": basis}
     pcs_names = ("compose", "project", "block_offsets", "records", "scan", "emit_pairs", "radix",
                  "tile_ranges", "dup_stats")
+    # warm-up steps (every kernel timed) give the project/cull/sort time
     pcs_ms = sum(table[k][0] for k in pcs_names if k in table)
-    pcs_gbs = pcs_bytes(units, a.steps, cfg.scene.sh_degree, cfg.scene.n) / (pcs_ms * 1e-3) / 1e9
+    pcs_gbs = pcs_bytes(units, a.warmup, cfg.scene.sh_degree, cfg.scene.n) / (pcs_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": s["vps"],
@@ -286,14 +405,16 @@ def main():
                    "lod_r_px": 1.0, "temporal": "on (after warm-up fold)"},
         "roofline": roof,
         "project_cull_sort_hbm": {"achieved": pcs_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                  "frac": pcs_gbs / HBM_PEAK_GBS, "ms_per_step": pcs_ms / a.steps},
-        "kernels_us": {k: 1000 * ms / cnt for k, (ms, cnt) in table.items()},
+                                  "frac": pcs_gbs / HBM_PEAK_GBS, "ms_per_step": pcs_ms / a.warmup},
+        "kernels_us_warmup": {k: 1000 * ms / cnt for k, (ms, cnt) in table.items()},
     }
     if "plain" in results:
         p = results["plain"]
         out["plain_views_per_s"] = p["vps"]
         out["speedup_vs_plain"] = s["vps"] / p["vps"]
-        out["plain_kernels_us"] = {k: 1000 * ms / cnt for k, (ms, cnt) in p["table"].items()}
+        out["plain_kernels_us_warmup"] = {k: 1000 * ms / cnt for k, (ms, cnt) in p["table"].items()}
+    if a.sweep:
+        out["sweep"] = lod_temporal_sweep(cfg, targets, torch)
     if not a.no_cpu:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(cfg)

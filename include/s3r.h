@@ -303,6 +303,7 @@ int s3r_plain_transform_bwd(const S3RScene* scene, const int32_t* tsteps, int32_
  * s3r_profile_name()).  Not for use while a stream is being captured.
  */
 int s3r_profile_enable(int on);
+int s3r_profile_only(int32_t id); /* >= 0: time kernel `id` only; -1: every kernel */
 int s3r_profile_reset(void);
 int s3r_profile_read(int32_t id, double* total_ms, int64_t* count);
 const char* s3r_profile_name(int32_t id);

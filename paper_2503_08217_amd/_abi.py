@@ -92,10 +92,19 @@ SIGNATURES = {
                                  C.POINTER(S3RGrads), P], C.c_int),
     "s3r_profile_enable": ([C.c_int], C.c_int),
     "s3r_profile_reset": ([], C.c_int),
+    "s3r_profile_only": ([C.c_int32], C.c_int),
     "s3r_profile_read": ([C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "s3r_profile_name": ([C.c_int32], C.c_char_p),
     "s3r_profile_kernels": ([], C.c_int),
 }
+
+
+def profile_id(name):
+    lib = load()
+    for i in range(lib.s3r_profile_kernels()):
+        if lib.s3r_profile_name(i).decode() == name:
+            return i
+    raise KeyError(name)
 
 
 def profile_table():

@@ -27,6 +27,7 @@ struct Prof {
   long long count[K_COUNT] = {};
   int open_id = -1;
   int open_ev = -1;
+  int only = -1;  // >= 0: bracket this kernel only
 };
 Prof g_prof;
 constexpr int kPool = 8192;
@@ -50,7 +51,7 @@ void drain() {
 }  // namespace
 
 void prof_begin(int id, hipStream_t st) {
-  if (!g_prof.on) return;
+  if (!g_prof.on || (g_prof.only >= 0 && id != g_prof.only)) return;
   if (g_prof.used + 2 > (int)g_prof.pool.size()) drain();
   g_prof.open_id = id;
   g_prof.open_ev = g_prof.used++;
@@ -79,6 +80,12 @@ int s3r_profile_enable(int on) {
   }
   if (!on) drain();
   g_prof.on = on != 0;
+  return S3R_OK;
+}
+
+int s3r_profile_only(int32_t id) {
+  if (id >= K_COUNT) return S3R_E_ARG;
+  g_prof.only = id < 0 ? -1 : id;
   return S3R_OK;
 }
 

@@ -7,10 +7,12 @@
 //   dL/dc_i     = alpha_i T_i dL/dC
 //   dL/dalpha_i = T_i c_i . dL/dC - (S_i + T_N bg) . dL/dC / (1 - alpha_i)
 // and alpha_i = min(alpha_max, o_i exp(power_i)) chains to the 2D mean, the
-// conic and the opacity.  A lane owns four pixels of a 16x16 tile (the tile is
-// one wave64); a record's gradient is summed over the lane's pixels, then over
-// the wave with DPP row operations, and added to the record with one set of
-// global atomics per tile.
+// conic and the opacity.  A thread owns one pixel and a wave64 an 8x8
+// sub-tile; a wave walks only the entries up to its own last contributor and
+// skips, uniformly, records whose cutoff box misses its sub-tile.  A record's
+// gradient is summed over the wave with DPP row operations, over the tile's
+// waves in LDS, and added to the record with one set of global atomics per
+// tile.
 //
 // k_project_bwd chains those 2D gradients through the conic inverse, the EWA
 // covariance J R Sigma R^T J^T (Eq. 1), the quaternion/scale parameterisation,
@@ -27,11 +29,11 @@ namespace s3r {
 template <int TS>
 __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
   using Sh = RasterShape<TS>;
-  constexpr int NT = Sh::NT, PPT = Sh::PPT, ROWS = Sh::ROWS;
-  constexpr int NW = NT / kWave > 0 ? NT / kWave : 1;
+  constexpr int NT = Sh::NT, NW = Sh::NW;
   __shared__ float4 s_geo[NT];
   __shared__ float4 s_con[NT];
   __shared__ float4 s_rgb[NT];
+  __shared__ float4 s_box[NT];
   __shared__ uint32_t s_rec[NT];
   __shared__ float s_g[NW > 1 ? NT : 1][9];
   __shared__ int s_max[NW];
@@ -42,39 +44,34 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
   const int lt = t - a.tile_offset[v];
   const int W = a.wh[2 * v], H = a.wh[2 * v + 1];
   const int gx = (W + TS - 1) / TS;
-  const int px = (lt % gx) * TS + tid % TS;
-  const int py0 = (lt / gx) * TS + tid / TS;
-  const float fxp = (float)px;
+  int ox, oy, sx, sy;
+  raster_pixel<TS>(tid, ox, oy, sx, sy);
+  const int tx0 = (lt % gx) * TS, ty0 = (lt / gx) * TS;
+  const int px = tx0 + ox, py = ty0 + oy;
+  const float fxp = (float)px, fyp = (float)py;
+  const float sub_x = (float)(tx0 + sx), sub_y = (float)(ty0 + sy);
   const int64_t s = a.tile_start[t];
   const int64_t e = min((int64_t)a.tile_start[t + 1], a.kp.cap_dup);
   const int64_t npx = (int64_t)W * H;
   const int64_t base = 3 * a.px_offset[v];
 
-  float T[PPT], dCr[PPT], dCg[PPT], dCb[PPT], bgdot[PPT], Sr[PPT], Sg[PPT], Sb[PPT];
-  int last[PPT];
-  int m = 0;
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int py = py0 + k * ROWS;
-    T[k] = 1.f;
-    dCr[k] = dCg[k] = dCb[k] = 0.f;
-    last[k] = 0;
-    Sr[k] = Sg[k] = Sb[k] = 0.f;
-    if (px < W && py < H) {
-      const int64_t p = (int64_t)py * W + px;
-      T[k] = a.T_final[a.px_offset[v] + p];
-      last[k] = a.last[a.px_offset[v] + p];
-      dCr[k] = a.d_color[base + p];
-      dCg[k] = a.d_color[base + npx + p];
-      dCb[k] = a.d_color[base + 2 * npx + p];
-    }
-    bgdot[k] = T[k] * (a.kp.bg0 * dCr[k] + a.kp.bg1 * dCg[k] + a.kp.bg2 * dCb[k]);
-    m = max(m, last[k]);
+  float T = 1.f, dCr = 0.f, dCg = 0.f, dCb = 0.f;
+  int last = 0;
+  if (px < W && py < H) {
+    const int64_t p = (int64_t)py * W + px;
+    T = a.T_final[a.px_offset[v] + p];
+    last = a.last[a.px_offset[v] + p];
+    dCr = a.d_color[base + p];
+    dCg = a.d_color[base + npx + p];
+    dCb = a.d_color[base + 2 * npx + p];
   }
-  // number of list entries any pixel of the tile needs
+  const float bgdot = T * (a.kp.bg0 * dCr + a.kp.bg1 * dCg + a.kp.bg2 * dCb);
+  float Sr = 0.f, Sg = 0.f, Sb = 0.f;
+  // list entries this wave's pixels need, and the whole tile's
+  int mw = last;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
-  if (lane == 0) s_max[wave] = m;
+  for (int o = 32; o > 0; o >>= 1) mw = max(mw, __shfl_xor(mw, o, kWave));
+  if (lane == 0) s_max[wave] = mw;
   __syncthreads();
   int nrep = 0;
   for (int w = 0; w < NW; ++w) nrep = max(nrep, s_max[w]);
@@ -86,9 +83,12 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
     const int64_t idx = b0 + tid;
     if (idx < b_end) {
       const uint32_t r = a.vals[idx];
-      s_geo[tid] = a.rec_geo[r];
-      s_con[tid] = a.rec_conic[r];
+      const float4 g = a.rec_geo[r];
+      const float4 c = a.rec_conic[r];
+      s_geo[tid] = g;
+      s_con[tid] = c;
       s_rgb[tid] = a.rec_rgb[r];
+      s_box[tid] = cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff);
       s_rec[tid] = r;
     }
     if (NW > 1) {
@@ -96,44 +96,45 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
       for (int q = 0; q < 9; ++q) s_g[tid][q] = 0.f;
     }
     __syncthreads();
-    for (int j = (int)(b_end - b0) - 1; j >= 0; --j) {
+    // entries past this wave's last contributor are skipped as a whole
+    const int jw = (int)min(b_end - b0, (int64_t)mw - (b0 - s));
+    for (int j = jw - 1; j >= 0; --j) {
+      if (!box_hits(s_box[j], sub_x, sub_y)) continue;  // uniform across the wave
       const int pos = (int)(b0 - s) + j;
       const float4 g = s_geo[j];
       const float4 c = s_con[j];
-      const float4 col = s_rgb[j];
       float g_u = 0.f, g_v = 0.f, g_A = 0.f, g_B = 0.f, g_C = 0.f, g_o = 0.f;
       float g_r = 0.f, g_g = 0.f, g_b = 0.f;
       bool contrib = false;
-#pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        if (pos >= last[k]) continue;
-        const float py = (float)(py0 + k * ROWS);
-        const Blend bl = blend_eval(g.x, g.y, c.x, c.y, c.z, g.z, fxp, py, a.kp);
-        if (!bl.hit) continue;
-        contrib = true;
-        const float one_m = 1.0f - bl.alpha;
-        const float Tb = T[k] / one_m;
-        const float wgt = bl.alpha * Tb;
-        g_r = fmaf(wgt, dCr[k], g_r);
-        g_g = fmaf(wgt, dCg[k], g_g);
-        g_b = fmaf(wgt, dCb[k], g_b);
-        const float cdot = col.x * dCr[k] + col.y * dCg[k] + col.z * dCb[k];
-        const float sdot = Sr[k] * dCr[k] + Sg[k] * dCg[k] + Sb[k] * dCb[k];
-        const float dal = Tb * cdot - (sdot + bgdot[k]) / one_m;
-        Sr[k] = fmaf(col.x, wgt, Sr[k]);
-        Sg[k] = fmaf(col.y, wgt, Sg[k]);
-        Sb[k] = fmaf(col.z, wgt, Sb[k]);
-        T[k] = Tb;
-        if (bl.raw <= a.kp.alpha_max) {
-          const float dx = g.x - fxp;
-          const float dy = g.y - py;
-          const float dpow = dal * bl.alpha;
-          g_o = fmaf(dal, bl.ex, g_o);
-          g_u -= dpow * (c.x * dx + c.y * dy);
-          g_v -= dpow * (c.z * dy + c.y * dx);
-          g_A -= 0.5f * dpow * dx * dx;
-          g_B -= dpow * dx * dy;
-          g_C -= 0.5f * dpow * dy * dy;
+      if (pos < last) {
+        const Blend bl = blend_eval(g.x, g.y, c.x, c.y, c.z, g.z, fxp, fyp, a.kp);
+        if (bl.hit) {
+          contrib = true;
+          const float4 col = s_rgb[j];
+          const float one_m = 1.0f - bl.alpha;
+          const float Tb = T / one_m;
+          const float wgt = bl.alpha * Tb;
+          g_r = wgt * dCr;
+          g_g = wgt * dCg;
+          g_b = wgt * dCb;
+          const float cdot = col.x * dCr + col.y * dCg + col.z * dCb;
+          const float sdot = Sr * dCr + Sg * dCg + Sb * dCb;
+          const float dal = Tb * cdot - (sdot + bgdot) / one_m;
+          Sr = fmaf(col.x, wgt, Sr);
+          Sg = fmaf(col.y, wgt, Sg);
+          Sb = fmaf(col.z, wgt, Sb);
+          T = Tb;
+          if (bl.raw <= a.kp.alpha_max) {
+            const float dx = g.x - fxp;
+            const float dy = g.y - fyp;
+            const float dpow = dal * bl.alpha;
+            g_o = dal * bl.ex;
+            g_u = -dpow * (c.x * dx + c.y * dy);
+            g_v = -dpow * (c.z * dy + c.y * dx);
+            g_A = -0.5f * dpow * dx * dx;
+            g_B = -dpow * dx * dy;
+            g_C = -0.5f * dpow * dy * dy;
+          }
         }
       }
       if (ballot(contrib) != 0ull) {

@@ -314,15 +314,46 @@ __device__ __forceinline__ Blend blend_eval(float u, float v, float A, float Bc,
   return b;
 }
 
-// pixels per lane of the rasterizer: a 16x16 tile is one wave64 with four
-// pixels per lane (rows y0, y0+4, y0+8, y0+12); 8x8 tiles use one pixel per
-// lane; 32x32 tiles four waves of four pixels
+// Rasterizer layout: one thread per pixel, each wave64 owns an 8x8 sub-tile
+// (a 16x16 tile is four waves).  Lane l of wave w covers pixel
+// (8 (w % (TS/8)) + l % 8, 8 (w / (TS/8)) + l / 8) of the tile.
 template <int TS>
 struct RasterShape {
-  static constexpr int PPT = TS >= 16 ? 4 : 1;
-  static constexpr int NT = TS * TS / PPT;
-  static constexpr int ROWS = NT / TS;  // rows covered by one pass of the lanes
+  static constexpr int NT = TS * TS;
+  static constexpr int SUB = TS / 8;  // sub-tiles per row
+  static constexpr int NW = NT / 64;
 };
+template <int TS>
+__device__ __forceinline__ void raster_pixel(int tid, int& ox, int& oy, int& sx, int& sy) {
+  const int w = tid / 64, l = tid % 64;
+  sx = 8 * (w % RasterShape<TS>::SUB);
+  sy = 8 * (w / RasterShape<TS>::SUB);
+  ox = sx + (l % 8);
+  oy = sy + (l / 8);
+}
+
+// Bounding box of the pixels where a record can pass the Mahalanobis cut.
+// -power <= cutoff means d^T Q d <= 2 cutoff (Q the conic), an ellipse whose
+// extent along x is sqrt(2 cutoff (Q^-1)_xx) = sqrt(2 cutoff C / det Q).  The
+// rasterizer's binary32 evaluation of the form differs from the exact one by
+// at most ~30 u kappa relative (u = 2^-24, kappa = condition of Q, bounded
+// above by (A + C)^2 / det); the box is grown by that margin so that skipping
+// records outside it never removes a pixel the blend test would keep, and is
+// unbounded when Q is too ill-conditioned for the bound to be useful.
+__device__ __forceinline__ float4 cutoff_box(float u, float v, float A, float B, float C,
+                                             float cutoff) {
+  const float det = A * C - B * B;
+  const float tr = A + C;
+  const float kap = tr * tr / det;
+  if (!(det > 0.f) || !(kap < 1.0e5f)) return make_float4(-3.0e38f, 3.0e38f, -3.0e38f, 3.0e38f);
+  const float grow = 2.f * cutoff * (1.002f + 64.f * 5.9604645e-8f * kap) / det;
+  const float hx = sqrtf(grow * C) + 0.01f;
+  const float hy = sqrtf(grow * A) + 0.01f;
+  return make_float4(u - hx, u + hx, v - hy, v + hy);
+}
+__device__ __forceinline__ bool box_hits(float4 b, float x0, float y0) {
+  return (b.y >= x0) && (b.x <= x0 + 7.f) && (b.w >= y0) && (b.z <= y0 + 7.f);
+}
 
 // SH coefficients of one Gaussian (B*3 floats) into registers; 16-byte loads
 // when the per-Gaussian stride keeps them aligned (degrees 1 and 3)

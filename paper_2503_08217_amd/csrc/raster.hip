@@ -1,108 +1,91 @@
 // Front-to-back alpha blending of Eq. (2) over every tile of every view in
 // one launch.
 //
-// One workgroup per tile; a 16x16 tile is a single wave64 whose lanes own four
-// pixels each, so every record read from LDS is blended into four pixels.
-// The tile's sorted list is consumed in batches: each lane stages one record
-// (mean, conic, opacity, colour) in LDS, then every lane blends the whole
-// batch into its pixels.  The loop ends as soon as every pixel of the tile
-// has reached the transmittance floor.  Pixels are sampled at integer
-// coordinates (x, y).
+// One workgroup per tile, one thread per pixel; each wave64 owns an 8x8
+// sub-tile of the 16x16 tile.  The tile's sorted list is consumed in
+// batches: each thread stages one record (mean, conic, opacity, colour and the
+// bounding box of its cutoff ellipse) in LDS, then every wave blends the batch
+// into its pixels, skipping -- uniformly across the wave -- records whose box
+// misses its sub-tile (no pixel there could pass the Mahalanobis cut).  The
+// loop ends as soon as every pixel of the tile has reached the transmittance
+// floor.  Pixels are sampled at integer coordinates (x, y).
 #include "internal.hpp"
 
 namespace s3r {
 
 template <int TS>
 __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_fwd(RasterArgs a) {
-  using Sh = RasterShape<TS>;
-  constexpr int NT = Sh::NT, PPT = Sh::PPT, ROWS = Sh::ROWS;
+  constexpr int NT = RasterShape<TS>::NT;
   __shared__ float4 s_geo[NT];  // u, v, opacity
   __shared__ float4 s_con[NT];  // A, B, C
   __shared__ float4 s_rgb[NT];
+  __shared__ float4 s_box[NT];  // cutoff bounding box
   const int tid = threadIdx.x;
   const int t = blockIdx.x;
   const int v = find_view(a.tile_offset, a.nv, t);
   const int lt = t - a.tile_offset[v];
   const int W = a.wh[2 * v], H = a.wh[2 * v + 1];
   const int gx = (W + TS - 1) / TS;
-  const int px = (lt % gx) * TS + tid % TS;
-  const int py0 = (lt / gx) * TS + tid / TS;
-  const float fxp = (float)px;
+  int ox, oy, sx, sy;
+  raster_pixel<TS>(tid, ox, oy, sx, sy);
+  const int tx0 = (lt % gx) * TS, ty0 = (lt / gx) * TS;
+  const int px = tx0 + ox, py = ty0 + oy;
+  const float fxp = (float)px, fyp = (float)py;
+  const float sub_x = (float)(tx0 + sx), sub_y = (float)(ty0 + sy);
+  const bool inside = (px < W) && (py < H);
   const int64_t s = a.tile_start[t];
   const int64_t e = min((int64_t)a.tile_start[t + 1], a.kp.cap_dup);
 
-  float T[PPT], cr[PPT], cg[PPT], cb[PPT];
-  int last[PPT];
-  bool done[PPT];
-  bool all_done = true;
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    T[k] = 1.f;
-    cr[k] = cg[k] = cb[k] = 0.f;
-    last[k] = 0;
-    done[k] = !(px < W && py0 + k * ROWS < H);
-    all_done = all_done && done[k];
-  }
+  float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f;
+  bool done = !inside;
+  int last = 0;
   for (int64_t b0 = s; b0 < e; b0 += NT) {
-    if (__syncthreads_count(all_done) == NT) break;
+    if (__syncthreads_count(done) == NT) break;
     const int64_t idx = b0 + tid;
     if (idx < e) {
       const uint32_t r = a.vals[idx];
-      s_geo[tid] = a.rec_geo[r];
-      s_con[tid] = a.rec_conic[r];
+      const float4 g = a.rec_geo[r];
+      const float4 c = a.rec_conic[r];
+      s_geo[tid] = g;
+      s_con[tid] = c;
       s_rgb[tid] = a.rec_rgb[r];
+      s_box[tid] = cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff);
     }
     __syncthreads();
     const int nb = (int)min((int64_t)NT, e - b0);
-    if (!all_done) {
+    // the wave walks the batch while any of its pixels is still open
+    if (ballot(!done) != 0ull) {
       for (int j = 0; j < nb; ++j) {
+        if (!box_hits(s_box[j], sub_x, sub_y)) continue;  // uniform across the wave
+        if (done) continue;
         const float4 g = s_geo[j];
         const float4 c = s_con[j];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          if (done[k]) continue;
-          const Blend bl = blend_eval(g.x, g.y, c.x, c.y, c.z, g.z, fxp,
-                                      (float)(py0 + k * ROWS), a.kp);
-          if (!bl.hit) continue;
-          const float Tn = T[k] * (1.0f - bl.alpha);
-          if (Tn < a.kp.t_min) {
-            done[k] = true;
-            continue;
-          }
-          const float4 col = s_rgb[j];
-          const float w = bl.alpha * T[k];
-          cr[k] = fmaf(col.x, w, cr[k]);
-          cg[k] = fmaf(col.y, w, cg[k]);
-          cb[k] = fmaf(col.z, w, cb[k]);
-          T[k] = Tn;
-          last[k] = (int)(b0 - s) + j + 1;
-          any = true;
+        const Blend bl = blend_eval(g.x, g.y, c.x, c.y, c.z, g.z, fxp, fyp, a.kp);
+        if (!bl.hit) continue;
+        const float Tn = T * (1.0f - bl.alpha);
+        if (Tn < a.kp.t_min) {
+          done = true;
+          continue;
         }
-        (void)any;
-        bool dn = true;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) dn = dn && done[k];
-        if (dn) {
-          all_done = true;
-          break;
-        }
+        const float4 col = s_rgb[j];
+        const float w = bl.alpha * T;
+        cr = fmaf(col.x, w, cr);
+        cg = fmaf(col.y, w, cg);
+        cb = fmaf(col.z, w, cb);
+        T = Tn;
+        last = (int)(b0 - s) + j + 1;
       }
     }
   }
-  const int64_t npx = (int64_t)W * H;
-  const int64_t base = 3 * a.px_offset[v];
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int py = py0 + k * ROWS;
-    if (px < W && py < H) {
-      const int64_t p = (int64_t)py * W + px;
-      a.color[base + p] = fmaf(T[k], a.kp.bg0, cr[k]);
-      a.color[base + npx + p] = fmaf(T[k], a.kp.bg1, cg[k]);
-      a.color[base + 2 * npx + p] = fmaf(T[k], a.kp.bg2, cb[k]);
-      a.T_final[a.px_offset[v] + p] = T[k];
-      a.last[a.px_offset[v] + p] = last[k];
-    }
+  if (inside) {
+    const int64_t npx = (int64_t)W * H;
+    const int64_t p = (int64_t)py * W + px;
+    const int64_t base = 3 * a.px_offset[v];
+    a.color[base + p] = fmaf(T, a.kp.bg0, cr);
+    a.color[base + npx + p] = fmaf(T, a.kp.bg1, cg);
+    a.color[base + 2 * npx + p] = fmaf(T, a.kp.bg2, cb);
+    a.T_final[a.px_offset[v] + p] = T;
+    a.last[a.px_offset[v] + p] = last;
   }
 }
 

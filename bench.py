@@ -21,8 +21,10 @@ refused).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -40,6 +42,54 @@ FLOP_FWD_PAIR = 22.0     # blending one (pixel, list entry) pair
 FLOP_BWD_PAIR = 60.0     # replaying one (pixel, list entry) pair backwards
 REC_BYTES = 72           # record written per survivor (gid, view, geo, conic, rgb, rect)
 GEOM_BYTES = 44          # mean, scale, quat, instance id of a Gaussian that passes
+
+
+# source files whose change invalidates a kernel's measured HBM traffic
+KERNEL_SOURCES = {
+    "raster_bwd": ("backward.hip", "common.hpp", "internal.hpp"),
+    "raster_fwd": ("raster.hip", "common.hpp", "internal.hpp"),
+    "project": ("project.hip", "common.hpp", "internal.hpp"),
+    "records": ("project.hip", "common.hpp", "internal.hpp"),
+    "radix": ("sort.hip", "common.hpp", "internal.hpp"),
+    "project_bwd": ("backward.hip", "common.hpp", "internal.hpp"),
+}
+
+
+def sources_digest(kernel):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, ()):
+        with open(os.path.join(ROOT, "paper_2503_08217_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the PMC summary under profiles/
+    (FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel calibration), or None when
+    there is none or the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    d = re.search(r"sources_sha256_16:\s*([0-9a-f]+)", text)
+    if not m or not d or d.group(1) != sources_digest(kernel):
+        return None
+    return float(m.group(1))
+
+
+def copy_calibration(mib, torch):
+    """A plain device copy of known size (`mib` MiB read and written), run
+    twice, whose FETCH_SIZE / WRITE_SIZE readings calibrate the counters."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {mib} MiB copied twice")
+    del src, dst
+    torch.cuda.empty_cache()
 
 
 def log(msg):
@@ -165,7 +215,7 @@ def pcs_bytes(units, steps, sh_degree, n):
                + 12 * u["N_dup"] + 24 * u["N_dup"] for u in per)
 
 
-def cpu_baseline(cfg, n_tiles_sample=48):
+def cpu_baseline(cfg, n_tiles_sample=160):
     """The oracle as it stands, on a bounded sample of one view of the same
     workload: the binary32 decision layer and colours over all N Gaussians,
     then FP64 blending + autograd backward of `n_tiles_sample` random 16x16
@@ -325,6 +375,8 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="also time the LOD threshold x temporal filter grid")
     ap.add_argument("--replays", type=int, default=100)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run a plain copy of this many MiB first (for counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported here "
@@ -335,6 +387,8 @@ def main():
 
     import scenes
 
+    if a.copy_calibration > 0:
+        copy_calibration(a.copy_calibration, torch)
     t_gen = time.perf_counter()
     cfg = scenes.make_config(a.config)
     cfg.params["tile"] = a.tile
@@ -381,7 +435,9 @@ def main():
     if rl:
         bound, ach, peak, unit, basis = rl
         roof = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-                "traffic": None, "kernel": dname, "avg_us": 1000 * dms / dcnt, "work": basis}
+                "traffic": measured_traffic(dname, cfg.name), "kernel": dname,
+                "avg_us": 1000 * dms / dcnt, "work": basis,
+                "sources_sha256_16": sources_digest(dname)}
     pcs_names = ("compose", "project", "block_offsets", "records", "scan", "emit_pairs", "radix",
                  "tile_ranges", "dup_stats")
     # warm-up steps (every kernel timed) give the project/cull/sort time

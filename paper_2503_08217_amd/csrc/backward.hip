@@ -8,11 +8,13 @@
 //   dL/dalpha_i = T_i c_i . dL/dC - (S_i + T_N bg) . dL/dC / (1 - alpha_i)
 // and alpha_i = min(alpha_max, o_i exp(power_i)) chains to the 2D mean, the
 // conic and the opacity.  A thread owns one pixel and a wave64 an 8x8
-// sub-tile; a wave walks only the entries up to its own last contributor and
-// skips, uniformly, records whose cutoff box misses its sub-tile.  A record's
-// gradient is summed over the wave with DPP row operations, over the tile's
-// waves in LDS, and added to the record with one set of global atomics per
-// tile.
+// sub-tile; each wave replays only the list entries up to its own last
+// contributor, 64 at a time, keeping with one ballot the entries whose cutoff
+// box meets its sub-tile.  A record's nine gradient components are summed
+// over the wave (permlane swaps pack four sums into one register, DPP row sums
+// finish) and added into an LDS slot shared by the tile's waves; the list is
+// walked in windows of twice the tile's pixel count of entries, each flushed with one set of global
+// atomics per record and tile.
 //
 // k_project_bwd chains those 2D gradients through the conic inverse, the EWA
 // covariance J R Sigma R^T J^T (Eq. 1), the quaternion/scale parameterisation,
@@ -28,14 +30,9 @@ namespace s3r {
 // ---------------------------------------------------------------------------
 template <int TS>
 __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
-  using Sh = RasterShape<TS>;
-  constexpr int NT = Sh::NT, NW = Sh::NW;
-  __shared__ float4 s_geo[NT];
-  __shared__ float4 s_con[NT];
-  __shared__ float4 s_rgb[NT];
-  __shared__ float4 s_box[NT];
-  __shared__ uint32_t s_rec[NT];
-  __shared__ float s_g[NW > 1 ? NT : 1][9];
+  constexpr int NT = RasterShape<TS>::NT, NW = RasterShape<TS>::NW;
+  constexpr int WIN = RasterShape<TS>::WIN;
+  __shared__ float s_g[WIN][9];  // gradient of list entries [w0, w0 + WIN), all waves
   __shared__ int s_max[NW];
   const int tid = threadIdx.x;
   const int lane = tid % kWave, wave = tid / kWave;
@@ -67,104 +64,105 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
   }
   const float bgdot = T * (a.kp.bg0 * dCr + a.kp.bg1 * dCg + a.kp.bg2 * dCb);
   float Sr = 0.f, Sg = 0.f, Sb = 0.f;
-  // list entries this wave's pixels need, and the whole tile's
+  // each wave replays its own list prefix (entries up to its last contributor)
   int mw = last;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mw = max(mw, __shfl_xor(mw, o, kWave));
+  mw = __builtin_amdgcn_readfirstlane(mw);
   if (lane == 0) s_max[wave] = mw;
+  for (int k = tid; k < WIN * 9; k += NT) (&s_g[0][0])[k] = 0.f;
   __syncthreads();
   int nrep = 0;
   for (int w = 0; w < NW; ++w) nrep = max(nrep, s_max[w]);
-  const int64_t end = min(e, s + nrep);
+  const int64_t tile_end = min(e, s + (int64_t)nrep);
+  const int64_t wave_end = min(e, s + (int64_t)mw);
 
-  for (int64_t b_end = end; b_end > s; b_end -= NT) {
-    const int64_t b0 = max(s, b_end - NT);
-    __syncthreads();
-    const int64_t idx = b0 + tid;
-    if (idx < b_end) {
-      const uint32_t r = a.vals[idx];
-      const float4 g = a.rec_geo[r];
-      const float4 c = a.rec_conic[r];
-      s_geo[tid] = g;
-      s_con[tid] = c;
-      s_rgb[tid] = a.rec_rgb[r];
-      s_box[tid] = cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff);
-      s_rec[tid] = r;
-    }
-    if (NW > 1) {
-#pragma unroll
-      for (int q = 0; q < 9; ++q) s_g[tid][q] = 0.f;
-    }
-    __syncthreads();
-    // entries past this wave's last contributor are skipped as a whole
-    const int jw = (int)min(b_end - b0, (int64_t)mw - (b0 - s));
-    for (int j = jw - 1; j >= 0; --j) {
-      if (!box_hits(s_box[j], sub_x, sub_y)) continue;  // uniform across the wave
-      const int pos = (int)(b0 - s) + j;
-      const float4 g = s_geo[j];
-      const float4 c = s_con[j];
-      float g_u = 0.f, g_v = 0.f, g_A = 0.f, g_B = 0.f, g_C = 0.f, g_o = 0.f;
-      float g_r = 0.f, g_g = 0.f, g_b = 0.f;
-      bool contrib = false;
-      if (pos < last) {
-        const Blend bl = blend_eval(g.x, g.y, c.x, c.y, c.z, g.z, fxp, fyp, a.kp);
-        if (bl.hit) {
-          contrib = true;
-          const float4 col = s_rgb[j];
-          const float one_m = 1.0f - bl.alpha;
-          const float Tb = T / one_m;
-          const float wgt = bl.alpha * Tb;
-          g_r = wgt * dCr;
-          g_g = wgt * dCg;
-          g_b = wgt * dCb;
-          const float cdot = col.x * dCr + col.y * dCg + col.z * dCb;
-          const float sdot = Sr * dCr + Sg * dCg + Sb * dCb;
-          const float dal = Tb * cdot - (sdot + bgdot) / one_m;
-          Sr = fmaf(col.x, wgt, Sr);
-          Sg = fmaf(col.y, wgt, Sg);
-          Sb = fmaf(col.z, wgt, Sb);
-          T = Tb;
-          if (bl.raw <= a.kp.alpha_max) {
-            const float dx = g.x - fxp;
-            const float dy = g.y - fyp;
-            const float dpow = dal * bl.alpha;
-            g_o = dal * bl.ex;
-            g_u = -dpow * (c.x * dx + c.y * dy);
-            g_v = -dpow * (c.z * dy + c.y * dx);
-            g_A = -0.5f * dpow * dx * dx;
-            g_B = -dpow * dx * dy;
-            g_C = -0.5f * dpow * dy * dy;
-          }
-        }
-      }
-      if (ballot(contrib) != 0ull) {
-        g_u = wave_sum_dpp(g_u); g_v = wave_sum_dpp(g_v); g_A = wave_sum_dpp(g_A);
-        g_B = wave_sum_dpp(g_B); g_C = wave_sum_dpp(g_C); g_o = wave_sum_dpp(g_o);
-        g_r = wave_sum_dpp(g_r); g_g = wave_sum_dpp(g_g); g_b = wave_sum_dpp(g_b);
-        if (lane == kWave - 1) {
-          float* G = (NW > 1) ? s_g[j] : reinterpret_cast<float*>(a.g2d + 3 * (size_t)s_rec[j]);
-          atomicAdd(G + 0, g_u); atomicAdd(G + 1, g_v); atomicAdd(G + 2, g_A);
-          atomicAdd(G + 3, g_B); atomicAdd(G + 4, g_C); atomicAdd(G + 5, g_o);
-          atomicAdd(G + 6, g_r); atomicAdd(G + 7, g_g); atomicAdd(G + 8, g_b);
-        }
-      }
-    }
-    if (NW > 1) {
-      __syncthreads();
-      // one set of global atomics per record and tile
+  // windows of the list, back to front; inside a window every wave walks
+  // its entries in batches of 64 and adds each record's wave total into the
+  // shared window slot, which is flushed with one set of global atomics
+  for (int64_t w_end = tile_end; w_end > s; w_end -= WIN) {
+    const int64_t w0 = max(s, w_end - WIN);
+    for (int64_t b_end = min(w_end, wave_end); b_end > w0; b_end -= kWave) {
+      const int64_t b0 = max(w0, b_end - kWave);
+      const int64_t idx = b0 + lane;
+      float4 g = make_float4(0.f, 0.f, 0.f, 0.f), c = g, col = g;
+      bool near = false;
       if (idx < b_end) {
-        const float* G = s_g[tid];
-        bool any = false;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) any |= (G[q] != 0.f);
-        if (any) {
-          float* D = reinterpret_cast<float*>(a.g2d + 3 * (size_t)s_rec[tid]);
-#pragma unroll
-          for (int q = 0; q < 9; ++q)
-            if (G[q] != 0.f) atomicAdd(D + q, G[q]);
+        const uint32_t r = a.vals[idx];
+        g = a.rec_geo[r];
+        c = a.rec_conic[r];
+        near = box_hits(cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff), sub_x, sub_y);
+        if (near) col = a.rec_rgb[r];
+      }
+      uint64_t m = ballot(near);
+      while (m != 0ull) {
+        const int j = 63 - __builtin_clzll(m);  // back to front
+        m &= ~(1ull << j);
+        const float u = bcast(g.x, j), vv = bcast(g.y, j), o = bcast(g.z, j);
+        const float A = bcast(c.x, j), B = bcast(c.y, j), C = bcast(c.z, j);
+        const float kr = bcast(col.x, j), kg = bcast(col.y, j), kb = bcast(col.z, j);
+        const int pos = (int)(b0 - s) + j;
+        const Blend bl = blend_eval(u, vv, A, B, C, o, fxp, fyp, a.kp);
+        const bool contrib = bl.hit && (pos < last);
+        if (ballot(contrib) == 0ull) continue;
+        const float one_m = 1.0f - bl.alpha;
+        const float rinv = 1.0f / one_m;
+        const float Tb = T * rinv;
+        const float wgt = bl.alpha * Tb;
+        const float cdot = kr * dCr + kg * dCg + kb * dCb;
+        const float sdot = Sr * dCr + Sg * dCg + Sb * dCb;
+        const float dal = Tb * cdot - (sdot + bgdot) * rinv;
+        // alpha clamped at alpha_max carries no gradient to o and the conic
+        const bool open = contrib && (bl.raw <= a.kp.alpha_max);
+        const float dx = u - fxp;
+        const float dy = vv - fyp;
+        const float dpow = open ? dal * bl.alpha : 0.f;
+        const float g_r = contrib ? wgt * dCr : 0.f;
+        const float g_g = contrib ? wgt * dCg : 0.f;
+        const float g_b = contrib ? wgt * dCb : 0.f;
+        const float g_o = open ? dal * bl.ex : 0.f;
+        const float g_u = -dpow * (A * dx + B * dy);
+        const float g_v = -dpow * (C * dy + B * dx);
+        const float g_A = -0.5f * dpow * dx * dx;
+        const float g_B = -dpow * dx * dy;
+        const float g_C = -0.5f * dpow * dy * dy;
+        Sr = contrib ? fmaf(kr, wgt, Sr) : Sr;
+        Sg = contrib ? fmaf(kg, wgt, Sg) : Sg;
+        Sb = contrib ? fmaf(kb, wgt, Sb) : Sb;
+        T = contrib ? Tb : T;
+        // rows of s1 hold u, A, v, B and rows of s2 C, r, o, g; b ends in lane 63
+        const float s1 = wave_sum4(g_u, g_v, g_A, g_B);
+        const float s2 = wave_sum4(g_C, g_o, g_r, g_g);
+        const float sb = wave_sum_dpp(g_b);
+        if ((lane & 15) == 15) {
+          float* G = s_g[(int)(b0 - w0) + j];
+          const int row = lane >> 4;
+          const int q = ((row & 1) << 1) | (row >> 1);
+          atomicAdd(G + q, s1);
+          atomicAdd(G + 4 + q, s2);
+          if (row == 3) atomicAdd(G + 8, sb);
         }
       }
     }
+    __syncthreads();
+    for (int k = tid; k < (int)(w_end - w0); k += NT) {
+      float* G = s_g[k];
+      float gv[9];
+      bool any = false;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        gv[q] = G[q];
+        any |= (gv[q] != 0.f);
+        G[q] = 0.f;
+      }
+      if (any) {
+        float* D = reinterpret_cast<float*>(a.g2d + 3 * (size_t)a.vals[w0 + k]);
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+          if (gv[q] != 0.f) atomicAdd(D + q, gv[q]);
+      }
+    }
+    __syncthreads();
   }
 }
 

@@ -24,6 +24,10 @@ constexpr int kMaxViews = 64;
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+// value of x in lane j (j wave-uniform), as a scalar operand
+__device__ __forceinline__ float bcast(float x, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+}
 
 // number of set bits of `mask` below this lane
 __device__ __forceinline__ int lane_rank(uint64_t mask) {
@@ -51,6 +55,28 @@ __device__ __forceinline__ float wave_sum_dpp(float x) {
   x = dpp_add<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
   x = dpp_add<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
   return x;
+}
+
+// Four wave-wide sums at once: a permlane32 swap pairs x with y and z with w
+// (each register then holds one value's half-sums in lanes 0-31 and the
+// other's in lanes 32-63), a permlane16 swap pairs the two results, and DPP
+// row sums finish.  On return every lane of row k (lanes 16k..16k+15) holds
+// the wave total of x (k = 0), z (k = 1), y (k = 2) or w (k = 3).
+__device__ __forceinline__ float wave_sum4(float x, float y, float z, float w) {
+  const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(z), __float_as_uint(w), false,
+                                                  false);
+  const float xy = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  const float zw = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(xy), __float_as_uint(zw), false,
+                                                  false);
+  float s = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  s = dpp_add<0xB1, 0xf>(s);   // quad_perm [1,0,3,2]
+  s = dpp_add<0x4E, 0xf>(s);   // quad_perm [2,3,0,1]
+  s = dpp_add<0x124, 0xf>(s);  // row_ror:4
+  s = dpp_add<0x128, 0xf>(s);  // row_ror:8
+  return s;
 }
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
@@ -298,19 +324,16 @@ struct Blend {
 
 __device__ __forceinline__ Blend blend_eval(float u, float v, float A, float Bc, float C, float o,
                                             float px, float py, const KParams& kp) {
+  // evaluated without branches: the exponential is taken even past the cut
+  // (its value is then unused), so a wave needs no divergent control flow
   Blend b;
   const float dx = u - px;
   const float dy = v - py;
   b.power = fmaf(-0.5f, fmaf(A * dx, dx, C * dy * dy), -Bc * dx * dy);
-  b.ex = 0.f;
-  b.raw = 0.f;
-  b.alpha = 0.f;
-  b.hit = false;
-  if (-b.power > kp.cutoff) return b;
   b.ex = __expf(b.power);
   b.raw = o * b.ex;
   b.alpha = fminf(kp.alpha_max, b.raw);
-  b.hit = !(b.alpha < kp.alpha_min);
+  b.hit = !(-b.power > kp.cutoff) && !(b.alpha < kp.alpha_min);
   return b;
 }
 
@@ -322,6 +345,9 @@ struct RasterShape {
   static constexpr int NT = TS * TS;
   static constexpr int SUB = TS / 8;  // sub-tiles per row
   static constexpr int NW = NT / 64;
+  // list entries whose gradients the raster backward accumulates in LDS at
+  // once (36 B each; 18 KB for a 16x16 tile keeps eight workgroups per CU)
+  static constexpr int WIN = 2 * NT;
 };
 template <int TS>
 __device__ __forceinline__ void raster_pixel(int tid, int& ox, int& oy, int& sx, int& sy) {

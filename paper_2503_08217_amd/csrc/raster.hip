@@ -2,25 +2,21 @@
 // one launch.
 //
 // One workgroup per tile, one thread per pixel; each wave64 owns an 8x8
-// sub-tile of the 16x16 tile.  The tile's sorted list is consumed in
-// batches: each thread stages one record (mean, conic, opacity, colour and the
-// bounding box of its cutoff ellipse) in LDS, then every wave blends the batch
-// into its pixels, skipping -- uniformly across the wave -- records whose box
-// misses its sub-tile (no pixel there could pass the Mahalanobis cut).  The
-// loop ends as soon as every pixel of the tile has reached the transmittance
-// floor.  Pixels are sampled at integer coordinates (x, y).
+// sub-tile of the 16x16 tile and walks the tile's sorted list independently
+// of the other waves (no LDS, no barriers).  A batch of 64 entries is fetched
+// lane-parallel; entries whose cutoff box misses the sub-tile (no pixel there
+// could pass the Mahalanobis cut) are dropped with one ballot, and the rest
+// are broadcast from their lane into scalar registers and blended in list
+// order.  A wave stops once all its pixels reached the transmittance floor.
+// Pixels are sampled at integer coordinates (x, y).
 #include "internal.hpp"
 
 namespace s3r {
 
 template <int TS>
 __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_fwd(RasterArgs a) {
-  constexpr int NT = RasterShape<TS>::NT;
-  __shared__ float4 s_geo[NT];  // u, v, opacity
-  __shared__ float4 s_con[NT];  // A, B, C
-  __shared__ float4 s_rgb[NT];
-  __shared__ float4 s_box[NT];  // cutoff bounding box
   const int tid = threadIdx.x;
+  const int lane = tid % kWave;
   const int t = blockIdx.x;
   const int v = find_view(a.tile_offset, a.nv, t);
   const int lt = t - a.tile_offset[v];
@@ -39,42 +35,40 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_fwd(RasterArgs a
   float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f;
   bool done = !inside;
   int last = 0;
-  for (int64_t b0 = s; b0 < e; b0 += NT) {
-    if (__syncthreads_count(done) == NT) break;
-    const int64_t idx = b0 + tid;
+  // Each wave walks the tile's list on its own, 64 entries at a time: lane l
+  // fetches entry b0 + l, one ballot keeps the entries whose cutoff box
+  // meets the wave's sub-tile, and those are broadcast lane by lane.
+  for (int64_t b0 = s; b0 < e; b0 += kWave) {
+    if (ballot(!done) == 0ull) break;
+    const int64_t idx = b0 + lane;
+    float4 g = make_float4(0.f, 0.f, 0.f, 0.f), c = g, col = g;
+    bool near = false;
     if (idx < e) {
       const uint32_t r = a.vals[idx];
-      const float4 g = a.rec_geo[r];
-      const float4 c = a.rec_conic[r];
-      s_geo[tid] = g;
-      s_con[tid] = c;
-      s_rgb[tid] = a.rec_rgb[r];
-      s_box[tid] = cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff);
+      g = a.rec_geo[r];
+      c = a.rec_conic[r];
+      near = box_hits(cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff), sub_x, sub_y);
+      if (near) col = a.rec_rgb[r];
     }
-    __syncthreads();
-    const int nb = (int)min((int64_t)NT, e - b0);
-    // the wave walks the batch while any of its pixels is still open
-    if (ballot(!done) != 0ull) {
-      for (int j = 0; j < nb; ++j) {
-        if (!box_hits(s_box[j], sub_x, sub_y)) continue;  // uniform across the wave
-        if (done) continue;
-        const float4 g = s_geo[j];
-        const float4 c = s_con[j];
-        const Blend bl = blend_eval(g.x, g.y, c.x, c.y, c.z, g.z, fxp, fyp, a.kp);
-        if (!bl.hit) continue;
-        const float Tn = T * (1.0f - bl.alpha);
-        if (Tn < a.kp.t_min) {
-          done = true;
-          continue;
-        }
-        const float4 col = s_rgb[j];
-        const float w = bl.alpha * T;
-        cr = fmaf(col.x, w, cr);
-        cg = fmaf(col.y, w, cg);
-        cb = fmaf(col.z, w, cb);
-        T = Tn;
-        last = (int)(b0 - s) + j + 1;
-      }
+    uint64_t m = ballot(near);
+    while (m != 0ull) {
+      const int j = __builtin_ctzll(m);
+      m &= m - 1ull;
+      const float u = bcast(g.x, j), vv = bcast(g.y, j), o = bcast(g.z, j);
+      const float A = bcast(c.x, j), B = bcast(c.y, j), C = bcast(c.z, j);
+      const float kr = bcast(col.x, j), kg = bcast(col.y, j), kb = bcast(col.z, j);
+      const Blend bl = blend_eval(u, vv, A, B, C, o, fxp, fyp, a.kp);
+      const bool hit = bl.hit && !done;
+      const float Tn = T * (1.0f - bl.alpha);
+      const bool stop = Tn < a.kp.t_min;  // this entry would push T under the floor
+      const bool take = hit && !stop;
+      done = done || (hit && stop);
+      const float w = bl.alpha * T;
+      cr = take ? fmaf(kr, w, cr) : cr;
+      cg = take ? fmaf(kg, w, cg) : cg;
+      cb = take ? fmaf(kb, w, cb) : cb;
+      T = take ? Tn : T;
+      last = take ? (int)(b0 - s) + j + 1 : last;
     }
   }
   if (inside) {
@@ -113,39 +107,56 @@ hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // per-view mean absolute error and its gradient
 // ---------------------------------------------------------------------------
+// Each workgroup takes one contiguous range of pixels, so a thread's view
+// changes rarely; per-thread sums are reduced over the wave when its lanes
+// share a view, then per workgroup, and a workgroup adds one value per view it
+// touched to the loss (few same-address atomics: they serialise).
 __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ color,
                                             const float* __restrict__ target,
                                             const int64_t* __restrict__ pxo,
                                             const int32_t* __restrict__ wh, int nv, int64_t total,
-                                            float* __restrict__ loss, float* __restrict__ dcol) {
+                                            int64_t chunk, float* __restrict__ loss,
+                                            float* __restrict__ dcol) {
   __shared__ float s_loss[kMaxViews];
   for (int v = threadIdx.x; v < nv; v += blockDim.x) s_loss[v] = 0.f;
   __syncthreads();
-  int cur = -1;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = min(total, lo + chunk);
+  int cur = 0;
+  while (cur + 1 < nv && pxo[cur + 1] <= lo) ++cur;
+  int64_t vend = cur + 1 < nv ? pxo[cur + 1] : total;
+  int64_t npx = (int64_t)wh[2 * cur] * wh[2 * cur + 1];
+  int64_t vb = pxo[cur];
+  float inv = 1.0f / (3.0f * (float)npx);
   float acc = 0.f;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    int v = 0;
-    while (v + 1 < nv && pxo[v + 1] <= i) ++v;
-    if (v != cur) {
-      if (cur >= 0) atomicAdd(&s_loss[cur], acc);
-      cur = v;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    if (i >= vend) {
+      atomicAdd(&s_loss[cur], acc);
       acc = 0.f;
+      while (cur + 1 < nv && pxo[cur + 1] <= i) ++cur;
+      vend = cur + 1 < nv ? pxo[cur + 1] : total;
+      npx = (int64_t)wh[2 * cur] * wh[2 * cur + 1];
+      vb = pxo[cur];
+      inv = 1.0f / (3.0f * (float)npx);
     }
-    const int64_t npx = (int64_t)wh[2 * v] * wh[2 * v + 1];
-    const int64_t loc = i - pxo[v];
-    const float inv = 1.0f / (3.0f * (float)npx);
+    const int64_t loc = i - vb;
     float a = 0.f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const int64_t q = 3 * pxo[v] + c * npx + loc;
+      const int64_t q = 3 * vb + c * npx + loc;
       const float d = color[q] - target[q];
       a += fabsf(d);
       dcol[q] = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
     }
     acc += a * inv;
   }
-  if (cur >= 0) atomicAdd(&s_loss[cur], acc);
+  const int c0 = __shfl(cur, 0, kWave);
+  if (ballot(cur != c0) == 0ull) {
+    acc = wave_sum_dpp(acc);
+    if ((threadIdx.x % kWave) == kWave - 1) atomicAdd(&s_loss[cur], acc);
+  } else {
+    atomicAdd(&s_loss[cur], acc);
+  }
   __syncthreads();
   for (int v = threadIdx.x; v < nv; v += blockDim.x)
     if (s_loss[v] != 0.f) atomicAdd(loss + v, s_loss[v]);
@@ -156,11 +167,12 @@ hipError_t launch_l1_loss(const float* color, const float* target, const int64_t
                           float* d_color, hipStream_t st) {
   hipError_t e = launch_zero(loss, (size_t)nv * 4, nullptr, 0, nullptr, 0, nullptr, 0, st);
   if (e != hipSuccess) return e;
-  int64_t grid = (total_px + 255) / 256;
-  if (grid > 1024) grid = 1024;
-  if (grid > 0)
-    S3R_LAUNCH(K_L1, k_l1, dim3((unsigned)grid), dim3(256), 0, st, color, target, px_offset, wh,
-                       nv, total_px, loss, d_color);
+  if (total_px <= 0) return hipGetLastError();
+  // about 512 workgroups of 256 threads, each over a contiguous range
+  const int64_t chunk = max((int64_t)256 * 8, ((total_px + 511) / 512 + 255) / 256 * 256);
+  const int64_t grid = (total_px + chunk - 1) / chunk;
+  S3R_LAUNCH(K_L1, k_l1, dim3((unsigned)grid), dim3(256), 0, st, color, target, px_offset, wh, nv,
+             total_px, chunk, loss, d_color);
   return hipGetLastError();
 }
 

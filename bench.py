@@ -439,7 +439,7 @@ def main():
                 "avg_us": 1000 * dms / dcnt, "work": basis,
                 "sources_sha256_16": sources_digest(dname)}
     pcs_names = ("compose", "project", "block_offsets", "records", "scan", "emit_pairs", "radix",
-                 "tile_ranges", "dup_stats")
+                 "tile_ranges", "tile_order")
     # warm-up steps (every kernel timed) give the project/cull/sort time
     pcs_ms = sum(table[k][0] for k in pcs_names if k in table)
     pcs_gbs = pcs_bytes(units, a.warmup, cfg.scene.sh_degree, cfg.scene.n) / (pcs_ms * 1e-3) / 1e9

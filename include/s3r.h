@@ -176,6 +176,8 @@ typedef struct S3RBins {
   int32_t* tile_count; /* [total_tiles] number of records covering each tile */
   int32_t* tile_start; /* [total_tiles+1] start of each tile's list          */
   uint32_t* vals;      /* [cap_dup] record index of each list entry, sorted  */
+  int32_t* tile_order; /* [total_tiles] tiles by descending list length (the
+                          rasterizer's launch order; ties in tile order)      */
 } S3RBins;
 
 typedef struct S3RImage {

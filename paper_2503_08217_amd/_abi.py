@@ -52,7 +52,7 @@ class S3RProjected(C.Structure):
 
 
 class S3RBins(C.Structure):
-    _fields_ = [("tile_count", P), ("tile_start", P), ("vals", P)]
+    _fields_ = [("tile_count", P), ("tile_start", P), ("vals", P), ("tile_order", P)]
 
 
 class S3RImage(C.Structure):

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
   __shared__ int s_max[NW];
   const int tid = threadIdx.x;
   const int lane = tid % kWave, wave = tid / kWave;
-  const int t = blockIdx.x;
+  const int t = a.tile_order[blockIdx.x];
   const int v = find_view(a.tile_offset, a.nv, t);
   const int lt = t - a.tile_offset[v];
   const int W = a.wh[2 * v], H = a.wh[2 * v + 1];
@@ -77,23 +77,43 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
   const int64_t tile_end = min(e, s + (int64_t)nrep);
   const int64_t wave_end = min(e, s + (int64_t)mw);
 
-  // windows of the list, back to front; inside a window every wave walks
-  // its entries in batches of 64 and adds each record's wave total into the
-  // shared window slot, which is flushed with one set of global atomics
-  for (int64_t w_end = tile_end; w_end > s; w_end -= WIN) {
-    const int64_t w0 = max(s, w_end - WIN);
-    for (int64_t b_end = min(w_end, wave_end); b_end > w0; b_end -= kWave) {
-      const int64_t b0 = max(w0, b_end - kWave);
-      const int64_t idx = b0 + lane;
-      float4 g = make_float4(0.f, 0.f, 0.f, 0.f), c = g, col = g;
-      bool near = false;
-      if (idx < b_end) {
-        const uint32_t r = a.vals[idx];
-        g = a.rec_geo[r];
-        c = a.rec_conic[r];
-        near = box_hits(cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff), sub_x, sub_y);
-        if (near) col = a.rec_rgb[r];
+  // Batches are the 64-entry blocks [s + 64 m, s + 64 m + 64) of the list and
+  // windows the WIN-entry blocks [s + WIN k, s + WIN k + WIN); both are walked
+  // back to front.  Inside a window every wave replays its batches (those
+  // below its own end) and adds each record's wave total into the shared
+  // window slot, flushed with one set of global atomics.  Loads are pipelined:
+  // record ids two batches ahead, record fields one batch ahead.
+  constexpr int BPW = WIN / kWave;  // batches per window
+  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  int mb = (int)((wave_end - s + kWave - 1) / kWave) - 1;  // next batch of this wave
+  uint32_t rn = 0u;
+  float4 gn = zero4, cn = zero4, kn = zero4;
+  if (mb >= 0) {
+    const int64_t i0 = s + (int64_t)mb * kWave + lane;
+    if (i0 < wave_end) {
+      rn = a.vals[i0];
+      gn = a.rec_geo[rn];
+      cn = a.rec_conic[rn];
+      kn = a.rec_rgb[rn];
+    }
+    rn = mb >= 1 ? a.vals[s + (int64_t)(mb - 1) * kWave + lane] : 0u;
+  }
+  const int nwin = (int)((tile_end - s + WIN - 1) / WIN);
+  for (int wi = nwin - 1; wi >= 0; --wi) {
+    const int64_t w0 = s + (int64_t)wi * WIN;
+    const int64_t w_end = min(tile_end, w0 + WIN);
+    for (; mb >= wi * BPW; --mb) {
+      const int64_t b0 = s + (int64_t)mb * kWave;
+      const bool valid = b0 + lane < wave_end;
+      const float4 g = gn, c = cn, col = kn;
+      if (mb >= 1) {
+        gn = a.rec_geo[rn];
+        cn = a.rec_conic[rn];
+        kn = a.rec_rgb[rn];
       }
+      rn = mb >= 2 ? a.vals[b0 - 2 * kWave + lane] : 0u;
+      const bool near =
+          valid && box_hits(cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff), sub_x, sub_y);
       uint64_t m = ballot(near);
       while (m != 0ull) {
         const int j = 63 - __builtin_clzll(m);  // back to front

@@ -294,6 +294,7 @@ int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* vi
   S3R_REQUIRE(proj->rec_npairs);
   S3R_REQUIRE(bins->tile_count);
   S3R_REQUIRE(bins->tile_start);
+  S3R_REQUIRE(bins->tile_order);
   S3R_REQUIRE(bins->vals);
   const S3RSizes z = sizes_of(nullptr, views, params);
   if (!ws || ws_bytes < ws_sort(z, nullptr, nullptr)) return S3R_E_WORKSPACE;
@@ -314,6 +315,7 @@ int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* vi
   a.stats = proj->stats;
   a.tile_count = bins->tile_count;
   a.tile_start = bins->tile_start;
+  a.tile_order = bins->tile_order;
   a.pair_off = w.pair_off;
   a.keys = w.keys;
   a.keys_alt = w.keys_alt;
@@ -341,6 +343,7 @@ int s3r_raster_fwd(const S3RProjected* proj, const S3RBins* bins, const S3RViews
   S3R_REQUIRE(proj->rec_rgb);
   S3R_REQUIRE(proj->counters);
   S3R_REQUIRE(bins->tile_start);
+  S3R_REQUIRE(bins->tile_order);
   S3R_REQUIRE(bins->vals);
   S3R_REQUIRE(img->color);
   S3R_REQUIRE(img->T_final);
@@ -350,6 +353,7 @@ int s3r_raster_fwd(const S3RProjected* proj, const S3RBins* bins, const S3RViews
   a.rec_conic = reinterpret_cast<const float4*>(proj->rec_conic);
   a.rec_rgb = reinterpret_cast<const float4*>(proj->rec_rgb);
   a.tile_start = bins->tile_start;
+  a.tile_order = bins->tile_order;
   a.vals = bins->vals;
   a.tile_offset = views->tile_offset;
   a.px_offset = views->px_offset;
@@ -401,6 +405,7 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   S3R_REQUIRE(proj->rec_rgb);
   S3R_REQUIRE(proj->counters);
   S3R_REQUIRE(bins->tile_start);
+  S3R_REQUIRE(bins->tile_order);
   S3R_REQUIRE(bins->vals);
   S3R_REQUIRE(g->scale);
   S3R_REQUIRE(g->opacity);
@@ -431,6 +436,7 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   b.rec_gid = proj->rec_gid;
   b.rec_view = proj->rec_view;
   b.tile_start = bins->tile_start;
+  b.tile_order = bins->tile_order;
   b.vals = bins->vals;
   b.tile_offset = views->tile_offset;
   b.px_offset = views->px_offset;

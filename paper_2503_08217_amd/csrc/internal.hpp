@@ -9,7 +9,7 @@ namespace s3r {
 // kernels timed by the opt-in profiler (names in profile.hip)
 enum KernelId {
   K_COMPOSE, K_PLAIN_TRANSFORM, K_PROJECT, K_STATS, K_RECORDS, K_SCAN, K_EMIT, K_RADIX,
-  K_TILE_RANGES, K_DUP_STATS, K_RASTER_FWD, K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PROJECT_BWD,
+  K_TILE_RANGES, K_TILE_ORDER, K_RASTER_FWD, K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PROJECT_BWD,
   K_POSE_BWD, K_POSE6, K_PLAIN_TRANSFORM_BWD, K_VISIBILITY, K_ZERO, K_COUNT
 };
 void prof_begin(int id, hipStream_t st);
@@ -71,6 +71,7 @@ struct RasterArgs {
   const float4* rec_conic;
   const float4* rec_rgb;
   const int32_t* tile_start;
+  const int32_t* tile_order;
   const uint32_t* vals;
   const int32_t* tile_offset;
   const int64_t* px_offset;
@@ -91,6 +92,7 @@ struct BwdArgs {
   const int32_t* rec_gid;
   const int32_t* rec_view;
   const int32_t* tile_start;
+  const int32_t* tile_order;
   const uint32_t* vals;
   const int32_t* tile_offset;
   const int64_t* px_offset;
@@ -167,6 +169,7 @@ struct SortArgs {
   int32_t* stats;
   int32_t* tile_count;
   int32_t* tile_start;
+  int32_t* tile_order;
   // workspace
   int32_t* pair_off;   // [cap_surv]
   uint64_t* keys;      // [cap_dup]

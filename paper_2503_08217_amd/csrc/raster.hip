@@ -17,7 +17,7 @@ template <int TS>
 __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_fwd(RasterArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
-  const int t = blockIdx.x;
+  const int t = a.tile_order[blockIdx.x];
   const int v = find_view(a.tile_offset, a.nv, t);
   const int lt = t - a.tile_offset[v];
   const int W = a.wh[2 * v], H = a.wh[2 * v + 1];
@@ -36,20 +36,30 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_fwd(RasterArgs a
   bool done = !inside;
   int last = 0;
   // Each wave walks the tile's list on its own, 64 entries at a time: lane l
-  // fetches entry b0 + l, one ballot keeps the entries whose cutoff box
-  // meets the wave's sub-tile, and those are broadcast lane by lane.
+  // holds entry b0 + l, one ballot keeps the entries whose cutoff box meets
+  // the wave's sub-tile, and those are broadcast lane by lane.  Loads are
+  // pipelined: record ids two batches ahead, record fields one batch ahead.
+  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  uint32_t rn = (s + lane < e) ? a.vals[s + lane] : 0u;
+  float4 gn = zero4, cn = zero4, kn = zero4;
+  if (s + lane < e) {
+    gn = a.rec_geo[rn];
+    cn = a.rec_conic[rn];
+    kn = a.rec_rgb[rn];
+  }
+  rn = (s + kWave + lane < e) ? a.vals[s + kWave + lane] : 0u;
   for (int64_t b0 = s; b0 < e; b0 += kWave) {
     if (ballot(!done) == 0ull) break;
-    const int64_t idx = b0 + lane;
-    float4 g = make_float4(0.f, 0.f, 0.f, 0.f), c = g, col = g;
-    bool near = false;
-    if (idx < e) {
-      const uint32_t r = a.vals[idx];
-      g = a.rec_geo[r];
-      c = a.rec_conic[r];
-      near = box_hits(cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff), sub_x, sub_y);
-      if (near) col = a.rec_rgb[r];
+    const float4 g = gn, c = cn, col = kn;
+    const bool valid = b0 + lane < e;
+    if (b0 + kWave + lane < e) {
+      gn = a.rec_geo[rn];
+      cn = a.rec_conic[rn];
+      kn = a.rec_rgb[rn];
     }
+    rn = (b0 + 2 * kWave + lane < e) ? a.vals[b0 + 2 * kWave + lane] : 0u;
+    const bool near =
+        valid && box_hits(cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff), sub_x, sub_y);
     uint64_t m = ballot(near);
     while (m != 0ull) {
       const int j = __builtin_ctzll(m);

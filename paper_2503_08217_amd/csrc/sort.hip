@@ -305,10 +305,59 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
   }
 }
 
-__global__ void k_dup_stats(const int32_t* __restrict__ start, const int32_t* __restrict__ toff,
-                            int nv, int32_t* __restrict__ stats) {
-  const int v = threadIdx.x;
-  if (v < nv) stats[v * 4 + 3] = start[toff[v + 1]] - start[toff[v]];
+// Launch order of the rasterizer: tiles by descending list length, so the
+// longest lists (whose waves set the critical path) start first.  Lengths are
+// bucketed by their binary logarithm (empty lists last) and the order within
+// a bucket is the tile order: a stable counting sort in one workgroup, each
+// thread owning a contiguous run of tiles.  Also writes each view's number
+// of (tile, record) pairs.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 17;
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const int32_t* __restrict__ start,
+                                                             int total_tiles,
+                                                             const int32_t* __restrict__ toff,
+                                                             int nv, int32_t* __restrict__ order,
+                                                             int32_t* __restrict__ stats) {
+  __shared__ int cnt[kOrderBuckets * kOrderThreads];
+  __shared__ int s_part[kOrderThreads / kWave];
+  const int i = threadIdx.x;
+  const int chunk = (total_tiles + kOrderThreads - 1) / kOrderThreads;
+  const int lo = min(total_tiles, i * chunk), hi = min(total_tiles, lo + chunk);
+  auto bucket = [&](int t) {
+    const int len = start[t + 1] - start[t];
+    return len <= 0 ? kOrderBuckets - 1 : 15 - min(15, 31 - __builtin_clz((unsigned)len));
+  };
+  for (int b = 0; b < kOrderBuckets; ++b) cnt[b * kOrderThreads + i] = 0;
+  for (int t = lo; t < hi; ++t) cnt[bucket(t) * kOrderThreads + i] += 1;
+  __syncthreads();
+  // exclusive scan of cnt in (bucket, thread) order: thread i scans the
+  // kOrderBuckets consecutive entries starting at i * kOrderBuckets
+  int run = 0;
+  for (int k = 0; k < kOrderBuckets; ++k) run += cnt[i * kOrderBuckets + k];
+  int incl = run;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(incl, o, kWave);
+    if ((i % kWave) >= o) incl += y;
+  }
+  if ((i % kWave) == kWave - 1) s_part[i / kWave] = incl;
+  __syncthreads();
+  int base = incl - run;
+  for (int w = 0; w < i / kWave; ++w) base += s_part[w];
+  __syncthreads();
+  for (int k = 0; k < kOrderBuckets; ++k) {
+    const int c = cnt[i * kOrderBuckets + k];
+    cnt[i * kOrderBuckets + k] = base;
+    base += c;
+  }
+  __syncthreads();
+  for (int t = lo; t < hi; ++t) {
+    const int b = bucket(t);
+    const int pos = cnt[b * kOrderThreads + i];
+    cnt[b * kOrderThreads + i] = pos + 1;
+    order[pos] = t;
+  }
+  if (i < nv) stats[i * 4 + 3] = start[toff[i + 1]] - start[toff[i]];
 }
 
 int radix_passes(int total_tiles) {
@@ -355,8 +404,8 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
     S3R_LAUNCH(K_TILE_RANGES, k_tile_ranges, dim3(grid), dim3(256), 0, st, sorted,
                a.counters + S3R_CNT_DUP, a.total_tiles, a.tile_start, a.tile_count);
   }
-  S3R_LAUNCH(K_DUP_STATS, k_dup_stats, dim3(1), dim3(64), 0, st, a.tile_start, a.tile_offset, a.nv,
-             a.stats);
+  S3R_LAUNCH(K_TILE_ORDER, k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, a.tile_start,
+             a.total_tiles, a.tile_offset, a.nv, a.tile_order, a.stats);
   return hipGetLastError();
 }
 

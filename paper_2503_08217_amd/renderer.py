@@ -146,6 +146,7 @@ class Renderer:
         self.rec_npairs = torch.zeros(cs, device=d, dtype=i32)
         self.tile_count = torch.zeros(self.total_tiles, device=d, dtype=i32)
         self.tile_start = torch.zeros(self.total_tiles + 1, device=d, dtype=i32)
+        self.tile_order = torch.zeros(max(1, self.total_tiles), device=d, dtype=i32)
         self.vals = torch.zeros(cd, device=d, dtype=i32)
         self.color = torch.zeros(3 * self.total_px, device=d, dtype=f32)
         self.T_final = torch.zeros(self.total_px, device=d, dtype=f32)
@@ -192,7 +193,8 @@ class Renderer:
             _ptr(self.cam), _ptr(self.cen), _ptr(self.t_norm), _ptr(self.mask), _ptr(self.rec_gid),
             _ptr(self.rec_view), _ptr(self.rec_geo), _ptr(self.rec_conic), _ptr(self.rec_rgb),
             _ptr(self.rec_rect), _ptr(self.counters), _ptr(self.stats), _ptr(self.rec_npairs))
-        self.c_bins = A.S3RBins(_ptr(self.tile_count), _ptr(self.tile_start), _ptr(self.vals))
+        self.c_bins = A.S3RBins(_ptr(self.tile_count), _ptr(self.tile_start), _ptr(self.vals),
+                                _ptr(self.tile_order))
         self.c_img = A.S3RImage(_ptr(self.color), _ptr(self.T_final), _ptr(self.last))
         self.c_grads = A.S3RGrads(
             _ptr(self.g_mean), _ptr(self.g_scale), _ptr(self.g_quat), _ptr(self.g_opacity),

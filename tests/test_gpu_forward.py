@@ -153,9 +153,8 @@ def test_batched_uneven_views_equal_single_views():
 
 @pytest.mark.parametrize("n", [9000, 30000])
 def test_crowded_tiles_sorted_exactly(n):
-    """Tens of thousands of Gaussians pile into a few tiles: lists longer than
-    the LDS sort take the chunk-sort + merge-pass path and must still match
-    the oracle's order bit for bit."""
+    """Tens of thousands of Gaussians pile into a few tiles: lists spanning
+    many radix-sort blocks must still match the oracle's order bit for bit."""
     scene, views = scenes.micro_scene(11, n=n, width=64, height=48, n_inst=0, spread=0.05, T=1)
     p = scenes.default_params(tile=16)
     banner(f"crowded tiles n={n}")
@@ -165,6 +164,25 @@ def test_crowded_tiles_sorted_exactly(n):
     counts = r.tile_count.cpu().numpy()
     assert counts.max() > 4096
     check_view(scene, views, p, r, rec, 0, region=(16, 16, 48, 40))
+
+
+def test_tile_launch_order():
+    """The rasterizer's launch order: every tile once, by descending binary
+    logarithm of its list length (empty lists last), tile order within a
+    bucket; and the per-view pair counts it reports."""
+    c = scenes.make_config(2, scale_n=0.05)
+    views = c.views.subset([4, 22, 39])
+    banner("tile launch order")
+    r = make_renderer(c.scene, views, c.params)
+    r.forward()
+    start = r.tile_start.cpu().numpy().astype(np.int64)
+    order = r.tile_order.cpu().numpy()[: r.total_tiles]
+    n = np.diff(start)
+    key = np.where(n > 0, 15 - np.minimum(15, np.floor(np.log2(np.maximum(n, 1))).astype(int)), 16)
+    np.testing.assert_array_equal(order, np.lexsort((np.arange(n.size), key)))
+    toff = r.tile_offset.cpu().numpy().astype(np.int64)
+    st = r.stats.cpu().numpy()
+    np.testing.assert_array_equal(st[:, 3], start[toff[1:]] - start[toff[:-1]])
 
 
 def test_stochastic_lod_parity():

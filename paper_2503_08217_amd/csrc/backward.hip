@@ -32,7 +32,9 @@ template <int TS>
 __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
   constexpr int NT = RasterShape<TS>::NT, NW = RasterShape<TS>::NW;
   constexpr int WIN = RasterShape<TS>::WIN;
-  __shared__ float s_g[WIN][9];  // gradient of list entries [w0, w0 + WIN), all waves
+  // per list entry of the window [w0, w0 + WIN), summed over the tile's waves:
+  // moments m_x, m_y, m_xx, m_xy, m_yy, then d opacity and d rgb
+  __shared__ float s_g[WIN][9];
   __shared__ int s_max[NW];
   const int tid = threadIdx.x;
   const int lane = tid % kWave, wave = tid / kWave;
@@ -126,34 +128,32 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
         const bool contrib = bl.hit && (pos < last);
         if (ballot(contrib) == 0ull) continue;
         const float one_m = 1.0f - bl.alpha;
-        const float rinv = 1.0f / one_m;
+        const float rinv = __builtin_amdgcn_rcpf(one_m);  // one_m >= 1 - alpha_max
         const float Tb = T * rinv;
-        const float wgt = bl.alpha * Tb;
+        const float wgt = contrib ? bl.alpha * Tb : 0.f;
         const float cdot = kr * dCr + kg * dCg + kb * dCb;
         const float sdot = Sr * dCr + Sg * dCg + Sb * dCb;
         const float dal = Tb * cdot - (sdot + bgdot) * rinv;
         // alpha clamped at alpha_max carries no gradient to o and the conic
         const bool open = contrib && (bl.raw <= a.kp.alpha_max);
+        const float dpow = open ? dal * bl.alpha : 0.f;
+        const float g_o = open ? dal * bl.ex : 0.f;
+        // d power / d(u, v, A, B, C) are linear in the conic, so the wave sums
+        // the moments dpow (dx, dy, dx^2, dx dy, dy^2) and the conic is applied
+        // once per record when the window is flushed
         const float dx = u - fxp;
         const float dy = vv - fyp;
-        const float dpow = open ? dal * bl.alpha : 0.f;
-        const float g_r = contrib ? wgt * dCr : 0.f;
-        const float g_g = contrib ? wgt * dCg : 0.f;
-        const float g_b = contrib ? wgt * dCb : 0.f;
-        const float g_o = open ? dal * bl.ex : 0.f;
-        const float g_u = -dpow * (A * dx + B * dy);
-        const float g_v = -dpow * (C * dy + B * dx);
-        const float g_A = -0.5f * dpow * dx * dx;
-        const float g_B = -dpow * dx * dy;
-        const float g_C = -0.5f * dpow * dy * dy;
-        Sr = contrib ? fmaf(kr, wgt, Sr) : Sr;
-        Sg = contrib ? fmaf(kg, wgt, Sg) : Sg;
-        Sb = contrib ? fmaf(kb, wgt, Sb) : Sb;
+        const float m_x = dpow * dx, m_y = dpow * dy;
+        const float m_xx = m_x * dx, m_xy = m_x * dy, m_yy = m_y * dy;
+        Sr = fmaf(kr, wgt, Sr);
+        Sg = fmaf(kg, wgt, Sg);
+        Sb = fmaf(kb, wgt, Sb);
         T = contrib ? Tb : T;
-        // rows of s1 hold u, A, v, B and rows of s2 C, r, o, g; b ends in lane 63
-        const float s1 = wave_sum4(g_u, g_v, g_A, g_B);
-        const float s2 = wave_sum4(g_C, g_o, g_r, g_g);
-        const float sb = wave_sum_dpp(g_b);
+        // window slot q of the record receives, in order, m_x, m_y, m_xx, m_xy
+        // (from s1), m_yy, o, r, g (from s2) and b (lane 63 of sb)
+        const float s1 = wave_sum4(m_x, m_y, m_xx, m_xy);
+        const float s2 = wave_sum4(m_yy, g_o, wgt * dCr, wgt * dCg);
+        const float sb = wave_sum_dpp(wgt * dCb);
         if ((lane & 15) == 15) {
           float* G = s_g[(int)(b0 - w0) + j];
           const int row = lane >> 4;
@@ -176,9 +176,18 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
         G[q] = 0.f;
       }
       if (any) {
-        float* D = reinterpret_cast<float*>(a.g2d + 3 * (size_t)a.vals[w0 + k]);
+        const uint32_t r = a.vals[w0 + k];
+        const float4 c = a.rec_conic[r];
+        // moments -> d(u, v, A, B, C): -(A mx + B my), -(B mx + C my),
+        // -mxx / 2, -mxy, -myy / 2
+        const float g5[5] = {-(c.x * gv[0] + c.y * gv[1]), -(c.y * gv[0] + c.z * gv[1]),
+                             -0.5f * gv[2], -gv[3], -0.5f * gv[4]};
+        float* D = reinterpret_cast<float*>(a.g2d + 3 * (size_t)r);
 #pragma unroll
-        for (int q = 0; q < 9; ++q)
+        for (int q = 0; q < 5; ++q)
+          if (g5[q] != 0.f) atomicAdd(D + q, g5[q]);
+#pragma unroll
+        for (int q = 5; q < 9; ++q)
           if (gv[q] != 0.f) atomicAdd(D + q, gv[q]);
       }
     }

@@ -55,6 +55,11 @@ KERNEL_SOURCES = {
 }
 
 
+# kernels of steps a1-a8 (instance cameras through tile ranges)
+PCS_KERNELS = ("compose", "project", "block_offsets", "records", "scan", "emit_pairs", "radix",
+               "tile_ranges", "tile_order")
+
+
 def sources_digest(kernel):
     h = hashlib.sha256()
     for f in KERNEL_SOURCES.get(kernel, ()):
@@ -204,15 +209,21 @@ def kernel_roofline(name, total_ms, launches, units, steps, sh_degree, n):
     return None
 
 
-def pcs_bytes(units, steps, sh_degree, n):
-    """Algorithmic HBM bytes of project/cull/sort over the timed steps: the
-    Gaussians' visibility interval, the geometry of those that pass, the M_t
-    bits, SH + opacity + record of the survivors, and every (tile, record)
-    pair written once and read + written once by a sort."""
+def pcs_batch_bytes(batch, sh_degree, n):
+    """Algorithmic HBM bytes of project/cull/sort for one batch of views (a
+    list of per-view units): every Gaussian's visibility interval once, the
+    geometry of the Gaussians that pass the temporal test (counted for the
+    view where most pass: a lower bound on the union), per view the M_t bits,
+    SH + opacity + record of each survivor, and every (tile, record) pair
+    written once and read + written once by a sort."""
     sh_bytes = 12 * (sh_degree + 1) ** 2
-    per = [units[i % len(units)] for i in range(steps)]
-    return sum(8 * n + GEOM_BYTES * u["N_t"] + n / 8 + (4 + sh_bytes + REC_BYTES) * u["N_r"]
-               + 12 * u["N_dup"] + 24 * u["N_dup"] for u in per)
+    return (8 * n + GEOM_BYTES * max(u["N_t"] for u in batch)
+            + sum(n / 8 + (4 + sh_bytes + REC_BYTES) * u["N_r"] + 36 * u["N_dup"] for u in batch))
+
+
+def pcs_bytes(units, steps, sh_degree, n):
+    """pcs_batch_bytes over `steps` one-view steps cycling through `units`."""
+    return sum(pcs_batch_bytes([units[i % len(units)]], sh_degree, n) for i in range(steps))
 
 
 def cpu_baseline(cfg, n_tiles_sample=160):
@@ -346,14 +357,40 @@ def batched_graph(cfg, torch, replays, tiles):
         torch.cuda.synchronize()
         ms = np.asarray([a.elapsed_time(b) for a, b in times])
         st = r.stats.cpu().numpy()
+        # a few eager steps with every kernel timed: per-kernel breakdown and
+        # the project/cull/sort share of HBM peak for this batch
+        from paper_2503_08217_amd import _abi
+        lib = _abi.load()
+        _abi.check(lib.s3r_profile_reset(), "profile reset")
+        _abi.check(lib.s3r_profile_only(-1), "profile only")
+        _abi.check(lib.s3r_profile_enable(1), "profile enable")
+        prof_steps = 3
+        for _ in range(prof_steps):
+            r.step(target)
+        torch.cuda.synchronize()
+        table = _abi.profile_table()
+        _abi.check(lib.s3r_profile_enable(0), "profile disable")
+        units = [dict(N_t=int(x[0]), N_f=int(x[1]), N_r=int(x[2]), N_dup=int(x[3])) for x in st]
+        pcs_ms = sum(table[k][0] for k in PCS_KERNELS if k in table) / prof_steps
+        pcs_b = pcs_batch_bytes(units, cfg.scene.sh_degree, cfg.scene.n)
         res = {"tile": tile, "p50_ms": float(np.percentile(ms, 50)),
                "p99_ms": float(np.percentile(ms, 99)), "mean_ms": float(ms.mean()),
                "views_per_s": views.n_views / (ms.mean() * 1e-3),
                "mean_visible_fraction": float(st[:, 0].mean() / cfg.scene.n),
-               "records": c["n_surv"], "pairs": c["n_dup"]}
+               "records": c["n_surv"], "pairs": c["n_dup"],
+               "gaussians_per_s": cfg.scene.n * views.n_views / (ms.mean() * 1e-3),
+               "project_cull_sort_hbm": {"achieved": pcs_b / (pcs_ms * 1e-3) / 1e9,
+                                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                         "frac": pcs_b / (pcs_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                         "ms_per_step": pcs_ms, "bytes": pcs_b},
+               "kernels_us_per_step": {k: 1000 * v[0] / prof_steps for k, v in table.items()}}
         log(f"batched {cfg.name} tile {tile}: p50 {res['p50_ms']:.2f} ms, p99 "
             f"{res['p99_ms']:.2f} ms, {res['views_per_s']:.1f} views/s, N_t/N "
-            f"{res['mean_visible_fraction']:.3f}")
+            f"{res['mean_visible_fraction']:.3f}, project/cull/sort "
+            f"{res['project_cull_sort_hbm']['ms_per_step']:.3f} ms at "
+            f"{100 * res['project_cull_sort_hbm']['frac']:.1f}% of HBM peak")
+        for k, v in sorted(res["kernels_us_per_step"].items(), key=lambda kv: -kv[1])[:12]:
+            log(f"   {k:22s} {v:9.1f} us/step")
         tune.append(res)
         if best is None or res["mean_ms"] < best["mean_ms"]:
             best = res
@@ -372,8 +409,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", type=int, default=16, choices=(8, 16, 32))
-    ap.add_argument("--sweep", action="store_true",
-                    help="also time the LOD threshold x temporal filter grid")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the LOD threshold x temporal filter grid")
     ap.add_argument("--replays", type=int, default=100)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run a plain copy of this many MiB first (for counter calibration)")
@@ -438,10 +475,8 @@ def main():
                 "traffic": measured_traffic(dname, cfg.name), "kernel": dname,
                 "avg_us": 1000 * dms / dcnt, "work": basis,
                 "sources_sha256_16": sources_digest(dname)}
-    pcs_names = ("compose", "project", "block_offsets", "records", "scan", "emit_pairs", "radix",
-                 "tile_ranges", "tile_order")
     # warm-up steps (every kernel timed) give the project/cull/sort time
-    pcs_ms = sum(table[k][0] for k in pcs_names if k in table)
+    pcs_ms = sum(table[k][0] for k in PCS_KERNELS if k in table)
     pcs_gbs = pcs_bytes(units, a.warmup, cfg.scene.sh_degree, cfg.scene.n) / (pcs_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -451,6 +486,7 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": s["ms"],
+        "gaussians_per_s": cfg.scene.n * s["vps"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -469,7 +505,7 @@ def main():
         out["plain_views_per_s"] = p["vps"]
         out["speedup_vs_plain"] = s["vps"] / p["vps"]
         out["plain_kernels_us_warmup"] = {k: 1000 * ms / cnt for k, (ms, cnt) in p["table"].items()}
-    if a.sweep:
+    if not a.no_sweep and a.config == 3:
         out["sweep"] = lod_temporal_sweep(cfg, targets, torch)
     if not a.no_cpu:
         t0 = time.perf_counter()

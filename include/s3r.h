@@ -170,6 +170,12 @@ typedef struct S3RProjected {
   int32_t* stats;     /* [V][4] N_t (temporal pass), N_f (= |M_t|), N_r (records),
                          N_dup (pairs, written by s3r_sort)                     */
   int32_t* rec_npairs;/* [cap_surv] number of tiles each record covers          */
+  uint32_t* surv;     /* [V][ceil(N/64)*2] bit i of view v: Gaussian i has a record
+                         (M_t and kept by the LOD test); same layout as mask     */
+  int32_t* bstat;     /* [ceil(N/256)][V][4] per block of 256 Gaussians and view:
+                         temporal passes, M_t count, records, first record.  The
+                         records of a batch are ordered by (block, view, Gaussian);
+                         s3r_raster_bwd uses this to find each Gaussian's records */
 } S3RProjected;
 
 typedef struct S3RBins {
@@ -187,7 +193,8 @@ typedef struct S3RImage {
 } S3RImage;
 
 typedef struct S3RGrads {
-  /* accumulated (+=) into caller-zeroed buffers */
+  /* written (=) by s3r_raster_bwd: every entry, zero where a Gaussian has no
+     record, so the caller never zeroes them; `pose` is zeroed, then summed */
   float* mean;    /* [N][3] */
   float* scale;   /* [N][3] */
   float* quat;    /* [N][4] */
@@ -262,10 +269,13 @@ int s3r_l1_loss(const S3RImage* img, const float* target, const S3RViews* views,
 /*
  * s3r_raster_bwd -- gradient of the blending (replayed back to front from
  * T_final and `last`) and of the projection, colour and instance cameras
- * (chain of Eq. 1 and the SH colour), accumulated into `g`.  Pose gradients
- * are chained through W_{t,i} = W_t W_{t,i2g} and also given in 6-DoF form.
- * In the plain route the world-frame gradients g->mean_w / g->rot_w are
- * filled instead of mean / quat; s3r_plain_transform_bwd finishes them.
+ * (chain of Eq. 1 and the SH colour), written to `g` (every per-Gaussian
+ * entry; no caller-side zeroing).  The projection gradient is gathered per
+ * Gaussian over the views of the batch, using `proj->surv` and `proj->bstat`
+ * to find each Gaussian's records.  Pose gradients are chained through
+ * W_{t,i} = W_t W_{t,i2g} and also given in 6-DoF form.  In the plain route
+ * the world-frame gradients g->mean_w / g->rot_w (every slot of the batch)
+ * are written instead of mean / quat; s3r_plain_transform_bwd finishes them.
  */
 int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams* params,
                    const S3RProjected* proj, const S3RBins* bins, const S3RImage* img,
@@ -292,7 +302,8 @@ int s3r_plain_transform(const S3RScene* scene, const int32_t* tsteps, int32_t n_
 
 /*
  * s3r_plain_transform_bwd -- chains world-frame gradients (S3RGrads.mean_w,
- * rot_w) back to local mean / quat and to the poses of the n_ts timesteps.
+ * rot_w) back to local mean / quat (written) and to the poses of the n_ts
+ * timesteps (added to g->pose).
  */
 int s3r_plain_transform_bwd(const S3RScene* scene, const int32_t* tsteps, int32_t n_ts,
                             S3RGrads* g, void* stream);

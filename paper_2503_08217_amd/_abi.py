@@ -48,7 +48,8 @@ class S3RViews(C.Structure):
 class S3RProjected(C.Structure):
     _fields_ = [("cam", P), ("cen", P), ("t_norm", P), ("mask", P), ("rec_gid", P),
                 ("rec_view", P), ("rec_geo", P), ("rec_conic", P), ("rec_rgb", P),
-                ("rec_rect", P), ("counters", P), ("stats", P), ("rec_npairs", P)]
+                ("rec_rect", P), ("counters", P), ("stats", P), ("rec_npairs", P), ("surv", P),
+                ("bstat", P)]
 
 
 class S3RBins(C.Structure):

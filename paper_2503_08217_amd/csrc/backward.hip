@@ -235,30 +235,85 @@ __device__ __forceinline__ void wave_segmented_add(int key, const float val[12],
   }
 }
 
-// Accumulate into a per-Gaussian gradient.  With one view per batch every
-// Gaussian owns at most one record, so a plain read-modify-write suffices.
-__device__ __forceinline__ void acc(float* p, float v, bool exclusive) {
-  if (exclusive) *p += v;
-  else atomicAdd(p, v);
+// bit of Gaussian i in a [ceil(N/64)*2] word mask (word i / 32, bit i % 32)
+__device__ __forceinline__ bool mask_bit(const uint32_t* m, int i) {
+  return (m[i >> 5] >> (i & 31)) & 1u;
 }
 
-__global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
-  const int nrec = a.counters[S3R_CNT_SURV];
-  const bool ex = a.nv == 1;
+// Gradient of the projection, colour and instance cameras, gathered per
+// Gaussian.  One thread per record; the record that is its Gaussian's first
+// in the batch (the owner) does the work: it walks the later views, finds
+// the Gaussian's record in each view where it survived (records are ordered
+// by (block of 256 Gaussians, view, Gaussian), so the slot is the block's
+// first record of that view plus the Gaussian's rank among the block's
+// survivors), chains each record's 2D gradient back through Eq. (1) and the
+// SH colour, sums over views (SH coefficients in the Gaussian's own rows),
+// and writes the Gaussian's gradients once: no per-Gaussian atomics.  With
+// one view per batch every record is an owner.  The entry point zeroes the
+// dense gradient arrays first, so Gaussians without records cost nothing
+// here.  Camera gradients are summed per wave over lanes of the same (view,
+// instance) before their atomics.
+__device__ __forceinline__ void project_bwd_owner(const ProjBwdArgs& a, int r0, int nrec) {
   const bool plain = (a.kp.flags & S3R_PLAIN) != 0;
   const int B = (a.sh_deg + 1) * (a.sh_deg + 1);
-  const int stride = gridDim.x * blockDim.x;
-  for (int base = blockIdx.x * blockDim.x; base < nrec; base += stride) {
-    const int r = base + threadIdx.x;
-    const bool active = r < nrec;
+  int i = 0, v0 = 0;
+  bool active = r0 < nrec;
+  if (active) {
+    i = a.rec_gid[r0];
+    v0 = a.rec_view[r0];
+    // the owner is the Gaussian's record in the first view where it survived
+    for (int v = 0; v < v0; ++v)
+      if (mask_bit(a.surv + (size_t)v * a.mask_words, i)) {
+        active = false;
+        break;
+      }
+  }
+  const int k = active ? clampi(a.inst[i], 0, a.n_slots - 1) : 0;
+  const int vb = i / kProjBlock, wave = (i % kProjBlock) / kWave, bit = i % kWave;
+
+  // the Gaussian's parameters (local frame)
+  float mx = 0.f, my = 0.f, mz = 0.f, sc[3] = {1.f, 1.f, 1.f}, Rl[9];
+  float4 q = make_float4(1.f, 0.f, 0.f, 0.f);
+  if (active) {
+    mx = a.mean[3 * i]; my = a.mean[3 * i + 1]; mz = a.mean[3 * i + 2];
+    sc[0] = a.scale[3 * i]; sc[1] = a.scale[3 * i + 1]; sc[2] = a.scale[3 * i + 2];
+    q = reinterpret_cast<const float4*>(a.quat)[i];
+  }
+  // d_sh is summed in place (this thread owns the Gaussian's entries): the
+  // first record writes, later ones add; Gaussians without records keep the
+  // zeros the caller side of the launch wrote
+  float* dsh = a.d_sh + (size_t)i * B * 3;
+  const bool vec_sh = ((3 * B) & 3) == 0;
+  bool first = true;
+  quat_rot(q.x, q.y, q.z, q.w, Rl);
+  // plain route: world-frame gradients (zeroed by the entry point) are
+  // summed in place per timestep slot; this thread owns the Gaussian's rows
+  // accumulated over the views
+  float acc_mu[3] = {0.f, 0.f, 0.f}, acc_sc[3] = {0.f, 0.f, 0.f}, acc_R[9], acc_o = 0.f;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc_R[t] = 0.f;
+
+  for (int v = 0; v < a.nv; ++v) {
+    // this Gaussian's record in view v, if it has one
+    int64_t r = r0;
+    bool has = active && v == v0;
+    if (active && v > v0 && mask_bit(a.surv + (size_t)v * a.mask_words, i)) {
+      const int first = a.bstat[((size_t)vb * a.nv + v) * 4 + 3];
+      int before = 0;
+      for (int w = 0; w <= wave; ++w) {
+        const uint32_t* sb = a.surv + (size_t)v * a.mask_words + 2 * ((size_t)vb * kProjWaves + w);
+        uint64_t word = ((uint64_t)sb[1] << 32) | sb[0];
+        if (w == wave) word &= (1ull << bit) - 1ull;
+        before += __popcll(word);
+      }
+      r = (int64_t)first + before;
+      has = r < a.kp.cap_surv;
+    }
     int cam_key = -1;
     float dcam[12];
 #pragma unroll
-    for (int q = 0; q < 12; ++q) dcam[q] = 0.f;
-    if (active) {
-      const int i = a.rec_gid[r];
-      const int v = a.rec_view[r];
-      const int k = clampi(a.inst[i], 0, a.n_slots - 1);
+    for (int t = 0; t < 12; ++t) dcam[t] = 0.f;
+    if (has) {
       const int tau = clampi(a.tstep[v], 0, a.n_ts - 1);
       const float4 G0 = a.g2d[3 * (size_t)r], G1 = a.g2d[3 * (size_t)r + 1],
                    G2 = a.g2d[3 * (size_t)r + 2];
@@ -269,22 +324,19 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
       const int Wd = a.wh[2 * v], Hd = a.wh[2 * v + 1];
 
       // ---- forward recompute ----
-      float mx, my, mz, Rg[9];
-      float4 q = make_float4(1.f, 0.f, 0.f, 0.f);
+      float px_m = mx, py_m = my, pz_m = mz, Rg[9];
       int slot = 0;
       if (plain) {
         slot = a.plain_slot[v];
         const float* mw = a.mean_w + ((size_t)slot * a.n + i) * 3;
-        mx = mw[0]; my = mw[1]; mz = mw[2];
+        px_m = mw[0]; py_m = mw[1]; pz_m = mw[2];
         const float* rw = a.rot_w + ((size_t)slot * a.n + i) * 9;
 #pragma unroll
         for (int t = 0; t < 9; ++t) Rg[t] = rw[t];
       } else {
-        mx = a.mean[3 * i]; my = a.mean[3 * i + 1]; mz = a.mean[3 * i + 2];
-        q = reinterpret_cast<const float4*>(a.quat)[i];
-        quat_rot(q.x, q.y, q.z, q.w, Rg);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) Rg[t] = Rl[t];
       }
-      const float sc[3] = {a.scale[3 * i], a.scale[3 * i + 1], a.scale[3 * i + 2]};
       float P[12];
       {
         const float4* c4 =
@@ -294,9 +346,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
         P[4] = c1.x; P[5] = c1.y; P[6] = c1.z; P[7] = c1.w;
         P[8] = c2.x; P[9] = c2.y; P[10] = c2.z; P[11] = c2.w;
       }
-      const float px = ((P[0] * mx + P[1] * my) + P[2] * mz) + P[3];
-      const float py = ((P[4] * mx + P[5] * my) + P[6] * mz) + P[7];
-      const float pz = ((P[8] * mx + P[9] * my) + P[10] * mz) + P[11];
+      const float px = ((P[0] * px_m + P[1] * py_m) + P[2] * pz_m) + P[3];
+      const float py = ((P[4] * px_m + P[5] * py_m) + P[6] * pz_m) + P[7];
+      const float pz = ((P[8] * px_m + P[9] * py_m) + P[10] * pz_m) + P[11];
       float M[9];
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii)
@@ -397,10 +449,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
         for (int jj = 0; jj < 3; ++jj)
           dM[ii * 3 + jj] = 2.f * (dS[ii * 3] * M[jj] + dS[ii * 3 + 1] * M[3 + jj] +
                                    dS[ii * 3 + 2] * M[6 + jj]);
-      float dsc[3], dRg[9];
+      float dRg[9];
 #pragma unroll
       for (int jj = 0; jj < 3; ++jj) {
-        dsc[jj] = Rg[jj] * dM[jj] + Rg[3 + jj] * dM[3 + jj] + Rg[6 + jj] * dM[6 + jj];
+        acc_sc[jj] += Rg[jj] * dM[jj] + Rg[3 + jj] * dM[3 + jj] + Rg[6 + jj] * dM[6 + jj];
 #pragma unroll
         for (int ii = 0; ii < 3; ++ii) dRg[ii * 3 + jj] = dM[ii * 3 + jj] * sc[jj];
       }
@@ -408,7 +460,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
       float dmu[3], dtau[3] = {dpx, dpy, dpz};
 #pragma unroll
       for (int jj = 0; jj < 3; ++jj) dmu[jj] = P[jj] * dpx + P[4 + jj] * dpy + P[8 + jj] * dpz;
-      const float mm[3] = {mx, my, mz};
+      const float mm[3] = {px_m, py_m, pz_m};
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii)
 #pragma unroll
@@ -419,7 +471,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
       const float* Gp = nullptr;
       if (plain) {
         const float4 cw = reinterpret_cast<const float4*>(a.cen)[(size_t)v * a.n_slots];
-        w3[0] = mx - cw.x; w3[1] = my - cw.y; w3[2] = mz - cw.z;
+        w3[0] = px_m - cw.x; w3[1] = py_m - cw.y; w3[2] = pz_m - cw.z;
         Gp = a.pose + ((size_t)tau * a.n_slots + k) * 12;
 #pragma unroll
         for (int jj = 0; jj < 3; ++jj) dl[jj] = Gp[jj] * w3[0] + Gp[4 + jj] * w3[1] + Gp[8 + jj] * w3[2];
@@ -446,29 +498,29 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) dr[c] = raw[c] >= 0.f ? drgb[c] : 0.f;
       float gb[16];
-      float* dsh = a.d_sh + (size_t)i * B * 3;
 #pragma unroll
       for (int b = 0; b < 16; ++b)
         gb[b] = (b < B) ? f[3 * b] * dr[0] + f[3 * b + 1] * dr[1] + f[3 * b + 2] * dr[2] : 0.f;
-      // dL/df_{b,c} = Y_b dr_c, element q = 3 b + c
-      if (ex && ((3 * B) & 3) == 0) {
+      // dL/df_{b,c} = Y_b dr_c, element 3 b + c
+      if (vec_sh) {
         float4* d4 = reinterpret_cast<float4*>(dsh);
 #pragma unroll
-        for (int q = 0; q < 12; ++q) {
-          if (4 * q < 3 * B) {
-            float4 x = d4[q];
-            x.x += Y[(4 * q) / 3] * dr[(4 * q) % 3];
-            x.y += Y[(4 * q + 1) / 3] * dr[(4 * q + 1) % 3];
-            x.z += Y[(4 * q + 2) / 3] * dr[(4 * q + 2) % 3];
-            x.w += Y[(4 * q + 3) / 3] * dr[(4 * q + 3) % 3];
-            d4[q] = x;
+        for (int t = 0; t < 12; ++t) {
+          if (4 * t < 3 * B) {
+            float4 x = first ? make_float4(0.f, 0.f, 0.f, 0.f) : d4[t];
+            x.x += Y[(4 * t) / 3] * dr[(4 * t) % 3];
+            x.y += Y[(4 * t + 1) / 3] * dr[(4 * t + 1) % 3];
+            x.z += Y[(4 * t + 2) / 3] * dr[(4 * t + 2) % 3];
+            x.w += Y[(4 * t + 3) / 3] * dr[(4 * t + 3) % 3];
+            d4[t] = x;
           }
         }
       } else {
 #pragma unroll
-        for (int q = 0; q < 48; ++q)
-          if (q < 3 * B) acc(dsh + q, Y[q / 3] * dr[q % 3], ex);
+        for (int t = 0; t < 48; ++t)
+          if (t < 3 * B) dsh[t] = (first ? 0.f : dsh[t]) + Y[t / 3] * dr[t % 3];
       }
+      first = false;
       float ddir[3];
       sh_basis_grad(a.sh_deg, dir[0], dir[1], dir[2], gb, ddir[0], ddir[1], ddir[2]);
       const float dd = dir[0] * ddir[0] + dir[1] * ddir[1] + dir[2] * ddir[2];
@@ -476,20 +528,19 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) ddl[c] = (ddir[c] - dir[c] * dd) / nrm;
 
-      acc(a.d_opac + i, dO, ex);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc(a.d_scale + 3 * i + c, dsc[c], ex);
+      acc_o += dO;
       if (plain) {
-        // dl = R_G^T w, w = mu_w - c_w
+        // dl = R_G^T w, w = mu_w - c_w; this thread owns (slot, i)
         float dw[3];
 #pragma unroll
-        for (int ii = 0; ii < 3; ++ii) dw[ii] = Gp[ii * 4] * ddl[0] + Gp[ii * 4 + 1] * ddl[1] + Gp[ii * 4 + 2] * ddl[2];
+        for (int ii = 0; ii < 3; ++ii)
+          dw[ii] = Gp[ii * 4] * ddl[0] + Gp[ii * 4 + 1] * ddl[1] + Gp[ii * 4 + 2] * ddl[2];
         float* dmw = a.d_mean_w + ((size_t)slot * a.n + i) * 3;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc(dmw + c, dmu[c] + dw[c], ex);
+        for (int c = 0; c < 3; ++c) dmw[c] += dmu[c] + dw[c];
         float* drw = a.d_rot_w + ((size_t)slot * a.n + i) * 9;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc(drw + t, dRg[t], ex);
+        for (int t = 0; t < 9; ++t) drw[t] += dRg[t];
         if (k > 0) {
           // dR_G[j][i] += w_j ddl_i (rotation part of the pose)
 #pragma unroll
@@ -501,7 +552,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
       } else {
         // d = mu - cen, cen = -R_c^T tau
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dmu[c] += ddl[c];
+        for (int c = 0; c < 3; ++c) acc_mu[c] += dmu[c] + ddl[c];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc_R[t] += dRg[t];
         const float dcen[3] = {-ddl[0], -ddl[1], -ddl[2]};
 #pragma unroll
         for (int ii = 0; ii < 3; ++ii) {
@@ -509,12 +562,6 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
           for (int jj = 0; jj < 3; ++jj) dRc[ii * 3 + jj] += -P[ii * 4 + 3] * dcen[jj];
           dtau[ii] += -(P[ii * 4] * dcen[0] + P[ii * 4 + 1] * dcen[1] + P[ii * 4 + 2] * dcen[2]);
         }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc(a.d_mean + 3 * i + c, dmu[c], ex);
-        float dq[4];
-        quat_rot_bwd(q, dRg, dq);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc(a.d_quat + 4 * i + c, dq[c], ex);
         if (k > 0) {
 #pragma unroll
           for (int ii = 0; ii < 3; ++ii) {
@@ -528,6 +575,25 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
     }
     wave_segmented_add(cam_key, dcam, plain ? a.d_pose : a.d_cam);
   }
+
+  if (first) return;  // not an owner: nothing to write
+  a.d_opac[i] = acc_o;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) a.d_scale[3 * i + c] = acc_sc[c];
+  if (!plain) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.d_mean[3 * i + c] = acc_mu[c];
+    float dq[4];
+    quat_rot_bwd(q, acc_R, dq);
+    reinterpret_cast<float4*>(a.d_quat)[i] = make_float4(dq[0], dq[1], dq[2], dq[3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
+  const int nrec = (int)min((int64_t)a.counters[S3R_CNT_SURV], a.kp.cap_surv);
+  const int stride = gridDim.x * blockDim.x;
+  for (int base = blockIdx.x * blockDim.x; base < nrec; base += stride)
+    project_bwd_owner(a, base + (int)threadIdx.x, nrec);
 }
 
 // dL/dG_{tau,k} += W_R^T dL/dP_{v,k} for every view v (slot 0 skipped)
@@ -558,7 +624,11 @@ __global__ void k_pose6(const float* __restrict__ pose, const float* __restrict_
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= TS_) return;
   float* o = d_pose6 + (size_t)idx * 6;
-  if (idx % S == 0) return;
+  if (idx % S == 0) {  // slot 0 (static Gaussians) has no pose
+#pragma unroll
+    for (int c = 0; c < 6; ++c) o[c] = 0.f;
+    return;
+  }
   const float* G = pose + (size_t)idx * 12;
   const float* D = d_pose + (size_t)idx * 12;
   float M[12];  // rows 0..2 of G~^T D: M[i][c] = sum_r G[r][i] D[r][c]
@@ -637,9 +707,9 @@ __global__ __launch_bounds__(256) void k_plain_transform_bwd(
       float dq[4];
       quat_rot_bwd(q, dRq, dq);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) d_mean[3 * i + c] += dmu[c];
+      for (int c = 0; c < 3; ++c) d_mean[3 * i + c] = dmu[c];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) d_quat[4 * i + c] += dq[c];
+      for (int c = 0; c < 4; ++c) d_quat[4 * i + c] = dq[c];
     }
   }
 }
@@ -678,9 +748,35 @@ hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_project_bwd(const ProjBwdArgs& a, int64_t cap_surv, hipStream_t st) {
-  const int64_t want = (cap_surv + 255) / 256;
-  const int grid = (int)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+// plain route: clear the world-frame gradients of every timestep slot of the
+// batch (slots = 1 + the largest plain_slot of the views)
+__global__ __launch_bounds__(256) void k_zero_plain_w(const int32_t* __restrict__ plain_slot,
+                                                      int nv, int64_t n, float4* __restrict__ mw,
+                                                      float4* __restrict__ rw) {
+  int ns = 0;
+  for (int v = 0; v < nv; ++v) ns = max(ns, plain_slot[v] + 1);
+  const int64_t n_mw = ns * n * 3 / 4, n_rw = ns * n * 9 / 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_mw; j += stride) mw[j] = z;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_rw; j += stride) rw[j] = z;
+  // tails (ns * n * 3 and ns * n * 9 need not be multiples of 4)
+  if (blockIdx.x == 0 && threadIdx.x < 4) {
+    float* m = reinterpret_cast<float*>(mw);
+    float* r = reinterpret_cast<float*>(rw);
+    const int64_t tm = 4 * n_mw + threadIdx.x, tr = 4 * n_rw + threadIdx.x;
+    if (tm < ns * n * 3) m[tm] = 0.f;
+    if (tr < ns * n * 9) r[tr] = 0.f;
+  }
+}
+
+hipError_t launch_project_bwd(const ProjBwdArgs& a, hipStream_t st) {
+  if ((a.kp.flags & S3R_PLAIN) != 0)
+    S3R_LAUNCH(K_ZERO, k_zero_plain_w, dim3(2048), dim3(256), 0, st, a.plain_slot, a.nv,
+               (int64_t)a.n, reinterpret_cast<float4*>(a.d_mean_w),
+               reinterpret_cast<float4*>(a.d_rot_w));
+  const int64_t want = (a.kp.cap_surv + 255) / 256;
+  const int grid = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
   S3R_LAUNCH(K_PROJECT_BWD, k_project_bwd, dim3(grid), dim3(256), 0, st, a);
   return hipGetLastError();
 }

@@ -25,8 +25,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
   } while (0)
 
 struct WsProject {
-  uint32_t* surv;
-  int32_t* bstat;
+  int32_t* reserved;
 };
 struct WsSort {
   uint64_t* keys;
@@ -43,14 +42,9 @@ struct WsBwd {
 };
 
 size_t ws_project(const S3RSizes& z, WsProject* w, char* base) {
-  const int nblk = project_blocks(z.n);
-  const size_t words = (size_t)((z.n + 63) / 64) * 2;
-  size_t off = 0;
-  if (w) w->surv = reinterpret_cast<uint32_t*>(base + off);
-  off += align_up(words * z.n_views * 4 + 8);
-  if (w) w->bstat = reinterpret_cast<int32_t*>(base + off);
-  off += align_up((size_t)nblk * z.n_views * 16 + 16);
-  return off;
+  (void)z;
+  if (w) w->reserved = reinterpret_cast<int32_t*>(base);
+  return align_up(16);
 }
 
 size_t ws_sort(const S3RSizes& z, WsSort* w, char* base) {
@@ -223,6 +217,8 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
   S3R_REQUIRE(out->counters);
   S3R_REQUIRE(out->stats);
   S3R_REQUIRE(out->rec_npairs);
+  S3R_REQUIRE(out->surv);
+  S3R_REQUIRE(out->bstat);
   const S3RSizes z = sizes_of(scene, views, params);
   if (!ws && ws_bytes) return S3R_E_NULL;
   if (ws_bytes < ws_project(z, nullptr, nullptr) || !ws) return S3R_E_WORKSPACE;
@@ -271,8 +267,8 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
   a.rec_rect = reinterpret_cast<int4*>(out->rec_rect);
   a.rec_npairs = out->rec_npairs;
   a.counters = out->counters;
-  a.surv = w.surv;
-  a.bstat = w.bstat;
+  a.surv = out->surv;
+  a.bstat = out->bstat;
   a.nblk = nblk;
   a.kp = kparams(*params);
   S3R_HIP(launch_project(a, out->stats, st));
@@ -404,6 +400,8 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   S3R_REQUIRE(proj->rec_conic);
   S3R_REQUIRE(proj->rec_rgb);
   S3R_REQUIRE(proj->counters);
+  S3R_REQUIRE(proj->surv);
+  S3R_REQUIRE(proj->bstat);
   S3R_REQUIRE(bins->tile_start);
   S3R_REQUIRE(bins->tile_order);
   S3R_REQUIRE(bins->vals);
@@ -427,8 +425,18 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   const hipStream_t st = as_stream(stream);
   const KParams kp = kparams(*params);
 
-  S3R_HIP(launch_zero(w.d_cam, (size_t)views->n_views * scene->n_slots * 48, nullptr, 0, nullptr,
-                      0, nullptr, 0, st));
+  {
+    // every gradient output is written by this call: clear the dense arrays
+    // (Gaussians without records keep these zeros) and the accumulators
+    const size_t N = (size_t)scene->n;
+    const size_t B = (size_t)(scene->sh_degree + 1) * (scene->sh_degree + 1);
+    void* ps[7] = {w.d_cam, g->pose, g->scale, g->opacity, g->sh, plain ? nullptr : g->mean,
+                   plain ? nullptr : g->quat};
+    const size_t bs[7] = {(size_t)views->n_views * scene->n_slots * 48,
+                          (size_t)scene->n_timesteps * scene->n_slots * 48, N * 12, N * 4,
+                          N * B * 12, N * 12, N * 16};
+    S3R_HIP(launch_zero_n(ps, bs, 7, st));
+  }
   BwdArgs b{};
   b.rec_geo = reinterpret_cast<const float4*>(proj->rec_geo);
   b.rec_conic = reinterpret_cast<const float4*>(proj->rec_conic);
@@ -475,6 +483,9 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   p.rec_gid = proj->rec_gid;
   p.rec_view = proj->rec_view;
   p.counters = proj->counters;
+  p.surv = proj->surv;
+  p.bstat = proj->bstat;
+  p.mask_words = ((scene->n + 63) / 64) * 2;
   p.g2d = w.g2d;
   p.d_mean = g->mean;
   p.d_scale = g->scale;
@@ -486,7 +497,7 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   p.d_cam = w.d_cam;
   p.d_pose = g->pose;
   p.kp = kp;
-  S3R_HIP(launch_project_bwd(p, params->cap_surv, st));
+  S3R_HIP(launch_project_bwd(p, st));
   if (!plain)
     S3R_HIP(launch_pose_bwd(views->W, views->tstep, scene->pose, w.d_cam, views->n_views,
                             scene->n_slots, scene->n_timesteps, g->pose, g->pose6, st));

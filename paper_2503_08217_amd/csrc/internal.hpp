@@ -128,8 +128,11 @@ struct ProjBwdArgs {
   const int32_t* rec_gid;
   const int32_t* rec_view;
   const int32_t* counters;
+  const uint32_t* surv;   // [V][mask_words] survivor bits
+  const int32_t* bstat;   // [nblk][V][4] per-block counts and first record
+  int64_t mask_words;
   const float4* g2d;
-  // gradients (accumulated)
+  // gradients (written)
   float* d_mean;
   float* d_scale;
   float* d_quat;
@@ -148,10 +151,17 @@ hipError_t launch_compose(const float* W, const int32_t* tstep, const float* pos
 hipError_t launch_plain_transform(const float* mean, const float* quat, const int32_t* inst,
                                   const float* pose, int n, int S, const int32_t* tsteps, int n_ts,
                                   float* mean_w, float* rot_w, hipStream_t st);
+// Gaussians per projection workgroup: records are ordered by (block, view,
+// Gaussian) and the per-(block, view) survivor counts give each block's
+// first record
+constexpr int kProjBlock = 256;
+constexpr int kProjWaves = kProjBlock / kWave;
 int project_blocks(int64_t n);
 hipError_t launch_project(const ProjArgs& a, int32_t* stats, hipStream_t st);
 
 // util.hip
+// zero up to 8 device buffers (16-byte aligned) with one kernel
+hipError_t launch_zero_n(void* const* ps, const size_t* bytes, int count, hipStream_t st);
 hipError_t launch_zero(void* p0, size_t b0, void* p1, size_t b1, void* p2, size_t b2, void* p3,
                        size_t b3, hipStream_t st);
 
@@ -193,7 +203,7 @@ hipError_t launch_l1_loss(const float* color, const float* target, const int64_t
 
 // backward.hip
 hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st);
-hipError_t launch_project_bwd(const ProjBwdArgs& a, int64_t cap_surv, hipStream_t st);
+hipError_t launch_project_bwd(const ProjBwdArgs& a, hipStream_t st);
 hipError_t launch_pose_bwd(const float* W, const int32_t* tstep, const float* pose,
                            const float* d_cam, int nv, int S, int T, float* d_pose,
                            float* d_pose6, hipStream_t st);

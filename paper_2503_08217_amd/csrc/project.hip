@@ -107,9 +107,6 @@ __global__ __launch_bounds__(256) void k_plain_transform(
 // ---------------------------------------------------------------------------
 // a2-a5: temporal test, projection, M_t, LOD, colour, compaction.
 // ---------------------------------------------------------------------------
-constexpr int kProjBlock = 256;
-constexpr int kProjWaves = kProjBlock / kWave;
-
 struct Loaded {
   float mx, my, mz;
   float R[9];  // the Gaussian's rotation (local, or world for the plain route)

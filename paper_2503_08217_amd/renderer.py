@@ -144,6 +144,8 @@ class Renderer:
         self.counters = torch.zeros(16, device=d, dtype=i32)
         self.stats = torch.zeros(V, 4, device=d, dtype=i32)
         self.rec_npairs = torch.zeros(cs, device=d, dtype=i32)
+        self.surv = torch.zeros(V, self.mask_words, device=d, dtype=i32)
+        self.bstat = torch.zeros((n + 255) // 256 * V * 4 + 4, device=d, dtype=i32)
         self.tile_count = torch.zeros(self.total_tiles, device=d, dtype=i32)
         self.tile_start = torch.zeros(self.total_tiles + 1, device=d, dtype=i32)
         self.tile_order = torch.zeros(max(1, self.total_tiles), device=d, dtype=i32)
@@ -192,7 +194,8 @@ class Renderer:
         self.c_proj = A.S3RProjected(
             _ptr(self.cam), _ptr(self.cen), _ptr(self.t_norm), _ptr(self.mask), _ptr(self.rec_gid),
             _ptr(self.rec_view), _ptr(self.rec_geo), _ptr(self.rec_conic), _ptr(self.rec_rgb),
-            _ptr(self.rec_rect), _ptr(self.counters), _ptr(self.stats), _ptr(self.rec_npairs))
+            _ptr(self.rec_rect), _ptr(self.counters), _ptr(self.stats), _ptr(self.rec_npairs),
+            _ptr(self.surv), _ptr(self.bstat))
         self.c_bins = A.S3RBins(_ptr(self.tile_count), _ptr(self.tile_start), _ptr(self.vals),
                                 _ptr(self.tile_order))
         self.c_img = A.S3RImage(_ptr(self.color), _ptr(self.T_final), _ptr(self.last))
@@ -292,7 +295,6 @@ class Renderer:
         point-life update (Eq. 5)."""
         self.forward()
         self.l1_loss(target)
-        self.zero_grads()
         self.raster_bwd()
         if update_visibility and not self.plain:
             self.update_visibility(A.S3R_VIS_UPDATE)
@@ -366,7 +368,6 @@ class RenderFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, d_color):
         r = ctx.renderer
-        r.zero_grads()
         r.raster_bwd(d_color.contiguous())
         return (None, r.g_mean.clone(), r.g_scale.clone(), r.g_quat.clone(),
                 r.g_opacity.clone(), r.g_sh.clone(), r.g_pose.view(r.T, r.S, 12).clone())

@@ -44,7 +44,7 @@ def test_struct_sizes_match_c_layout():
     assert C.sizeof(A.S3RParams) == 96
     assert C.sizeof(A.S3RScene) == 11 * 8 + 8 + 16
     assert C.sizeof(A.S3RViews) == 7 * 8 + 16
-    assert C.sizeof(A.S3RProjected) == 13 * 8
+    assert C.sizeof(A.S3RProjected) == 15 * 8
     assert C.sizeof(A.S3RBins) == 4 * 8
     assert C.sizeof(A.S3RGrads) == 9 * 8
     assert C.sizeof(A.S3RSizes) == 40
@@ -81,7 +81,7 @@ def test_host_validation_codes(lib):
     ptr = C.c_void_p(al)
     scene = A.S3RScene(*([ptr] * 9), C.c_void_p(0), C.c_void_p(0), 4, 0, 1, 1, 0)
     views = A.S3RViews(*([ptr] * 6), C.c_void_p(0), 1, 1, 64)
-    proj = A.S3RProjected(*([ptr] * 13))
+    proj = A.S3RProjected(*([ptr] * 15))
     p = _params()
     ws = C.c_void_p(al)
     # NULL scene

@@ -25,7 +25,8 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
   } while (0)
 
 struct WsProject {
-  int32_t* reserved;
+  int32_t* chunk_sum;
+  int32_t* chunk_stat;
 };
 struct WsSort {
   uint64_t* keys;
@@ -42,9 +43,13 @@ struct WsBwd {
 };
 
 size_t ws_project(const S3RSizes& z, WsProject* w, char* base) {
-  (void)z;
-  if (w) w->reserved = reinterpret_cast<int32_t*>(base);
-  return align_up(16);
+  const int nchunk = offset_chunks(project_blocks(z.n), (int)z.n_views);
+  size_t off = 0;
+  if (w) w->chunk_sum = reinterpret_cast<int32_t*>(base + off);
+  off += align_up((size_t)nchunk * 4 + 16);
+  if (w) w->chunk_stat = reinterpret_cast<int32_t*>(base + off);
+  off += align_up((size_t)nchunk * z.n_views * 12 + 16);
+  return off;
 }
 
 size_t ws_sort(const S3RSizes& z, WsSort* w, char* base) {
@@ -269,6 +274,8 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
   a.counters = out->counters;
   a.surv = out->surv;
   a.bstat = out->bstat;
+  a.chunk_sum = w.chunk_sum;
+  a.chunk_stat = w.chunk_stat;
   a.nblk = nblk;
   a.kp = kparams(*params);
   S3R_HIP(launch_project(a, out->stats, st));

@@ -60,7 +60,10 @@ struct ProjArgs {
   int32_t* counters;
   // per (block, view): N_t, N_f, N_r, first record (workspace)
   int32_t* bstat;
-  // workspace
+  // workspace: per chunk of (block, view) entries, the record count sum
+  // (then its offset) and per-view partial stats
+  int32_t* chunk_sum;
+  int32_t* chunk_stat;
   uint64_t* flags;
   int nblk;
   KParams kp;
@@ -157,6 +160,7 @@ hipError_t launch_plain_transform(const float* mean, const float* quat, const in
 constexpr int kProjBlock = 256;
 constexpr int kProjWaves = kProjBlock / kWave;
 int project_blocks(int64_t n);
+int offset_chunks(int64_t nblk, int nv);
 hipError_t launch_project(const ProjArgs& a, int32_t* stats, hipStream_t st);
 
 // util.hip

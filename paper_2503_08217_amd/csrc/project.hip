@@ -2,15 +2,16 @@
 // selection, projection (Eq. 1), frustum mask M_t, LOD cull, SH colour of the
 // survivors, and compaction of the survivors into records.
 //
-// Three kernels, none of which waits on another workgroup or uses a
-// contended atomic:
+// Kernels, none of which waits on another workgroup or uses a contended
+// atomic:
 //   k_cull           each workgroup owns 256 consecutive Gaussians and loops
 //                    over the batch's views (a Gaussian's 44 bytes of geometry
 //                    are read once per batch); decisions become M_t bits and
 //                    survivor bits through wave ballots, plus per-(block,
 //                    view) counts
-//   k_block_offsets  one workgroup scans the counts into the first record of
-//                    every (block, view)
+//   k_off_*          an exclusive scan of the counts (chunk sums, one small
+//                    top scan, chunk rescans) gives the first record of every
+//                    (block, view)
 //   k_records        survivors (only) re-project, query their colour and write
 //                    their record at base + rank within the block
 // Records come out ordered by Gaussian block, then view, then Gaussian.
@@ -241,59 +242,114 @@ __global__ __launch_bounds__(kProjBlock) void k_cull(ProjArgs a) {
 // Exclusive scan of the per-(block, view) survivor counts in (block, view)
 // order -> first record of each (block, view); totals -> counters and stats.
 // One workgroup of 1024 threads, each owning a contiguous run of entries.
-__global__ __launch_bounds__(1024) void k_block_offsets(int32_t* __restrict__ bstat, int nblk,
-                                                        int nv, int32_t* __restrict__ counters,
-                                                        int32_t* __restrict__ stats,
-                                                        int64_t cap_surv) {
-  __shared__ uint32_t s_w[16];
-  __shared__ int s_stat[kMaxViews][3];
+// Phase B: first record of every (block, view) -- an exclusive scan of the
+// record counts in (block, view) order, over chunks of kOffChunk entries:
+// chunk sums (and per-view partial stats), a one-workgroup scan of the chunk
+// sums, then each chunk rescanned with its offset.  No contended atomics.
+constexpr int kOffChunk = 1024;
+constexpr int kOffThreads = 256;
+constexpr int kOffPer = kOffChunk / kOffThreads;
+
+__device__ __forceinline__ int block_exclusive_scan(int x, int* s_w, int& total) {
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-  for (int q = tid; q < nv * 3; q += 1024) s_stat[q / 3][q % 3] = 0;
-  __syncthreads();
-  const int64_t total = (int64_t)nblk * nv;
-  const int64_t per = (total + 1023) / 1024;
-  const int64_t e0 = tid * per, e1 = min(total, e0 + per);
-  uint32_t sum = 0;
-  int acc[3] = {0, 0, 0};
-  int cur_v = -1;
-  for (int64_t e = e0; e < e1; ++e) {
-    const int32_t* bs = bstat + e * 4;
-    sum += (uint32_t)bs[2];
-    const int v = (int)(e % nv);
-    if (v != cur_v && cur_v >= 0) {
-      for (int q = 0; q < 3; ++q) atomicAdd(&s_stat[cur_v][q], acc[q]);
-      acc[0] = acc[1] = acc[2] = 0;
-    }
-    cur_v = v;
-    acc[0] += bs[0]; acc[1] += bs[1]; acc[2] += bs[2];
-  }
-  if (cur_v >= 0)
-    for (int q = 0; q < 3; ++q) atomicAdd(&s_stat[cur_v][q], acc[q]);
-  // block-wide exclusive scan of the per-thread sums
-  uint32_t incl = sum;
+  int incl = x;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t t = __shfl_up(incl, o, kWave);
+    const int t = __shfl_up(incl, o, kWave);
     if (lane >= o) incl += t;
   }
   if (lane == kWave - 1) s_w[wave] = incl;
   __syncthreads();
-  uint32_t run = incl - sum;
-  for (int w = 0; w < wave; ++w) run += s_w[w];
-  for (int64_t e = e0; e < e1; ++e) {
-    int32_t* bs = bstat + e * 4;
-    const int64_t st = run;
-    bs[3] = (int32_t)(st < cap_surv ? st : cap_surv);
-    run += (uint32_t)bs[2];
+  int base = 0;
+  total = 0;
+  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+    if (w < wave) base += s_w[w];
+    total += s_w[w];
   }
   __syncthreads();
-  if (tid == 0) {
-    int64_t tot = 0;
-    for (int w = 0; w < 16; ++w) tot += s_w[w];
-    counters[S3R_CNT_SURV] = (int32_t)(tot < cap_surv ? tot : cap_surv);
-    counters[S3R_CNT_OVF_SURV] = (int32_t)(tot > cap_surv ? tot - cap_surv : 0);
+  return base + incl - x;
+}
+
+__global__ __launch_bounds__(kOffThreads) void k_off_reduce(const int32_t* __restrict__ bstat,
+                                                           int64_t total, int nv,
+                                                           int32_t* __restrict__ csum,
+                                                           int32_t* __restrict__ cstat) {
+  __shared__ int s_w[kOffThreads / kWave];
+  __shared__ int s_stat[kMaxViews][3];
+  const int tid = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  for (int q = tid; q < nv * 3; q += kOffThreads) s_stat[q / 3][q % 3] = 0;
+  __syncthreads();
+  int sum = 0;
+  for (int m = 0; m < kOffPer; ++m) {
+    const int64_t e = c * kOffChunk + (int64_t)m * kOffThreads + tid;
+    if (e < total) {
+      const int4 bs = reinterpret_cast<const int4*>(bstat)[e];
+      const int v = (int)(e % nv);
+      sum += bs.z;
+      if (bs.x) atomicAdd(&s_stat[v][0], bs.x);
+      if (bs.y) atomicAdd(&s_stat[v][1], bs.y);
+      if (bs.z) atomicAdd(&s_stat[v][2], bs.z);
+    }
   }
-  for (int q = tid; q < nv * 3; q += 1024) stats[(q / 3) * 4 + (q % 3)] = s_stat[q / 3][q % 3];
+  int tot;
+  (void)block_exclusive_scan(sum, s_w, tot);
+  if (tid == 0) csum[c] = tot;
+  for (int q = tid; q < nv * 3; q += kOffThreads) cstat[(c * nv + q / 3) * 3 + q % 3] = s_stat[q / 3][q % 3];
+}
+
+__global__ __launch_bounds__(1024) void k_off_top(int32_t* __restrict__ csum, int nchunk, int nv,
+                                                  const int32_t* __restrict__ cstat,
+                                                  int32_t* __restrict__ counters,
+                                                  int32_t* __restrict__ stats, int64_t cap_surv) {
+  __shared__ int s_w[1024 / kWave];
+  const int tid = threadIdx.x;
+  const int per = (nchunk + 1023) / 1024;
+  const int c0 = min(nchunk, tid * per), c1 = min(nchunk, c0 + per);
+  int sum = 0;
+  for (int c = c0; c < c1; ++c) sum += csum[c];
+  int tot;
+  int run = block_exclusive_scan(sum, s_w, tot);
+  for (int c = c0; c < c1; ++c) {
+    const int x = csum[c];
+    csum[c] = run;
+    run += x;
+  }
+  if (tid == 0) {
+    counters[S3R_CNT_SURV] = (int32_t)min((int64_t)tot, cap_surv);
+    counters[S3R_CNT_OVF_SURV] = (int32_t)max((int64_t)0, (int64_t)tot - cap_surv);
+  }
+  for (int q = tid; q < nv * 3; q += 1024) {
+    int acc = 0;
+    for (int c = 0; c < nchunk; ++c) acc += cstat[((int64_t)c * nv + q / 3) * 3 + q % 3];
+    stats[(q / 3) * 4 + (q % 3)] = acc;
+  }
+}
+
+__global__ __launch_bounds__(kOffThreads) void k_off_down(int32_t* __restrict__ bstat,
+                                                         int64_t total,
+                                                         const int32_t* __restrict__ csum,
+                                                         int64_t cap_surv) {
+  __shared__ int s_w[kOffThreads / kWave];
+  const int tid = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  // thread t takes the kOffPer consecutive entries c*kOffChunk + t*kOffPer + m
+  int cnt[kOffPer];
+  int sum = 0;
+#pragma unroll
+  for (int m = 0; m < kOffPer; ++m) {
+    const int64_t e = c * kOffChunk + (int64_t)tid * kOffPer + m;
+    cnt[m] = e < total ? bstat[e * 4 + 2] : 0;
+    sum += cnt[m];
+  }
+  int tot;
+  int64_t run = (int64_t)csum[c] + block_exclusive_scan(sum, s_w, tot);
+#pragma unroll
+  for (int m = 0; m < kOffPer; ++m) {
+    const int64_t e = c * kOffChunk + (int64_t)tid * kOffPer + m;
+    if (e < total) bstat[e * 4 + 3] = (int32_t)min(run, cap_surv);
+    run += cnt[m];
+  }
 }
 
 // Phase C: records of the survivors, at the slots given by the block offsets.
@@ -407,10 +463,22 @@ hipError_t launch_plain_transform(const float* mean, const float* quat, const in
 
 int project_blocks(int64_t n) { return (int)((n + kProjBlock - 1) / kProjBlock); }
 
+int offset_chunks(int64_t nblk, int nv) {
+  return (int)((nblk * nv + kOffChunk - 1) / kOffChunk);
+}
+
 hipError_t launch_project(const ProjArgs& a, int32_t* stats, hipStream_t st) {
   if (a.nblk > 0) S3R_LAUNCH(K_PROJECT, k_cull, dim3(a.nblk), dim3(kProjBlock), 0, st, a);
-  S3R_LAUNCH(K_STATS, k_block_offsets, dim3(1), dim3(1024), 0, st, a.bstat, a.nblk, a.nv,
-             a.counters, stats, a.kp.cap_surv);
+  const int64_t total = (int64_t)a.nblk * a.nv;
+  const int nchunk = offset_chunks(a.nblk, a.nv);
+  if (nchunk > 0)
+    S3R_LAUNCH(K_STATS, k_off_reduce, dim3(nchunk), dim3(kOffThreads), 0, st, a.bstat, total, a.nv,
+               a.chunk_sum, a.chunk_stat);
+  S3R_LAUNCH(K_STATS, k_off_top, dim3(1), dim3(1024), 0, st, a.chunk_sum, nchunk, a.nv,
+             a.chunk_stat, a.counters, stats, a.kp.cap_surv);
+  if (nchunk > 0)
+    S3R_LAUNCH(K_STATS, k_off_down, dim3(nchunk), dim3(kOffThreads), 0, st, a.bstat, total,
+               a.chunk_sum, a.kp.cap_surv);
   if (a.nblk > 0) S3R_LAUNCH(K_RECORDS, k_records, dim3(a.nblk), dim3(kProjBlock), 0, st, a);
   return hipGetLastError();
 }

@@ -36,6 +36,7 @@ struct WsSort {
   int32_t* hist;
   int32_t* sums;
   int32_t* misc;
+  int32_t* order_cnt;
 };
 struct WsBwd {
   float4* g2d;
@@ -70,6 +71,8 @@ size_t ws_sort(const S3RSizes& z, WsSort* w, char* base) {
   off += align_up((size_t)sb * 4 + 4);
   if (w) w->misc = reinterpret_cast<int32_t*>(base + off);
   off += align_up(64);
+  if (w) w->order_cnt = reinterpret_cast<int32_t*>(base + off);
+  off += align_up(order_count_words(z.total_tiles) * 4);
   return off;
 }
 
@@ -329,6 +332,7 @@ int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* vi
   a.hist = w.hist;
   a.scan_sums = w.sums;
   a.misc = w.misc;
+  a.order_cnt = w.order_cnt;
   a.cap_dup = params->cap_dup;
   a.cap_surv = params->cap_surv;
   S3R_HIP(launch_sort(a, as_stream(stream)));

@@ -193,10 +193,12 @@ struct SortArgs {
   int32_t* hist;       // [256 * scan_blocks(cap_dup)]
   int32_t* scan_sums;
   int32_t* misc;       // [0] total pairs, [1] histogram total
+  int32_t* order_cnt;  // [order_count_words] per (bucket, chunk) tile counts
   int64_t cap_dup, cap_surv;
 };
 int radix_passes(int total_tiles);
 size_t sort_hist_words(int64_t cap_dup);
+size_t order_count_words(int total_tiles);
 hipError_t launch_sort(const SortArgs& a, hipStream_t st);
 
 // raster.hip

@@ -308,56 +308,114 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
 // Launch order of the rasterizer: tiles by descending list length, so the
 // longest lists (whose waves set the critical path) start first.  Lengths are
 // bucketed by their binary logarithm (empty lists last) and the order within
-// a bucket is the tile order: a stable counting sort in one workgroup, each
-// thread owning a contiguous run of tiles.  Also writes each view's number
-// of (tile, record) pairs.
-constexpr int kOrderThreads = 1024;
+// a bucket is the tile order: a stable counting sort over chunks of
+// kOrderChunk tiles (per-chunk bucket counts, a one-workgroup scan over
+// (bucket, chunk), per-chunk placement).  The top kernel also writes each
+// view's number of (tile, record) pairs.
 constexpr int kOrderBuckets = 17;
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const int32_t* __restrict__ start,
-                                                             int total_tiles,
-                                                             const int32_t* __restrict__ toff,
-                                                             int nv, int32_t* __restrict__ order,
-                                                             int32_t* __restrict__ stats) {
-  __shared__ int cnt[kOrderBuckets * kOrderThreads];
-  __shared__ int s_part[kOrderThreads / kWave];
-  const int i = threadIdx.x;
-  const int chunk = (total_tiles + kOrderThreads - 1) / kOrderThreads;
-  const int lo = min(total_tiles, i * chunk), hi = min(total_tiles, lo + chunk);
-  auto bucket = [&](int t) {
-    const int len = start[t + 1] - start[t];
-    return len <= 0 ? kOrderBuckets - 1 : 15 - min(15, 31 - __builtin_clz((unsigned)len));
-  };
-  for (int b = 0; b < kOrderBuckets; ++b) cnt[b * kOrderThreads + i] = 0;
-  for (int t = lo; t < hi; ++t) cnt[bucket(t) * kOrderThreads + i] += 1;
+constexpr int kOrderThreads = 256;
+constexpr int kOrderPer = 4;
+constexpr int kOrderChunk = kOrderThreads * kOrderPer;
+
+__device__ __forceinline__ int order_bucket(const int32_t* start, int t) {
+  const int len = start[t + 1] - start[t];
+  return len <= 0 ? kOrderBuckets - 1 : 15 - min(15, 31 - __builtin_clz((unsigned)len));
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_order_count(const int32_t* __restrict__ start,
+                                                              int total_tiles, int nchunk,
+                                                              int32_t* __restrict__ cnt) {
+  __shared__ int s_c[kOrderBuckets];
+  const int tid = threadIdx.x, c = blockIdx.x;
+  if (tid < kOrderBuckets) s_c[tid] = 0;
   __syncthreads();
-  // exclusive scan of cnt in (bucket, thread) order: thread i scans the
-  // kOrderBuckets consecutive entries starting at i * kOrderBuckets
-  int run = 0;
-  for (int k = 0; k < kOrderBuckets; ++k) run += cnt[i * kOrderBuckets + k];
-  int incl = run;
+  for (int m = 0; m < kOrderPer; ++m) {
+    const int t = c * kOrderChunk + m * kOrderThreads + tid;
+    if (t < total_tiles) atomicAdd(&s_c[order_bucket(start, t)], 1);
+  }
+  __syncthreads();
+  if (tid < kOrderBuckets) cnt[tid * nchunk + c] = s_c[tid];  // bucket-major
+}
+
+__global__ __launch_bounds__(1024) void k_order_top(int32_t* __restrict__ cnt, int n,
+                                                    const int32_t* __restrict__ start,
+                                                    const int32_t* __restrict__ toff, int nv,
+                                                    int32_t* __restrict__ stats) {
+  __shared__ int s_w[1024 / kWave];
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int per = (n + 1023) / 1024;
+  const int e0 = min(n, tid * per), e1 = min(n, e0 + per);
+  int sum = 0;
+  for (int e = e0; e < e1; ++e) sum += cnt[e];
+  int incl = sum;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     const int y = __shfl_up(incl, o, kWave);
-    if ((i % kWave) >= o) incl += y;
+    if (lane >= o) incl += y;
   }
-  if ((i % kWave) == kWave - 1) s_part[i / kWave] = incl;
+  if (lane == kWave - 1) s_w[wave] = incl;
   __syncthreads();
-  int base = incl - run;
-  for (int w = 0; w < i / kWave; ++w) base += s_part[w];
+  int run = incl - sum;
+  for (int w = 0; w < wave; ++w) run += s_w[w];
+  for (int e = e0; e < e1; ++e) {
+    const int x = cnt[e];
+    cnt[e] = run;
+    run += x;
+  }
+  if (tid < nv) stats[tid * 4 + 3] = start[toff[tid + 1]] - start[toff[tid]];
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_order_place(const int32_t* __restrict__ start,
+                                                              int total_tiles, int nchunk,
+                                                              const int32_t* __restrict__ cnt,
+                                                              int32_t* __restrict__ order) {
+  // per (bucket, thread) counts of the chunk, scanned in (bucket, thread) order
+  __shared__ int s_c[kOrderBuckets * kOrderThreads];
+  __shared__ int s_w[kOrderThreads / kWave];
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave, c = blockIdx.x;
+  const int t0 = c * kOrderChunk + tid * kOrderPer;  // this thread's consecutive tiles
+  int bk[kOrderPer];
+  for (int b = 0; b < kOrderBuckets; ++b) s_c[b * kOrderThreads + tid] = 0;
+#pragma unroll
+  for (int m = 0; m < kOrderPer; ++m) {
+    const int t = t0 + m;
+    bk[m] = t < total_tiles ? order_bucket(start, t) : -1;
+    if (bk[m] >= 0) s_c[bk[m] * kOrderThreads + tid] += 1;
+  }
+  __syncthreads();
+  // thread i scans entries i*17 .. i*17+16 of the linear (bucket, thread) order
+  int sum = 0;
+  for (int k = 0; k < kOrderBuckets; ++k) sum += s_c[tid * kOrderBuckets + k];
+  int incl = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  if (lane == kWave - 1) s_w[wave] = incl;
+  __syncthreads();
+  int run = incl - sum;
+  for (int w = 0; w < wave; ++w) run += s_w[w];
   __syncthreads();
   for (int k = 0; k < kOrderBuckets; ++k) {
-    const int c = cnt[i * kOrderBuckets + k];
-    cnt[i * kOrderBuckets + k] = base;
-    base += c;
+    const int x = s_c[tid * kOrderBuckets + k];
+    s_c[tid * kOrderBuckets + k] = run;
+    run += x;
   }
   __syncthreads();
-  for (int t = lo; t < hi; ++t) {
-    const int b = bucket(t);
-    const int pos = cnt[b * kOrderThreads + i];
-    cnt[b * kOrderThreads + i] = pos + 1;
-    order[pos] = t;
+  // in-chunk position = scanned (bucket, thread) entry minus the chunk-local
+  // start of the bucket; global position = the (bucket, chunk) offset plus it
+  __shared__ int s_base[kOrderBuckets];
+  if (tid < kOrderBuckets) s_base[tid] = s_c[tid * kOrderThreads];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < kOrderPer; ++m) {
+    if (bk[m] < 0) continue;
+    const int b = bk[m];
+    const int in_chunk = s_c[b * kOrderThreads + tid] - s_base[b];
+    s_c[b * kOrderThreads + tid] += 1;
+    order[cnt[b * nchunk + c] + in_chunk] = t0 + m;
   }
-  if (i < nv) stats[i * 4 + 3] = start[toff[i + 1]] - start[toff[i]];
 }
 
 int radix_passes(int total_tiles) {
@@ -367,6 +425,10 @@ int radix_passes(int total_tiles) {
 }
 
 size_t sort_hist_words(int64_t cap_dup) { return (size_t)256 * scan_blocks(cap_dup); }
+
+size_t order_count_words(int total_tiles) {
+  return (size_t)kOrderBuckets * ((total_tiles + kOrderChunk - 1) / kOrderChunk) + 4;
+}
 
 hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
   // 1. pairs per record -> first pair of each record
@@ -404,8 +466,17 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
     S3R_LAUNCH(K_TILE_RANGES, k_tile_ranges, dim3(grid), dim3(256), 0, st, sorted,
                a.counters + S3R_CNT_DUP, a.total_tiles, a.tile_start, a.tile_count);
   }
-  S3R_LAUNCH(K_TILE_ORDER, k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, a.tile_start,
-             a.total_tiles, a.tile_offset, a.nv, a.tile_order, a.stats);
+  {
+    const int nchunk = (a.total_tiles + kOrderChunk - 1) / kOrderChunk;
+    if (nchunk > 0)
+      S3R_LAUNCH(K_TILE_ORDER, k_order_count, dim3(nchunk), dim3(kOrderThreads), 0, st,
+                 a.tile_start, a.total_tiles, nchunk, a.order_cnt);
+    S3R_LAUNCH(K_TILE_ORDER, k_order_top, dim3(1), dim3(1024), 0, st, a.order_cnt,
+               kOrderBuckets * nchunk, a.tile_start, a.tile_offset, a.nv, a.stats);
+    if (nchunk > 0)
+      S3R_LAUNCH(K_TILE_ORDER, k_order_place, dim3(nchunk), dim3(kOrderThreads), 0, st,
+                 a.tile_start, a.total_tiles, nchunk, a.order_cnt, a.tile_order);
+  }
   return hipGetLastError();
 }
 

@@ -102,8 +102,11 @@ def log(msg):
 
 
 def make_renderer(cfg, plain):
+    """The streamlined renderer clears only the gradient rows its previous
+    backward wrote (sparse gradient mode); the plain route keeps dense
+    world-frame gradient arrays, as the conventional pipeline does."""
     from paper_2503_08217_amd.renderer import Renderer
-    params = dict(cfg.params)
+    params = dict(cfg.params, grad_sparse=not plain)
     if plain:
         params.update(temporal=False, lod=False, lod_r=0.0)
     first = cfg.views.subset([cfg.timed_views[0]])
@@ -311,6 +314,50 @@ def lod_temporal_sweep(cfg, targets, torch, steps=16):
     return out
 
 
+def scale_up(torch, lengths, steps=16):
+    """Per-view fwd+bwd time as the corridor grows at constant density and
+    camera (1700 static Gaussians per metre, 30 instances per km, one frame
+    every 20 m), streamlined vs plain: the paper's scale-up experiment."""
+    import scenes
+    out = []
+    for L in lengths:
+        t0 = time.perf_counter()
+        cfg = scenes.make_scaleup(L)
+        tg_np = scenes.targets(cfg.cfg, cfg.views, cfg.timed_views)
+        targets = [torch.as_tensor(t.ravel()).cuda().contiguous() for t in tg_np]
+        row = {"length_m": L, "gaussians": int(cfg.scene.n), "timesteps": int(cfg.views.n_views),
+               "generated_s": time.perf_counter() - t0}
+        for plain in (False, True):
+            r = make_renderer(cfg, plain)
+            if not plain:
+                warmup_temporal(r, cfg, torch)
+            handles = r.prepare_views([cfg.views.subset([v]) for v in cfg.timed_views])
+            for h in handles:
+                r.use_views(h)
+                r.fit_capacity()
+            handles = r.prepare_views([cfg.views.subset([v]) for v in cfg.timed_views])
+            units = view_units(r, handles, targets, torch)
+            for i in range(4):
+                r.use_views(handles[i % len(handles)])
+                r.step(targets[i % len(handles)])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for i in range(steps):
+                r.use_views(handles[i % len(handles)])
+                r.step(targets[i % len(handles)])
+            torch.cuda.synchronize()
+            ms = 1000 * (time.perf_counter() - t1) / steps
+            mean = {k: float(np.mean([u[k] for u in units])) for k in ("N_t", "N_r", "N_dup")}
+            row["plain" if plain else "streamlined"] = dict(ms_per_view=ms, **mean)
+            del r
+            torch.cuda.empty_cache()
+        log(f"scale-up {L:6.0f} m, N={row['gaussians']}: streamlined "
+            f"{row['streamlined']['ms_per_view']:.3f} ms/view (N_t {row['streamlined']['N_t']:.0f},"
+            f" N_r {row['streamlined']['N_r']:.0f}), plain {row['plain']['ms_per_view']:.3f} ms/view")
+        out.append(row)
+    return out
+
+
 def batched_graph(cfg, torch, replays, tiles):
     """Batched multi-view step (all timed views of the workload in one batch)
     captured in a HIP graph; tile size picked by timing each candidate."""
@@ -339,7 +386,7 @@ def batched_graph(cfg, torch, replays, tiles):
     best = None
     tune = []
     for tile in tiles:
-        params = dict(cfg.params, tile=tile)
+        params = dict(cfg.params, tile=tile, grad_sparse=True)
         r = Renderer(cfg.scene, views, params, cap_surv=max(1024, cfg.scene.n // 2),
                      cap_dup=max(4096, 2 * cfg.scene.n))
         r.vis_s.copy_(vis_s)
@@ -412,6 +459,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the LOD threshold x temporal filter grid")
     ap.add_argument("--replays", type=int, default=100)
+    ap.add_argument("--scale-up", action="store_true",
+                    help="per-view time vs corridor length (125 m .. 3 km), then exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run a plain copy of this many MiB first (for counter calibration)")
     a = ap.parse_args()
@@ -426,6 +475,11 @@ def main():
 
     if a.copy_calibration > 0:
         copy_calibration(a.copy_calibration, torch)
+    if a.scale_up:
+        rows = scale_up(torch, (125.0, 250.0, 500.0, 1000.0, 2000.0, 3000.0), steps=a.steps)
+        print(json.dumps({"metric": "per-view fwd+bwd ms vs corridor length, streamlined vs plain",
+                          "unit": "ms/view", "data": "synthetic", "rows": rows}), flush=True)
+        return
     t_gen = time.perf_counter()
     cfg = scenes.make_config(a.config)
     cfg.params["tile"] = a.tile

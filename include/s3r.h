@@ -79,9 +79,12 @@ enum {
   S3R_LOD = 2,      /* apply the LOD cull with threshold lod_r (Sec. 3.3)  */
   S3R_PLAIN = 4,    /* project the world-frame arrays of s3r_plain_transform
                        with the view camera (conventional route, Sec. 3.1) */
-  S3R_LOD_STOCHASTIC = 8 /* Eq. (7): drop a sub-threshold Gaussian with
+  S3R_LOD_STOCHASTIC = 8, /* Eq. (7): drop a sub-threshold Gaussian with
                        probability p = p_max + (p_max - 0.01) min(0, (d - D)/D)
                        instead of always (needs S3R_LOD)                   */
+  S3R_GRAD_SPARSE = 16 /* s3r_raster_bwd clears only the gradient rows it
+                       wrote on the previous call (S3RGrads.rows) instead of
+                       the whole arrays; streamlined route only            */
 };
 
 /* modes of s3r_update_visibility */
@@ -206,6 +209,16 @@ typedef struct S3RGrads {
   /* plain route only: world-frame gradients, [n_plain_slots][N][3] / [..][9] */
   float* mean_w;
   float* rot_w;
+  /* S3R_GRAD_SPARSE only: rows[0 .. *n_rows) lists Gaussians whose rows of
+     mean / scale / quat / opacity / sh may be nonzero (written by the
+     previous call; entries of -1 are ignored).  A call clears those rows,
+     writes its own, and replaces the list: one entry per record, the
+     Gaussian for the record that is its Gaussian's first in the batch, -1
+     for the others.  Before the first
+     call the caller zeroes the arrays once and sets *n_rows = 0; between
+     calls it must not write the arrays.  [cap_surv] and [1], device. */
+  int32_t* rows;
+  int32_t* n_rows;
 } S3RGrads;
 
 /* Sizes used to plan workspaces. */

@@ -270,6 +270,8 @@ __device__ __forceinline__ void project_bwd_owner(const ProjBwdArgs& a, int r0, 
   }
   const int k = active ? clampi(a.inst[i], 0, a.n_slots - 1) : 0;
   const int vb = i / kProjBlock, wave = (i % kProjBlock) / kWave, bit = i % kWave;
+  // sparse gradient mode: the owners' Gaussians are the rows this call writes
+  if (a.rows && r0 < nrec) a.rows[r0] = active ? i : -1;
 
   // the Gaussian's parameters (local frame)
   float mx = 0.f, my = 0.f, mz = 0.f, sc[3] = {1.f, 1.f, 1.f}, Rl[9];
@@ -594,6 +596,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
   const int stride = gridDim.x * blockDim.x;
   for (int base = blockIdx.x * blockDim.x; base < nrec; base += stride)
     project_bwd_owner(a, base + (int)threadIdx.x, nrec);
+  if (a.n_rows && blockIdx.x == 0 && threadIdx.x == 0) *a.n_rows = nrec;
 }
 
 // dL/dG_{tau,k} += W_R^T dL/dP_{v,k} for every view v (slot 0 skipped)
@@ -768,6 +771,47 @@ __global__ __launch_bounds__(256) void k_zero_plain_w(const int32_t* __restrict_
     if (tm < ns * n * 3) m[tm] = 0.f;
     if (tr < ns * n * 9) r[tr] = 0.f;
   }
+}
+
+// Sparse gradient mode: clear the rows the previous call wrote, and record
+// the Gaussians whose rows this call writes (its records' Gaussians).
+__global__ __launch_bounds__(256) void k_clear_rows(const int32_t* __restrict__ rows,
+                                                    const int32_t* __restrict__ n_rows, int64_t n,
+                                                    int B, float* __restrict__ mean,
+                                                    float* __restrict__ scale,
+                                                    float* __restrict__ quat,
+                                                    float* __restrict__ opac,
+                                                    float* __restrict__ sh) {
+  const int cnt = *n_rows;
+  const int stride = gridDim.x * blockDim.x;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += stride) {
+    const int i = rows[j];
+    if (i < 0 || i >= n) continue;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      mean[3 * (size_t)i + c] = 0.f;
+      scale[3 * (size_t)i + c] = 0.f;
+    }
+    reinterpret_cast<float4*>(quat)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    opac[i] = 0.f;
+    float* s = sh + (size_t)i * 3 * B;
+    if (((3 * B) & 3) == 0) {
+      float4* s4 = reinterpret_cast<float4*>(s);
+      for (int t = 0; t < (3 * B) / 4; ++t) s4[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      for (int t = 0; t < 3 * B; ++t) s[t] = 0.f;
+    }
+  }
+}
+
+hipError_t launch_clear_rows(const int32_t* rows, const int32_t* n_rows, int64_t n, int B,
+                             float* mean, float* scale, float* quat, float* opac, float* sh,
+                             int64_t cap, hipStream_t st) {
+  const int64_t want = (cap + 255) / 256;
+  const int grid = (int)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+  S3R_LAUNCH(K_ZERO, k_clear_rows, dim3(grid), dim3(256), 0, st, rows, n_rows, n, B, mean, scale,
+             quat, opac, sh);
+  return hipGetLastError();
 }
 
 hipError_t launch_project_bwd(const ProjBwdArgs& a, hipStream_t st) {

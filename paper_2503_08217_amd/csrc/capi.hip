@@ -428,6 +428,11 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
     S3R_REQUIRE(g->quat);
   }
   if (g->pose6 && !aligned16(g->pose6)) return S3R_E_ALIGN;
+  const bool sparse = (params->flags & S3R_GRAD_SPARSE) != 0 && !plain;
+  if (sparse) {
+    S3R_REQUIRE(g->rows);
+    S3R_REQUIRE(g->n_rows);
+  }
   const S3RSizes z = sizes_of(scene, views, params);
   if (!ws || ws_bytes < ws_bwd(z, nullptr, nullptr)) return S3R_E_WORKSPACE;
   if (!aligned16(ws)) return S3R_E_ALIGN;
@@ -441,12 +446,17 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
     // (Gaussians without records keep these zeros) and the accumulators
     const size_t N = (size_t)scene->n;
     const size_t B = (size_t)(scene->sh_degree + 1) * (scene->sh_degree + 1);
-    void* ps[7] = {w.d_cam, g->pose, g->scale, g->opacity, g->sh, plain ? nullptr : g->mean,
-                   plain ? nullptr : g->quat};
+    const bool dense = !sparse;
+    void* ps[7] = {w.d_cam, g->pose, dense ? g->scale : nullptr, dense ? g->opacity : nullptr,
+                   dense ? g->sh : nullptr, (plain || !dense) ? nullptr : g->mean,
+                   (plain || !dense) ? nullptr : g->quat};
     const size_t bs[7] = {(size_t)views->n_views * scene->n_slots * 48,
                           (size_t)scene->n_timesteps * scene->n_slots * 48, N * 12, N * 4,
                           N * B * 12, N * 12, N * 16};
     S3R_HIP(launch_zero_n(ps, bs, 7, st));
+    if (sparse)
+      S3R_HIP(launch_clear_rows(g->rows, g->n_rows, scene->n, (int)B, g->mean, g->scale, g->quat,
+                                g->opacity, g->sh, params->cap_surv, st));
   }
   BwdArgs b{};
   b.rec_geo = reinterpret_cast<const float4*>(proj->rec_geo);
@@ -508,6 +518,8 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   p.d_cam = w.d_cam;
   p.d_pose = g->pose;
   p.kp = kp;
+  p.rows = sparse ? g->rows : nullptr;
+  p.n_rows = sparse ? g->n_rows : nullptr;
   S3R_HIP(launch_project_bwd(p, st));
   if (!plain)
     S3R_HIP(launch_pose_bwd(views->W, views->tstep, scene->pose, w.d_cam, views->n_views,

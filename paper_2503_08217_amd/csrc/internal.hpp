@@ -143,6 +143,8 @@ struct ProjBwdArgs {
   float* d_sh;
   float* d_mean_w;
   float* d_rot_w;
+  int32_t* rows;   // sparse gradient mode: [cap_surv] owner Gaussian or -1
+  int32_t* n_rows;  // (null in the dense mode)
   float* d_cam;    // [V][S][12] workspace
   float* d_pose;   // [T][S][12] (plain route: colour-direction part)
   KParams kp;
@@ -210,6 +212,10 @@ hipError_t launch_l1_loss(const float* color, const float* target, const int64_t
 // backward.hip
 hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st);
 hipError_t launch_project_bwd(const ProjBwdArgs& a, hipStream_t st);
+hipError_t launch_clear_rows(const int32_t* rows, const int32_t* n_rows, int64_t n, int B,
+                             float* mean, float* scale, float* quat, float* opac, float* sh,
+                             int64_t cap, hipStream_t st);
+
 hipError_t launch_pose_bwd(const float* W, const int32_t* tstep, const float* pose,
                            const float* d_cam, int nv, int S, int T, float* d_pose,
                            float* d_pose6, hipStream_t st);

@@ -169,6 +169,9 @@ class Renderer:
         self.g_sh = torch.zeros(n, self.B, 3, device=d, dtype=f32)
         self.g_pose = torch.zeros(self.T, S, 12, device=d, dtype=f32)
         self.g_pose6 = torch.zeros(self.T, S, 6, device=d, dtype=f32)
+        # rows written by the last backward (sparse gradient mode)
+        self.g_rows = torch.zeros(max(1, cs), device=d, dtype=i32)
+        self.g_n_rows = torch.zeros(4, device=d, dtype=i32)
         if self.plain:
             self.g_mean_w = torch.zeros(n_ts, n, 3, device=d, dtype=f32)
             self.g_rot_w = torch.zeros(n_ts, n, 9, device=d, dtype=f32)
@@ -202,7 +205,7 @@ class Renderer:
         self.c_grads = A.S3RGrads(
             _ptr(self.g_mean), _ptr(self.g_scale), _ptr(self.g_quat), _ptr(self.g_opacity),
             _ptr(self.g_sh), _ptr(self.g_pose), _ptr(self.g_pose6), _ptr(self.g_mean_w),
-            _ptr(self.g_rot_w))
+            _ptr(self.g_rot_w), _ptr(self.g_rows), _ptr(self.g_n_rows))
 
     def make_params(self):
         p = self.params
@@ -215,6 +218,8 @@ class Renderer:
             flags |= A.S3R_PLAIN
         if p.get("lod_stochastic", False):
             flags |= A.S3R_LOD_STOCHASTIC
+        if p.get("grad_sparse", False):
+            flags |= A.S3R_GRAD_SPARSE
         bg = (C.c_float * 3)(*[float(x) for x in p["bg"]])
         return A.S3RParams(int(p["tile"]), flags, float(p["lod_r"]), float(p["z_near"]),
                            float(p["z_far"]), float(p["eps2d"]), float(p["alpha_min"]),
@@ -257,8 +262,11 @@ class Renderer:
                 "s3r_l1_loss")
 
     def zero_grads(self):
+        """Clear every gradient array and the sparse-mode row list.  The
+        backward writes the gradients itself; this is only for starting over
+        (and required once before the first sparse-mode backward)."""
         for t in (self.g_mean, self.g_scale, self.g_quat, self.g_opacity, self.g_sh, self.g_pose,
-                  self.g_pose6, self.g_mean_w, self.g_rot_w):
+                  self.g_pose6, self.g_mean_w, self.g_rot_w, self.g_n_rows):
             if t is not None:
                 t.zero_()
 

@@ -46,7 +46,7 @@ def test_struct_sizes_match_c_layout():
     assert C.sizeof(A.S3RViews) == 7 * 8 + 16
     assert C.sizeof(A.S3RProjected) == 15 * 8
     assert C.sizeof(A.S3RBins) == 4 * 8
-    assert C.sizeof(A.S3RGrads) == 9 * 8
+    assert C.sizeof(A.S3RGrads) == 11 * 8
     assert C.sizeof(A.S3RSizes) == 40
 
 

@@ -13,6 +13,7 @@ from .corridor import (  # noqa: F401
     Views,
     default_params,
     make_config,
+    make_scaleup,
     micro_scene,
     targets,
 )

@@ -338,6 +338,28 @@ def make_config(cfg: int, *, scale_n: float = 1.0) -> Config:
     raise ValueError(f"unknown config {cfg}")
 
 
+def make_scaleup(length_m: float, *, density: float = 1700.0, inst_per_km: float = 30.0,
+                 spacing_m: float = 20.0, scale_n: float = 1.0) -> Config:
+    """Corridors of growing length at the mid corridor's density and camera
+    (1700 static Gaussians per metre, 30 instances of 10k per km, one 1920x1080
+    frame every `spacing_m` metres): the per-view cost as the scene grows,
+    the paper's scale-up experiment with synthetic streets."""
+    L = float(length_m)
+    rng = np.random.default_rng(SEED_BASE + 600 + int(round(L)))
+    T = max(2, int(round(L / spacing_m)))
+    static = _corridor_static(rng, max(1, int(round(density * L * scale_n))), L)
+    K = max(1, int(round(inst_per_km * L / 1000.0)))
+    local = [_box(rng, max(1, int(round(10_000 * scale_n))), 2.25, 1.0, 0.75) for _ in range(K)]
+    x_end = max(L - 50.0, 0.5 * L)
+    poses = _tracks(rng, K, T, min(10.0, 0.1 * L), max(x_end - 50.0, 0.2 * L))
+    scene = _assemble(rng, static, local, 3, 0.1, poses)
+    views = _forward_views(T, x_end, 1920, 1080, range(T))
+    params = default_params(tile=16, lod_r=1.0, temporal=True, lod=True)
+    timed = sorted(set(int(round(i * (T - 1) / 7)) for i in range(8)))
+    return Config(100 + int(round(L)), f"scaleup-{int(round(L))}m", scene, views, params, timed,
+                  warmup_fold=True)
+
+
 def micro_scene(seed: int, n: int = 8, width: int = 24, height: int = 20,
                 n_inst: int = 1, sh_degree: int = 1, T: int = 2,
                 spread: float = 1.0):

@@ -28,9 +28,14 @@ import math
 import numpy as np
 
 
-def composite(xs, ys, order, u, v, conic, opac, rgb, params, delta=1e-4):
+def composite(xs, ys, order, u, v, conic, opac, rgb, params, delta=1e-4, track=None):
     """xs, ys: (P,) pixel coordinates.  `order`: contributor ids in blending
-    order; u, v, opac (N,), conic (N,3), rgb (N,3) indexed by id.  FP64."""
+    order; u, v, opac (N,), conic (N,3), rgb (N,3) indexed by id.  FP64.
+
+    With a dict `track`, also records per Gaussian id whether it was blended
+    into at least one pixel (`track["took"]`, a set) and whether it was
+    evaluated at a pixel whose decisions lie in the guard band
+    (`track["uncertain"]`, a set): the rendering-derived visibility."""
     xs = np.asarray(xs, np.float64)
     ys = np.asarray(ys, np.float64)
     P = xs.size
@@ -59,6 +64,11 @@ def composite(xs, ys, order, u, v, conic, opac, rgb, params, delta=1e-4):
         flag |= act & (np.abs(Tn - tmin) <= delta * tmin)
         stop = act & (Tn < tmin)
         con = act & ~stop
+        if track is not None:
+            if con.any():
+                track["took"].add(int(i))
+            if (ev & flag).any():
+                track["uncertain"].add(int(i))
         C += np.where(con[:, None], np.asarray(rgb[i], np.float64)[None, :] * (alpha * T)[:, None], 0.0)
         T = np.where(con, Tn, T)
         ncon += con
@@ -67,8 +77,9 @@ def composite(xs, ys, order, u, v, conic, opac, rgb, params, delta=1e-4):
     return C + T[:, None] * bg[None, :], T, ncon, flag
 
 
-def composite_scalar(x, y, order, u, v, conic, opac, rgb, params):
-    """One pixel, plain Python floats and loops (brute force)."""
+def composite_scalar(x, y, order, u, v, conic, opac, rgb, params, took=None):
+    """One pixel, plain Python floats and loops (brute force); ids blended
+    into the pixel are added to the set `took` when one is given."""
     Cr = [0.0, 0.0, 0.0]
     T = 1.0
     n = 0
@@ -89,4 +100,6 @@ def composite_scalar(x, y, order, u, v, conic, opac, rgb, params):
             Cr[ch] += float(rgb[i][ch]) * alpha * T
         T = Tn
         n += 1
+        if took is not None:
+            took.add(int(i))
     return [Cr[ch] + T * params["bg"][ch] for ch in range(3)], T, n

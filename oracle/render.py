@@ -79,6 +79,30 @@ def render_view(scene, views, v, params, plain=False, region=None, with_image=Tr
     return out
 
 
+def raster_visible(scene, views, v, params, plain=False):
+    """Rendering-derived visibility of view v: the Gaussians blended into at
+    least one pixel (one reading of the visibility "obtained by the rendering
+    process"), plus those whose status rests on a guard-band decision.
+    Returns (took, uncertain) as boolean (N,) arrays."""
+    tr = {"took": set(), "uncertain": set()}
+    W34, Kv, wh, tau = views.W[v], views.K[v], views.wh[v], int(views.tstep[v])
+    d = decide32.project_cull32(scene, W34, Kv, wh, tau, params, plain=plain, view_index=v)
+    ids = np.nonzero(d["surv"])[0]
+    rgb = np.zeros((scene.n, 3))
+    if ids.size:
+        rgb[ids] = survivor_colours(scene, d, ids)[0]
+    xs, ys = view_pixels(int(wh[0]), int(wh[1]))
+    ordr = order.global_order(ids, d["depth_bits"])
+    conic = np.stack([d["conic_a"], d["conic_b"], d["conic_c"]], 1).astype(np.float64)
+    comp.composite(xs, ys, ordr, d["u"].astype(np.float64), d["v"].astype(np.float64), conic,
+                   scene.opacity.astype(np.float64), rgb, params, track=tr)
+    took = np.zeros(scene.n, bool)
+    unc = np.zeros(scene.n, bool)
+    took[list(tr["took"])] = True
+    unc[list(tr["uncertain"])] = True
+    return took, unc
+
+
 def tile_lists_of(d, ids, params):
     """Per-tile contributor lists of one view's survivors (see `order`)."""
     return order.tile_lists(ids, d["depth_bits"], d["x0"], d["x1"], d["y0"], d["y1"],

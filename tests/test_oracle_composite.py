@@ -93,3 +93,35 @@ def test_region_equals_full_image():
     full = render.render_view(c.scene, c.views, 0, c.params)
     part = render.render_view(c.scene, c.views, 0, c.params, region=(16, 32, 32, 48))
     np.testing.assert_allclose(part["image"], full["image"][:, 32:48, 16:32], atol=1e-14)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_rendering_visibility_equals_brute_force(seed):
+    """The rendering-derived visibility (Gaussians blended into at least one
+    pixel) equals the union over pixels of the scalar loop's contributors,
+    and is a subset of the survivors (M_t and the LOD test)."""
+    scene, views = scenes.micro_scene(seed, n=40, width=20, height=16, n_inst=1)
+    p = scenes.default_params(tile=8)
+    took, unc = render.raster_visible(scene, views, 0, p)
+    o = render.render_view(scene, views, 0, p)
+    d = o["dec"]
+    conic = np.stack([d["conic_a"], d["conic_b"], d["conic_c"]], 1).astype(float)
+    brute = set()
+    for y in range(16):
+        for x in range(20):
+            comp.composite_scalar(float(x), float(y), o["order"], d["u"], d["v"], conic,
+                                  scene.opacity, o["rgb"], p, took=brute)
+    np.testing.assert_array_equal(np.nonzero(took)[0], np.asarray(sorted(brute), dtype=np.int64))
+    assert not np.any(took & ~d["surv"])
+    assert took.sum() > 0
+
+
+def test_rendering_visibility_hidden_gaussian():
+    """A Gaussian behind an opaque stack is inside the frustum (in M_t) but
+    never blended: the rendering-derived visibility leaves it out."""
+    # three opacity-1 layers (alpha clamps to 0.99) then a fourth: T after two
+    # layers is 1e-4, so the third and fourth are never blended at the centre
+    u, v, con, o, rgb = _g([0.0] * 4, [0.0] * 4, [[1, 0, 1]] * 4, [1.0] * 4, [[1, 1, 1]] * 4)
+    tr = {"took": set(), "uncertain": set()}
+    comp.composite(np.array([0.0]), np.array([0.0]), [0, 1, 2, 3], u, v, con, o, rgb, P, track=tr)
+    assert tr["took"] == {0, 1}

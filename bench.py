@@ -114,17 +114,22 @@ def make_renderer(cfg, plain):
                     cap_dup=max(4096, 2 * cfg.scene.n))
 
 
-def warmup_temporal(r, cfg, torch):
+def warmup_temporal(r, cfg, torch, source="frustum"):
     """Temporal-visibility state after one pass over every timestep (Eq. 5),
-    folded into visibility intervals (Eq. 6)."""
+    folded into visibility intervals (Eq. 6).  `source` picks the visibility
+    that updates the point life: the frustum mask M_t, or "raster", the
+    Gaussians blended into at least one pixel (needs a full forward)."""
     from paper_2503_08217_amd import S3R_VIS_FOLD, S3R_VIS_UPDATE
     handles = r.prepare_views([cfg.views.subset([v]) for v in range(cfg.views.n_views)])
     saved = dict(r.params)
     r.set_flags(temporal=False)
     for h in handles:
         r.use_views(h)
-        r.project_cull()
-        r.update_visibility(S3R_VIS_UPDATE)
+        if source == "raster":
+            r.fit_capacity()
+        else:
+            r.project_cull()
+        r.update_visibility(S3R_VIS_UPDATE, source=source)
     r.update_visibility(S3R_VIS_FOLD)
     r.set_flags(**saved)
     torch.cuda.synchronize()
@@ -358,6 +363,46 @@ def scale_up(torch, lengths, steps=16):
     return out
 
 
+def visibility_sources(cfg, targets, torch, steps=16):
+    """The two readings of the visibility the rendering process yields: the
+    frustum mask M_t and the Gaussians blended into at least one pixel.  Each
+    drives the warm-up UPDATE and FOLD; reported: Gaussians passing the
+    temporal test per timed view, and views/s of the streamlined step."""
+    out = {}
+    for source in ("frustum", "raster"):
+        from paper_2503_08217_amd.renderer import Renderer
+        params = dict(cfg.params, grad_sparse=True, raster_mask=(source == "raster"),
+                      visibility_source=source)
+        first = cfg.views.subset([cfg.timed_views[0]])
+        r = Renderer(cfg.scene, first, params, cap_surv=max(1024, cfg.scene.n // 2),
+                     cap_dup=max(4096, 2 * cfg.scene.n))
+        warmup_temporal(r, cfg, torch, source=source)
+        handles = r.prepare_views([cfg.views.subset([v]) for v in cfg.timed_views])
+        for h in handles:
+            r.use_views(h)
+            r.fit_capacity()
+        handles = r.prepare_views([cfg.views.subset([v]) for v in cfg.timed_views])
+        units = view_units(r, handles, targets, torch)
+        for i in range(4):
+            r.use_views(handles[i % len(handles)])
+            r.step(targets[i % len(handles)])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            r.use_views(handles[i % len(handles)])
+            r.step(targets[i % len(handles)])
+        torch.cuda.synchronize()
+        vps = steps / (time.perf_counter() - t0)
+        out[source] = {"views_per_s": vps,
+                       "mean_N_t": float(np.mean([u["N_t"] for u in units])),
+                       "mean_N_r": float(np.mean([u["N_r"] for u in units]))}
+        log(f"visibility source {source}: {vps:.1f} views/s, N_t {out[source]['mean_N_t']:.0f}, "
+            f"N_r {out[source]['mean_N_r']:.0f}")
+        del r
+        torch.cuda.empty_cache()
+    return out
+
+
 def batched_graph(cfg, torch, replays, tiles):
     """Batched multi-view step (all timed views of the workload in one batch)
     captured in a HIP graph; tile size picked by timing each candidate."""
@@ -561,6 +606,7 @@ def main():
         out["plain_kernels_us_warmup"] = {k: 1000 * ms / cnt for k, (ms, cnt) in p["table"].items()}
     if not a.no_sweep and a.config == 3:
         out["sweep"] = lod_temporal_sweep(cfg, targets, torch)
+        out["visibility_source"] = visibility_sources(cfg, targets, torch)
     if not a.no_cpu:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -193,6 +193,14 @@ typedef struct S3RImage {
   float* color;   /* per view v: [3][h][w] planar at offset 3*px_offset[v]   */
   float* T_final; /* [total_px] transmittance after the last contributor     */
   int32_t* last;  /* [total_px] 1 + list position of the last contributor    */
+  /* optional rendering-derived visibility (NULL m_raster: not produced): bit i
+     of view v is set when Gaussian i was blended into at least one pixel of
+     view v -- a second reading of the visibility the rendering process gives
+     (Sec. 3.3), usable as the `mask` of s3r_update_visibility.  rec_taken is
+     per-record scratch [cap_surv]; n is the scene's N (sizes m_raster). */
+  uint32_t* m_raster; /* [V][ceil(N/64)*2], layout of S3RProjected.mask     */
+  int32_t* rec_taken;
+  int64_t n;
 } S3RImage;
 
 typedef struct S3RGrads {

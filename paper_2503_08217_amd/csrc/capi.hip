@@ -372,7 +372,21 @@ int s3r_raster_fwd(const S3RProjected* proj, const S3RBins* bins, const S3RViews
   a.T_final = img->T_final;
   a.last = img->last;
   a.kp = kparams(*params);
-  S3R_HIP(launch_raster_fwd(a, as_stream(stream)));
+  const hipStream_t st = as_stream(stream);
+  const int64_t mw = ((img->n + 63) / 64) * 2;
+  if (img->m_raster) {
+    S3R_REQUIRE(img->rec_taken);
+    S3R_REQUIRE(proj->rec_gid);
+    S3R_REQUIRE(proj->rec_view);
+    if (img->n < 0 || img->n >= (int64_t(1) << 31)) return S3R_E_SIZE;
+    a.rec_taken = img->rec_taken;
+    S3R_HIP(launch_zero(img->rec_taken, (size_t)params->cap_surv * 4, img->m_raster,
+                        (size_t)views->n_views * mw * 4, nullptr, 0, nullptr, 0, st));
+  }
+  S3R_HIP(launch_raster_fwd(a, st));
+  if (img->m_raster)
+    S3R_HIP(launch_raster_mask(img->rec_taken, proj->rec_gid, proj->rec_view, proj->counters,
+                               params->cap_surv, mw, img->m_raster, st));
   return S3R_OK;
 }
 

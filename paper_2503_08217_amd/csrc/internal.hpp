@@ -84,6 +84,7 @@ struct RasterArgs {
   float* color;
   float* T_final;
   int32_t* last;
+  int32_t* rec_taken;  // optional: record blended into some pixel (rendering-derived M_t)
   KParams kp;
 };
 
@@ -205,6 +206,9 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st);
 
 // raster.hip
 hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st);
+hipError_t launch_raster_mask(const int32_t* rec_taken, const int32_t* rec_gid,
+                              const int32_t* rec_view, const int32_t* counters, int64_t cap,
+                              int64_t mask_words, uint32_t* m_raster, hipStream_t st);
 hipError_t launch_l1_loss(const float* color, const float* target, const int64_t* px_offset,
                           const int32_t* wh, int nv, int64_t total_px, float* loss,
                           float* d_color, hipStream_t st);

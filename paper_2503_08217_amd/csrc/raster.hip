@@ -47,16 +47,19 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_fwd(RasterArgs a
     cn = a.rec_conic[rn];
     kn = a.rec_rgb[rn];
   }
+  uint32_t rcur = rn;  // record ids of the batch being blended
   rn = (s + kWave + lane < e) ? a.vals[s + kWave + lane] : 0u;
   for (int64_t b0 = s; b0 < e; b0 += kWave) {
     if (ballot(!done) == 0ull) break;
     const float4 g = gn, c = cn, col = kn;
+    const uint32_t rb = rcur;
     const bool valid = b0 + lane < e;
     if (b0 + kWave + lane < e) {
       gn = a.rec_geo[rn];
       cn = a.rec_conic[rn];
       kn = a.rec_rgb[rn];
     }
+    rcur = rn;
     rn = (b0 + 2 * kWave + lane < e) ? a.vals[b0 + 2 * kWave + lane] : 0u;
     const bool near =
         valid && box_hits(cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff), sub_x, sub_y);
@@ -79,6 +82,9 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_fwd(RasterArgs a
       cb = take ? fmaf(kb, w, cb) : cb;
       T = take ? Tn : T;
       last = take ? (int)(b0 - s) + j + 1 : last;
+      // rendering-derived visibility: mark the record (every writer stores 1)
+      if (a.rec_taken && ballot(take) != 0ull && lane == 0)
+        a.rec_taken[__builtin_amdgcn_readlane(rb, j)] = 1;
     }
   }
   if (inside) {
@@ -91,6 +97,33 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_fwd(RasterArgs a
     a.T_final[a.px_offset[v] + p] = T;
     a.last[a.px_offset[v] + p] = last;
   }
+}
+
+// M_raster bits from the records the rasterizer marked (one atomic per record;
+// a (view, Gaussian) pair has at most one record)
+__global__ __launch_bounds__(256) void k_raster_mask(const int32_t* __restrict__ rec_taken,
+                                                     const int32_t* __restrict__ rec_gid,
+                                                     const int32_t* __restrict__ rec_view,
+                                                     const int32_t* __restrict__ counters,
+                                                     int64_t cap, int64_t mask_words,
+                                                     uint32_t* __restrict__ m_raster) {
+  const int64_t n = min((int64_t)counters[S3R_CNT_SURV], cap);
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    if (!rec_taken[r]) continue;
+    const int i = rec_gid[r];
+    atomicOr(m_raster + (size_t)rec_view[r] * mask_words + (i >> 5), 1u << (i & 31));
+  }
+}
+
+hipError_t launch_raster_mask(const int32_t* rec_taken, const int32_t* rec_gid,
+                              const int32_t* rec_view, const int32_t* counters, int64_t cap,
+                              int64_t mask_words, uint32_t* m_raster, hipStream_t st) {
+  const int64_t want = (cap + 255) / 256;
+  const int grid = (int)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+  S3R_LAUNCH(K_RASTER_FWD, k_raster_mask, dim3(grid), dim3(256), 0, st, rec_taken, rec_gid,
+             rec_view, counters, cap, mask_words, m_raster);
+  return hipGetLastError();
 }
 
 hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st) {

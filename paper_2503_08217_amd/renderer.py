@@ -153,6 +153,12 @@ class Renderer:
         self.color = torch.zeros(3 * self.total_px, device=d, dtype=f32)
         self.T_final = torch.zeros(self.total_px, device=d, dtype=f32)
         self.last = torch.zeros(self.total_px, device=d, dtype=i32)
+        # optional rendering-derived visibility (Gaussians blended into a pixel)
+        if self.params.get("raster_mask", False):
+            self.m_raster = torch.zeros(V, self.mask_words, device=d, dtype=i32)
+            self.rec_taken = torch.zeros(max(1, cs), device=d, dtype=i32)
+        else:
+            self.m_raster = self.rec_taken = None
         self.d_color = torch.zeros(3 * self.total_px, device=d, dtype=f32)
         self.loss_v = torch.zeros(max(V, 4), device=d, dtype=f32)
         n_ts = len(self.plain_ts)
@@ -201,7 +207,8 @@ class Renderer:
             _ptr(self.surv), _ptr(self.bstat))
         self.c_bins = A.S3RBins(_ptr(self.tile_count), _ptr(self.tile_start), _ptr(self.vals),
                                 _ptr(self.tile_order))
-        self.c_img = A.S3RImage(_ptr(self.color), _ptr(self.T_final), _ptr(self.last))
+        self.c_img = A.S3RImage(_ptr(self.color), _ptr(self.T_final), _ptr(self.last),
+                                _ptr(self.m_raster), _ptr(self.rec_taken), self.n)
         self.c_grads = A.S3RGrads(
             _ptr(self.g_mean), _ptr(self.g_scale), _ptr(self.g_quat), _ptr(self.g_opacity),
             _ptr(self.g_sh), _ptr(self.g_pose), _ptr(self.g_pose6), _ptr(self.g_mean_w),
@@ -283,11 +290,17 @@ class Renderer:
                                                      len(self.plain_ts), C.byref(self.c_grads),
                                                      _stream()), "s3r_plain_transform_bwd")
 
-    def update_visibility(self, mode, margin=None):
+    def update_visibility(self, mode, margin=None, source=None):
+        """Eqs. (5)-(6).  The UPDATE uses the frustum mask M_t, or with
+        source="raster" the rendering-derived one of the last forward."""
         m = float(self.params.get("margin", 0.1) if margin is None else margin)
+        src = source or self.params.get("visibility_source", "frustum")
+        mask = self.m_raster if src == "raster" else self.mask
+        if mask is None:
+            raise ValueError("rendering-derived visibility needs raster_mask=True")
         A.check(A.load().s3r_update_visibility(
             _ptr(self.life_s), _ptr(self.life_e), _ptr(self.vis_s), _ptr(self.vis_e),
-            _ptr(self.mask), _ptr(self.t_norm), self.V, self.n, int(mode), m, _stream()),
+            _ptr(mask), _ptr(self.t_norm), self.V, self.n, int(mode), m, _stream()),
             "s3r_update_visibility")
 
     # --------------------------------------------------------------- composed

@@ -198,3 +198,29 @@ def test_stochastic_lod_parity():
     rec = records(r)
     for v in range(3):
         check_view(c.scene, views, p, r, rec, v, region=(400, 280, 432, 312))
+
+
+@pytest.mark.parametrize("which", ["config1", "config2"])
+def test_rendering_visibility_parity(which):
+    """The rendering-derived visibility (Gaussians blended into at least one
+    pixel) matches the oracle's for every Gaussian outside the guard band,
+    and is a subset of M_t."""
+    if which == "config1":
+        c = scenes.make_config(1)
+        views, p = c.views, dict(c.params, raster_mask=True)
+    else:
+        c = scenes.make_config(2, scale_n=0.02)
+        views, p = c.views.subset([30]), dict(c.params, raster_mask=True)
+    banner(f"rendering-derived visibility {which}")
+    r = make_renderer(c.scene, views, p)
+    r.forward()
+    m = r.m_raster.cpu().numpy().view(np.uint32)
+    bits = np.unpackbits(m.view(np.uint8).reshape(r.V, -1), axis=1, bitorder="little")
+    gpu = bits[:, : r.n].astype(bool)
+    mt = mask_bits(r)
+    assert not np.any(gpu & ~mt)
+    for v in range(views.n_views):
+        took, unc = render.raster_visible(c.scene, views, v, p)
+        sure = ~unc
+        np.testing.assert_array_equal(gpu[v][sure], took[sure], err_msg=f"view {v}")
+        assert took.sum() > 0

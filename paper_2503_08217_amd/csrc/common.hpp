@@ -157,6 +157,15 @@ __device__ __forceinline__ float clamp_nan(float v, float hi) {
 
 // Rg: the Gaussian's rotation (row-major 3x3), s: its scales, P: camera 3x4
 // (row-major), mean: position in the frame P maps from.
+// camera-space depth of a mean, in the canonical operation order, and the
+// depth test it must pass (the first condition of M_t)
+__device__ __forceinline__ float cam_depth(const float P[12], float mx, float my, float mz) {
+  return ((P[8] * mx + P[9] * my) + P[10] * mz) + P[11];
+}
+__device__ __forceinline__ bool depth_pass(float pz, const KParams& kp) {
+  return (kp.z_near < pz) && (pz < kp.z_far);
+}
+
 __device__ __forceinline__ void project_canonical(const float P[12], float mx, float my, float mz,
                                                   const float Rg[9], float s0, float s1, float s2,
                                                   float fx, float fy, float cx, float cy, int W,
@@ -164,8 +173,8 @@ __device__ __forceinline__ void project_canonical(const float P[12], float mx, f
                                                   int view = 0) {
   o.px = ((P[0] * mx + P[1] * my) + P[2] * mz) + P[3];
   o.py = ((P[4] * mx + P[5] * my) + P[6] * mz) + P[7];
-  o.pz = ((P[8] * mx + P[9] * my) + P[10] * mz) + P[11];
-  o.depth_ok = (kp.z_near < o.pz) && (o.pz < kp.z_far);
+  o.pz = cam_depth(P, mx, my, mz);
+  o.depth_ok = depth_pass(o.pz, kp);
 
   float M[9];
   M[0] = Rg[0] * s0; M[1] = Rg[1] * s1; M[2] = Rg[2] * s2;

@@ -202,11 +202,16 @@ __global__ __launch_bounds__(kProjBlock) void k_cull(ProjArgs a) {
       float P[12], fx, fy, cx, cy;
       int W, H;
       view_geometry(a, v, g, plain, i, e, P, fx, fy, cx, cy, W, H);
-      Proj o;
-      project_canonical(P, e.mx, e.my, e.mz, e.R, e.s0, e.s1, e.s2, fx, fy, cx, cy, W, H, a.kp, o,
-                        i, v);
-      vis = o.visible;
-      surv = vis && o.keep;
+      // a Gaussian behind the camera (or beyond z_far) fails M_t on its depth
+      // alone: skip the covariance, eigenvalue and rectangle (most pairs of a
+      // surround rig; the decision is the same one project_canonical takes)
+      if (depth_pass(cam_depth(P, e.mx, e.my, e.mz), a.kp)) {
+        Proj o;
+        project_canonical(P, e.mx, e.my, e.mz, e.R, e.s0, e.s1, e.s2, fx, fy, cx, cy, W, H, a.kp,
+                          o, i, v);
+        vis = o.visible;
+        surv = vis && o.keep;
+      }
     }
     const uint64_t bt = ballot(pass_t);
     const uint64_t bf = ballot(vis);

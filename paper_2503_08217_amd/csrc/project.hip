@@ -12,8 +12,9 @@
 //   k_off_*          an exclusive scan of the counts (chunk sums, one small
 //                    top scan, chunk rescans) gives the first record of every
 //                    (block, view)
-//   k_records        survivors (only) re-project, query their colour and write
-//                    their record at base + rank within the block
+//   k_records        survivors (only, packed densely over the block's
+//                    threads) re-project, query their colour and write their
+//                    record at base + rank within the block
 // Records come out ordered by Gaussian block, then view, then Gaussian.
 #include "internal.hpp"
 
@@ -358,42 +359,71 @@ __global__ __launch_bounds__(kOffThreads) void k_off_down(int32_t* __restrict__ 
 }
 
 // Phase C: records of the survivors, at the slots given by the block offsets.
-__global__ __launch_bounds__(kProjBlock) void k_records(ProjArgs a) {
-  const int tid = threadIdx.x;
-  const int wave = tid / kWave;
-  const int lane = tid % kWave;
-  const int vb = blockIdx.x;
-  const int i = vb * kProjBlock + tid;
-  const bool plain = (a.kp.flags & S3R_PLAIN) != 0;
-  // survivor words of this block's waves, all views
-  uint64_t any = 0;
-  for (int v = 0; v < a.nv; ++v) {
-    const int gw = vb * kProjWaves + wave;
-    if ((int64_t)gw * kWave < a.n) {
-      const uint32_t* sb = a.surv + (size_t)v * a.mask_words + 2 * (size_t)gw;
-      any |= (((uint64_t)sb[1] << 32) | sb[0]);
+// Position of the k-th (0-based) set bit of x (k < popcount(x)).
+__device__ __forceinline__ int select_bit(uint64_t x, int k) {
+  int pos = 0;
+#pragma unroll
+  for (int sft = 32; sft >= 1; sft >>= 1) {
+    const uint64_t lo = x & ((1ull << sft) - 1ull);
+    const int c = __popcll(lo);
+    if (k >= c) {
+      k -= c;
+      x >>= sft;
+      pos += sft;
+    } else {
+      x = lo;
     }
   }
-  if (!((any >> lane) & 1ull)) return;
-  Loaded g;
-  load_gaussian(a, i, true, plain, g);
-  const int B = (a.sh_deg + 1) * (a.sh_deg + 1);
-  for (int v = 0; v < a.nv; ++v) {
-    const int4 info = reinterpret_cast<const int4*>(a.bstat)[(size_t)vb * a.nv + v];
-    // survivors of this view in earlier waves of the block, and in this wave
-    int before = 0;
-    uint64_t mine = 0;
-    for (int w = 0; w <= wave; ++w) {
-      const int gw = vb * kProjWaves + w;
-      if ((int64_t)gw * kWave >= a.n) break;
+  return pos;
+}
+
+// The block's survivors of all views are processed densely: survivor k of
+// view v (in Gaussian order) is item prefix[v] + k of the block, and thread
+// t takes items t, t + 256, ...  (lanes are not tied to Gaussians: in a
+// batch of many views only a few per cent of the (Gaussian, view) pairs of a
+// block survive).
+__global__ __launch_bounds__(kProjBlock) void k_records(ProjArgs a) {
+  __shared__ uint64_t s_w[kMaxViews][kProjWaves];
+  __shared__ int s_pre[kMaxViews + 1];
+  const int tid = threadIdx.x;
+  const int vb = blockIdx.x;
+  const bool plain = (a.kp.flags & S3R_PLAIN) != 0;
+  for (int q = tid; q < a.nv * kProjWaves; q += kProjBlock) {
+    const int v = q / kProjWaves, w = q % kProjWaves;
+    const int gw = vb * kProjWaves + w;
+    uint64_t word = 0;
+    if ((int64_t)gw * kWave < a.n) {
       const uint32_t* sb = a.surv + (size_t)v * a.mask_words + 2 * (size_t)gw;
-      const uint64_t word = ((uint64_t)sb[1] << 32) | sb[0];
-      if (w < wave) before += __popcll(word);
-      else mine = word;
+      word = ((uint64_t)sb[1] << 32) | sb[0];
     }
-    if (!((mine >> lane) & 1ull)) continue;
-    const int64_t slot = (int64_t)info.w + before + lane_rank(mine);
+    s_w[v][w] = word;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int v = 0; v < a.nv; ++v) {
+      s_pre[v] = run;
+      for (int w = 0; w < kProjWaves; ++w) run += __popcll(s_w[v][w]);
+    }
+    s_pre[a.nv] = run;
+  }
+  __syncthreads();
+  const int total = s_pre[a.nv];
+  const int B = (a.sh_deg + 1) * (a.sh_deg + 1);
+  for (int item = tid; item < total; item += kProjBlock) {
+    int v = 0;
+    while (s_pre[v + 1] <= item) ++v;
+    int k = item - s_pre[v];
+    const int64_t slot = (int64_t)a.bstat[((size_t)vb * a.nv + v) * 4 + 3] + k;
+    int w = 0;
+    while (k >= __popcll(s_w[v][w])) {
+      k -= __popcll(s_w[v][w]);
+      ++w;
+    }
+    const int i = vb * kProjBlock + w * kWave + select_bit(s_w[v][w], k);
     if (slot >= a.kp.cap_surv) continue;
+    Loaded g;
+    load_gaussian(a, i, true, plain, g);
     Loaded e;
     float P[12], fx, fy, cx, cy;
     int W, H;

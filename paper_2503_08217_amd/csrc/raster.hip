@@ -154,6 +154,10 @@ hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st) {
 // changes rarely; per-thread sums are reduced over the wave when its lanes
 // share a view, then per workgroup, and a workgroup adds one value per view it
 // touched to the loss (few same-address atomics: they serialise).
+__device__ __forceinline__ float l1_sign(float d, float inv) {
+  return d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+}
+
 __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ color,
                                             const float* __restrict__ target,
                                             const int64_t* __restrict__ pxo,
@@ -162,7 +166,12 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ color,
                                             float* __restrict__ dcol) {
   __shared__ float s_loss[kMaxViews];
   for (int v = threadIdx.x; v < nv; v += blockDim.x) s_loss[v] = 0.f;
+  // with every view's pixel count a multiple of 4, planes and view offsets
+  // are 16-byte aligned and a thread takes 4 pixels with float4 accesses
+  bool vec = true;
+  for (int v = 0; v < nv; ++v) vec = vec && (((int64_t)wh[2 * v] * wh[2 * v + 1]) % 4 == 0);
   __syncthreads();
+  const int step = vec ? 4 : 1;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = min(total, lo + chunk);
   int cur = 0;
@@ -172,7 +181,7 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ color,
   int64_t vb = pxo[cur];
   float inv = 1.0f / (3.0f * (float)npx);
   float acc = 0.f;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+  for (int64_t i = lo + (int64_t)threadIdx.x * step; i < hi; i += (int64_t)blockDim.x * step) {
     if (i >= vend) {
       atomicAdd(&s_loss[cur], acc);
       acc = 0.f;
@@ -184,12 +193,25 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ color,
     }
     const int64_t loc = i - vb;
     float a = 0.f;
+    if (vec) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int64_t q = 3 * vb + c * npx + loc;
-      const float d = color[q] - target[q];
-      a += fabsf(d);
-      dcol[q] = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+      for (int c = 0; c < 3; ++c) {
+        const int64_t q = (3 * vb + c * npx + loc) / 4;
+        const float4 x = reinterpret_cast<const float4*>(color)[q];
+        const float4 t = reinterpret_cast<const float4*>(target)[q];
+        const float4 d = make_float4(x.x - t.x, x.y - t.y, x.z - t.z, x.w - t.w);
+        a += (fabsf(d.x) + fabsf(d.y)) + (fabsf(d.z) + fabsf(d.w));
+        reinterpret_cast<float4*>(dcol)[q] =
+            make_float4(l1_sign(d.x, inv), l1_sign(d.y, inv), l1_sign(d.z, inv), l1_sign(d.w, inv));
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int64_t q = 3 * vb + c * npx + loc;
+        const float d = color[q] - target[q];
+        a += fabsf(d);
+        dcol[q] = l1_sign(d, inv);
+      }
     }
     acc += a * inv;
   }
@@ -211,8 +233,9 @@ hipError_t launch_l1_loss(const float* color, const float* target, const int64_t
   hipError_t e = launch_zero(loss, (size_t)nv * 4, nullptr, 0, nullptr, 0, nullptr, 0, st);
   if (e != hipSuccess) return e;
   if (total_px <= 0) return hipGetLastError();
-  // about 512 workgroups of 256 threads, each over a contiguous range
-  const int64_t chunk = max((int64_t)256 * 8, ((total_px + 511) / 512 + 255) / 256 * 256);
+  // about 512 workgroups of 256 threads, each over a contiguous range (a
+  // multiple of 1024 pixels, so 4-pixel groups never straddle chunks)
+  const int64_t chunk = max((int64_t)256 * 8, ((total_px + 511) / 512 + 1023) / 1024 * 1024);
   const int64_t grid = (total_px + chunk - 1) / chunk;
   S3R_LAUNCH(K_L1, k_l1, dim3((unsigned)grid), dim3(256), 0, st, color, target, px_offset, wh, nv,
              total_px, chunk, loss, d_color);

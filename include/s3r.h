@@ -187,6 +187,12 @@ typedef struct S3RBins {
   uint32_t* vals;      /* [cap_dup] record index of each list entry, sorted  */
   int32_t* tile_order; /* [total_tiles] tiles by descending list length (the
                           rasterizer's launch order; ties in tile order)      */
+  int32_t* rec_pair;   /* [cap_surv] index of each record's first (record,
+                          tile) pair in emission order: a record emits the
+                          tiles of its rectangle row by row, so the pair of
+                          record r and tile (tx, ty) is rec_pair[r] +
+                          (ty - y0) (x1 - x0) + (tx - x0); read back by the
+                          backward to give each pair its own gradient slot */
 } S3RBins;
 
 typedef struct S3RImage {

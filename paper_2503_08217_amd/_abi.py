@@ -53,7 +53,8 @@ class S3RProjected(C.Structure):
 
 
 class S3RBins(C.Structure):
-    _fields_ = [("tile_count", P), ("tile_start", P), ("vals", P), ("tile_order", P)]
+    _fields_ = [("tile_count", P), ("tile_start", P), ("vals", P), ("tile_order", P),
+                ("rec_pair", P)]
 
 
 class S3RImage(C.Structure):

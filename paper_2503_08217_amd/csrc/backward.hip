@@ -28,8 +28,19 @@ namespace s3r {
 // ---------------------------------------------------------------------------
 // raster backward
 // ---------------------------------------------------------------------------
+// slot of the (record r, tile (tx, ty)) pair in emission order: a record's
+// pairs are the tiles of its rectangle row by row from rec_pair[r]
+__device__ __forceinline__ int64_t pair_slot(const int32_t* __restrict__ rec_pair,
+                                             const int4* __restrict__ rec_rect, uint32_t r, int tx,
+                                             int ty) {
+  const int4 rc = rec_rect[r];
+  return (int64_t)rec_pair[r] + (int64_t)(ty - rc.y) * (rc.z - rc.x) + (tx - rc.x);
+}
+
 template <int TS>
-__global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
+// (64 VGPRs: eight waves per SIMD)
+__global__ __launch_bounds__(RasterShape<TS>::NT)
+__attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
   constexpr int NT = RasterShape<TS>::NT, NW = RasterShape<TS>::NW;
   constexpr int WIN = RasterShape<TS>::WIN;
   // per list entry of the window [w0, w0 + WIN), summed over the tile's waves:
@@ -45,7 +56,8 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
   const int gx = (W + TS - 1) / TS;
   int ox, oy, sx, sy;
   raster_pixel<TS>(tid, ox, oy, sx, sy);
-  const int tx0 = (lt % gx) * TS, ty0 = (lt / gx) * TS;
+  const int tcx = lt % gx, tcy = lt / gx;
+  const int tx0 = tcx * TS, ty0 = tcy * TS;
   const int px = tx0 + ox, py = ty0 + oy;
   const float fxp = (float)px, fyp = (float)py;
   const float sub_x = (float)(tx0 + sx), sub_y = (float)(ty0 + sy);
@@ -165,6 +177,9 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
       }
     }
     __syncthreads();
+    // each entry of the window writes its record's nine sums for this tile
+    // into the pair's own slot (zeros where nothing blended): no two tiles
+    // share a slot, so no atomics reach global memory here
     for (int k = tid; k < (int)(w_end - w0); k += NT) {
       float* G = s_g[k];
       float gv[9];
@@ -175,23 +190,133 @@ __global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_bwd(BwdArgs a) {
         any |= (gv[q] != 0.f);
         G[q] = 0.f;
       }
+      const uint32_t r = a.vals[w0 + k];
+      float4 o0 = zero4, o1 = zero4, o2 = zero4;
       if (any) {
-        const uint32_t r = a.vals[w0 + k];
         const float4 c = a.rec_conic[r];
         // moments -> d(u, v, A, B, C): -(A mx + B my), -(B mx + C my),
-        // -mxx / 2, -mxy, -myy / 2
-        const float g5[5] = {-(c.x * gv[0] + c.y * gv[1]), -(c.y * gv[0] + c.z * gv[1]),
-                             -0.5f * gv[2], -gv[3], -0.5f * gv[4]};
-        float* D = reinterpret_cast<float*>(a.g2d + 3 * (size_t)r);
-#pragma unroll
-        for (int q = 0; q < 5; ++q)
-          if (g5[q] != 0.f) atomicAdd(D + q, g5[q]);
-#pragma unroll
-        for (int q = 5; q < 9; ++q)
-          if (gv[q] != 0.f) atomicAdd(D + q, gv[q]);
+        // -mxx / 2, -mxy, -myy / 2; then d opacity and d rgb
+        o0 = make_float4(-(c.x * gv[0] + c.y * gv[1]), -(c.y * gv[0] + c.z * gv[1]), -0.5f * gv[2],
+                         -gv[3]);
+        o1 = make_float4(-0.5f * gv[4], gv[5], gv[6], gv[7]);
+        o2 = make_float4(gv[8], 0.f, 0.f, 0.f);
       }
+      float4* P = a.part + 3 * pair_slot(a.rec_pair, a.rec_rect, r, tcx, tcy);
+      P[0] = o0;
+      P[1] = o1;
+      P[2] = o2;
     }
     __syncthreads();
+  }
+  // the first entry not replayed: it and every later entry of the list (later
+  // in (depth, record) order) keep no slot and read as zero gradients
+  if (tid == 0) {
+    int2 cut = make_int2(-1, 0);
+    if (tile_end < e) {
+      const uint32_t r = a.vals[tile_end];
+      cut = make_int2((int)r, (int)__float_as_uint(a.rec_geo[r].w));
+    }
+    a.tile_cut[t] = cut;
+  }
+}
+
+// Sum of the per-pair gradients of each record (pairs are contiguous per
+// record in emission order).  A pair counts only if its tile's backward
+// replayed it, i.e. if it precedes the tile's cut in the list order (depth
+// bits, then record index: the order of the stable sort).  A thread adds a run
+// of kPairRun pairs; a record wholly inside one run is stored directly, a
+// record crossing runs is summed in an LDS slot of the workgroup (the slot of
+// the run holding its first pair in this workgroup, or the carry-in slot for a
+// record begun in an earlier workgroup) and added to global memory with one
+// atomic per component and workgroup.  g2d must be zero beforehand for
+// records that cross runs.
+constexpr int kPairThreads = 256;
+constexpr int kPairRun = 8;
+
+__global__ __launch_bounds__(kPairThreads) void k_pair_reduce(BwdArgs a) {
+  constexpr int NS = kPairThreads + 1;  // slot kPairThreads: carry-in
+  __shared__ float s_acc[NS][9];
+  __shared__ int s_rec[NS];
+  const int nrec = a.counters[S3R_CNT_SURV];
+  const int64_t ndup = a.counters[S3R_CNT_DUP];
+  const int64_t P0 = (int64_t)blockIdx.x * kPairThreads * kPairRun;
+  if (P0 >= ndup || nrec <= 0) return;  // uniform over the workgroup
+  const int tid = threadIdx.x;
+  for (int k = tid; k < NS * 9; k += kPairThreads) (&s_acc[0][0])[k] = 0.f;
+  for (int k = tid; k < NS; k += kPairThreads) s_rec[k] = -1;
+  __syncthreads();
+  const int64_t p0 = P0 + (int64_t)tid * kPairRun;
+  const int64_t p1 = min(ndup, p0 + kPairRun);
+  if (p0 < p1) {
+    // last record whose first pair is at or before p0
+    int lo = 0, hi = nrec - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.rec_pair[mid] <= p0) lo = mid;
+      else hi = mid - 1;
+    }
+    int r = lo - 1;
+    int64_t first = 0, next = a.rec_pair[lo];
+    int4 rc = make_int4(0, 0, 1, 1);
+    int tx = 0, ty = 0, gx = 1, tbase = 0;
+    uint32_t db = 0u;
+    float acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = 0.f;
+    for (int64_t p = p0; p < p1; ++p) {
+      if (p >= next) {
+        // the record holding pair p (records without pairs are skipped)
+        do {
+          ++r;
+          first = next;
+          next = (r + 1 < nrec) ? (int64_t)a.rec_pair[r + 1] : INT64_MAX;
+        } while (p >= next);
+        rc = a.rec_rect[r];
+        const int v = a.rec_view[r];
+        db = __float_as_uint(a.rec_geo[r].w);
+        gx = (a.wh[2 * v] + a.kp.tile - 1) / a.kp.tile;
+        tbase = a.tile_offset[v];
+        const int j = (int)(p - first), w = rc.z - rc.x;
+        tx = rc.x + j % w;
+        ty = rc.y + j / w;
+      }
+      const int2 cut = a.tile_cut[tbase + ty * gx + tx];
+      const uint32_t dc = (uint32_t)cut.y;
+      if (cut.x < 0 || db < dc || (db == dc && r < cut.x)) {
+        const float4 x0 = a.part[3 * p], x1 = a.part[3 * p + 1], x2 = a.part[3 * p + 2];
+        acc[0] += x0.x; acc[1] += x0.y; acc[2] += x0.z; acc[3] += x0.w;
+        acc[4] += x1.x; acc[5] += x1.y; acc[6] += x1.z; acc[7] += x1.w;
+        acc[8] += x2.x;
+      }
+      if (++tx == rc.z) {
+        tx = rc.x;
+        ++ty;
+      }
+      if (p + 1 < p1 && p + 1 < next) continue;
+      // the segment of record r in this run ends at p
+      if (first >= p0 && next <= p1) {
+        a.g2d[3 * (size_t)r] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        a.g2d[3 * (size_t)r + 1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+        a.g2d[3 * (size_t)r + 2] = make_float4(acc[8], 0.f, 0.f, 0.f);
+      } else {
+        const int slot = first < P0 ? kPairThreads : (int)((first - P0) / kPairRun);
+        if (slot == tid || (slot == kPairThreads && p0 == P0)) s_rec[slot] = r;
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+          if (acc[q] != 0.f) atomicAdd(&s_acc[slot][q], acc[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) acc[q] = 0.f;
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < NS; k += kPairThreads) {
+    const int r = s_rec[k];
+    if (r < 0) continue;
+    float* D = reinterpret_cast<float*>(a.g2d + 3 * (size_t)r);
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      if (s_acc[k][q] != 0.f) atomicAdd(D + q, s_acc[k][q]);
   }
 }
 
@@ -747,6 +872,12 @@ hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st) {
       break;
     default:
       return hipErrorInvalidValue;
+  }
+  {
+    const int64_t per = (int64_t)kPairThreads * kPairRun;
+    const int64_t nb = (a.kp.cap_dup + per - 1) / per;
+    S3R_LAUNCH(K_PAIR_REDUCE, k_pair_reduce, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kPairThreads),
+               0, st, a);
   }
   return hipGetLastError();
 }

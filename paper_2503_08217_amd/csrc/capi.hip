@@ -32,7 +32,6 @@ struct WsSort {
   uint64_t* keys;
   uint64_t* keys_alt;
   uint32_t* vals;
-  int32_t* pair_off;
   int32_t* hist;
   int32_t* sums;
   int32_t* misc;
@@ -40,6 +39,8 @@ struct WsSort {
 };
 struct WsBwd {
   float4* g2d;
+  float4* part;
+  int2* tile_cut;
   float* d_cam;
 };
 
@@ -61,8 +62,6 @@ size_t ws_sort(const S3RSizes& z, WsSort* w, char* base) {
   off += align_up((size_t)z.cap_dup * 8);
   if (w) w->vals = reinterpret_cast<uint32_t*>(base + off);
   off += align_up((size_t)z.cap_dup * 4);
-  if (w) w->pair_off = reinterpret_cast<int32_t*>(base + off);
-  off += align_up((size_t)z.cap_surv * 4 + 4);
   const size_t hw = sort_hist_words(z.cap_dup);
   if (w) w->hist = reinterpret_cast<int32_t*>(base + off);
   off += align_up(hw * 4 + 4);
@@ -80,6 +79,10 @@ size_t ws_bwd(const S3RSizes& z, WsBwd* w, char* base) {
   size_t off = 0;
   if (w) w->g2d = reinterpret_cast<float4*>(base + off);
   off += align_up((size_t)z.cap_surv * 48);
+  if (w) w->part = reinterpret_cast<float4*>(base + off);
+  off += align_up((size_t)z.cap_dup * 48);
+  if (w) w->tile_cut = reinterpret_cast<int2*>(base + off);
+  off += align_up((size_t)z.total_tiles * 8 + 8);
   if (w) w->d_cam = reinterpret_cast<float*>(base + off);
   off += align_up((size_t)z.n_views * z.n_slots * 48 + 16);
   return off;
@@ -302,6 +305,7 @@ int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* vi
   S3R_REQUIRE(bins->tile_start);
   S3R_REQUIRE(bins->tile_order);
   S3R_REQUIRE(bins->vals);
+  S3R_REQUIRE(bins->rec_pair);
   const S3RSizes z = sizes_of(nullptr, views, params);
   if (!ws || ws_bytes < ws_sort(z, nullptr, nullptr)) return S3R_E_WORKSPACE;
   if (!aligned16(ws)) return S3R_E_ALIGN;
@@ -322,7 +326,7 @@ int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* vi
   a.tile_count = bins->tile_count;
   a.tile_start = bins->tile_start;
   a.tile_order = bins->tile_order;
-  a.pair_off = w.pair_off;
+  a.pair_off = bins->rec_pair;
   a.keys = w.keys;
   a.keys_alt = w.keys_alt;
   // the last radix pass must write the caller's value array
@@ -424,12 +428,14 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   S3R_REQUIRE(proj->rec_geo);
   S3R_REQUIRE(proj->rec_conic);
   S3R_REQUIRE(proj->rec_rgb);
+  S3R_REQUIRE(proj->rec_rect);
   S3R_REQUIRE(proj->counters);
   S3R_REQUIRE(proj->surv);
   S3R_REQUIRE(proj->bstat);
   S3R_REQUIRE(bins->tile_start);
   S3R_REQUIRE(bins->tile_order);
   S3R_REQUIRE(bins->vals);
+  S3R_REQUIRE(bins->rec_pair);
   S3R_REQUIRE(g->scale);
   S3R_REQUIRE(g->opacity);
   S3R_REQUIRE(g->sh);
@@ -490,6 +496,10 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   b.d_color = d_color;
   b.nv = views->n_views;
   b.total_tiles = views->total_tiles;
+  b.rec_pair = bins->rec_pair;
+  b.rec_rect = reinterpret_cast<const int4*>(proj->rec_rect);
+  b.part = w.part;
+  b.tile_cut = w.tile_cut;
   b.g2d = w.g2d;
   b.kp = kp;
   S3R_HIP(launch_raster_bwd(b, st));

@@ -9,8 +9,8 @@ namespace s3r {
 // kernels timed by the opt-in profiler (names in profile.hip)
 enum KernelId {
   K_COMPOSE, K_PLAIN_TRANSFORM, K_PROJECT, K_STATS, K_RECORDS, K_SCAN, K_EMIT, K_RADIX,
-  K_TILE_RANGES, K_TILE_ORDER, K_RASTER_FWD, K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PROJECT_BWD,
-  K_POSE_BWD, K_POSE6, K_PLAIN_TRANSFORM_BWD, K_VISIBILITY, K_ZERO, K_COUNT
+  K_TILE_RANGES, K_TILE_ORDER, K_RASTER_FWD, K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PAIR_REDUCE,
+  K_PROJECT_BWD, K_POSE_BWD, K_POSE6, K_PLAIN_TRANSFORM_BWD, K_VISIBILITY, K_ZERO, K_COUNT
 };
 void prof_begin(int id, hipStream_t st);
 void prof_end(int id, hipStream_t st);
@@ -106,7 +106,16 @@ struct BwdArgs {
   const int32_t* last;
   const float* d_color;
   int nv, total_tiles;
-  // per-record 2D gradients (workspace), 12 floats each
+  // first pair of each record in emission order and the records' tile
+  // rectangles: the slot of a (record, tile) pair in `part`
+  const int32_t* rec_pair;
+  const int4* rec_rect;
+  // per-pair 2D gradients (workspace, [cap_dup][12] floats), summed per
+  // record into g2d ([cap_surv][12] floats)
+  float4* part;
+  // per tile: the first list entry the backward did not replay (record,
+  // depth bits), or record -1 when it replayed the whole list (workspace)
+  int2* tile_cut;
   float4* g2d;
   KParams kp;
 };
@@ -188,7 +197,7 @@ struct SortArgs {
   int32_t* tile_start;
   int32_t* tile_order;
   // workspace
-  int32_t* pair_off;   // [cap_surv]
+  int32_t* pair_off;   // [cap_surv] first pair of each record (output)
   uint64_t* keys;      // [cap_dup]
   uint64_t* keys_alt;  // [cap_dup]
   uint32_t* vals0;     // [cap_dup]: emitted values; vals1 receives the last pass

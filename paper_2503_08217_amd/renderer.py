@@ -150,6 +150,7 @@ class Renderer:
         self.tile_start = torch.zeros(self.total_tiles + 1, device=d, dtype=i32)
         self.tile_order = torch.zeros(max(1, self.total_tiles), device=d, dtype=i32)
         self.vals = torch.zeros(cd, device=d, dtype=i32)
+        self.rec_pair = torch.zeros(cs + 1, device=d, dtype=i32)
         self.color = torch.zeros(3 * self.total_px, device=d, dtype=f32)
         self.T_final = torch.zeros(self.total_px, device=d, dtype=f32)
         self.last = torch.zeros(self.total_px, device=d, dtype=i32)
@@ -206,7 +207,7 @@ class Renderer:
             _ptr(self.rec_rect), _ptr(self.counters), _ptr(self.stats), _ptr(self.rec_npairs),
             _ptr(self.surv), _ptr(self.bstat))
         self.c_bins = A.S3RBins(_ptr(self.tile_count), _ptr(self.tile_start), _ptr(self.vals),
-                                _ptr(self.tile_order))
+                                _ptr(self.tile_order), _ptr(self.rec_pair))
         self.c_img = A.S3RImage(_ptr(self.color), _ptr(self.T_final), _ptr(self.last),
                                 _ptr(self.m_raster), _ptr(self.rec_taken), self.n)
         self.c_grads = A.S3RGrads(

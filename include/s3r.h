@@ -82,9 +82,16 @@ enum {
   S3R_LOD_STOCHASTIC = 8, /* Eq. (7): drop a sub-threshold Gaussian with
                        probability p = p_max + (p_max - 0.01) min(0, (d - D)/D)
                        instead of always (needs S3R_LOD)                   */
-  S3R_GRAD_SPARSE = 16 /* s3r_raster_bwd clears only the gradient rows it
+  S3R_GRAD_SPARSE = 16, /* s3r_raster_bwd clears only the gradient rows it
                        wrote on the previous call (S3RGrads.rows) instead of
                        the whole arrays; streamlined route only            */
+  S3R_SORT_TILES = 32  /* s3r_sort partitions the pairs by tile (radix passes
+                       over the tile bits only) and orders each list by depth
+                       in LDS: fastest when lists are short (a few thousand
+                       entries, as with the LOD cull); lists of 16384 entries
+                       or more take a slow one-workgroup path.  Without the
+                       flag a radix sort over all key bits orders every list,
+                       whatever its length.  Both give the same order.      */
 };
 
 /* modes of s3r_update_visibility */

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libs3r.so")
 
 S3R_OK = 0
 S3R_TEMPORAL, S3R_LOD, S3R_PLAIN, S3R_LOD_STOCHASTIC, S3R_GRAD_SPARSE = 1, 2, 4, 8, 16
+S3R_SORT_TILES = 32
 S3R_VIS_UPDATE, S3R_VIS_FOLD, S3R_VIS_RESET = 0, 1, 2
 S3R_WS_PROJECT, S3R_WS_SORT, S3R_WS_BACKWARD = 0, 1, 2
 CNT_SURV, CNT_OVF_SURV, CNT_DUP, CNT_OVF_DUP, CNT_SPIN = 0, 1, 2, 3, 4

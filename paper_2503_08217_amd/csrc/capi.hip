@@ -32,6 +32,7 @@ struct WsSort {
   uint64_t* keys;
   uint64_t* keys_alt;
   uint32_t* vals;
+  uint32_t* vals_alt;
   int32_t* hist;
   int32_t* sums;
   int32_t* misc;
@@ -61,6 +62,8 @@ size_t ws_sort(const S3RSizes& z, WsSort* w, char* base) {
   if (w) w->keys_alt = reinterpret_cast<uint64_t*>(base + off);
   off += align_up((size_t)z.cap_dup * 8);
   if (w) w->vals = reinterpret_cast<uint32_t*>(base + off);
+  off += align_up((size_t)z.cap_dup * 4);
+  if (w) w->vals_alt = reinterpret_cast<uint32_t*>(base + off);
   off += align_up((size_t)z.cap_dup * 4);
   const size_t hw = sort_hist_words(z.cap_dup);
   if (w) w->hist = reinterpret_cast<int32_t*>(base + off);
@@ -319,6 +322,7 @@ int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* vi
   a.nv = views->n_views;
   a.total_tiles = views->total_tiles;
   a.tile = params->tile;
+  a.by_tile = (params->flags & S3R_SORT_TILES) != 0;
   a.tile_offset = views->tile_offset;
   a.wh = views->wh;
   a.counters = proj->counters;
@@ -329,10 +333,9 @@ int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* vi
   a.pair_off = bins->rec_pair;
   a.keys = w.keys;
   a.keys_alt = w.keys_alt;
-  // the last radix pass must write the caller's value array
-  const bool odd = (radix_passes(views->total_tiles) & 1) != 0;
-  a.vals0 = odd ? w.vals : bins->vals;
-  a.vals1 = odd ? bins->vals : w.vals;
+  a.vals0 = w.vals;
+  a.vals1 = w.vals_alt;
+  a.vals_out = bins->vals;
   a.hist = w.hist;
   a.scan_sums = w.sums;
   a.misc = w.misc;

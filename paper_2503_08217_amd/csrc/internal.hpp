@@ -9,7 +9,8 @@ namespace s3r {
 // kernels timed by the opt-in profiler (names in profile.hip)
 enum KernelId {
   K_COMPOSE, K_PLAIN_TRANSFORM, K_PROJECT, K_STATS, K_RECORDS, K_SCAN, K_EMIT, K_RADIX,
-  K_TILE_RANGES, K_TILE_ORDER, K_RASTER_FWD, K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PAIR_REDUCE,
+  K_TILE_RANGES, K_TILE_ORDER, K_TILE_SORT, K_TILE_SORT_LARGE,
+  K_TILE_SORT_HUGE, K_RASTER_FWD, K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PAIR_REDUCE,
   K_PROJECT_BWD, K_POSE_BWD, K_POSE6, K_PLAIN_TRANSFORM_BWD, K_VISIBILITY, K_ZERO, K_COUNT
 };
 void prof_begin(int id, hipStream_t st);
@@ -189,6 +190,7 @@ struct SortArgs {
   const int32_t* rec_view;
   const int32_t* rec_npairs;
   int nv, total_tiles, tile;
+  bool by_tile;  // S3R_SORT_TILES: tile partition + per-list depth sort
   const int32_t* tile_offset;
   const int32_t* wh;
   int32_t* counters;
@@ -200,15 +202,16 @@ struct SortArgs {
   int32_t* pair_off;   // [cap_surv] first pair of each record (output)
   uint64_t* keys;      // [cap_dup]
   uint64_t* keys_alt;  // [cap_dup]
-  uint32_t* vals0;     // [cap_dup]: emitted values; vals1 receives the last pass
-  uint32_t* vals1;
+  uint32_t* vals0;     // [cap_dup]: emitted values
+  uint32_t* vals1;     // [cap_dup]: the other buffer of the partition passes
+  uint32_t* vals_out;  // [cap_dup]: the sorted lists (S3RBins.vals)
   int32_t* hist;       // [256 * scan_blocks(cap_dup)]
   int32_t* scan_sums;
   int32_t* misc;       // [0] total pairs, [1] histogram total
   int32_t* order_cnt;  // [order_count_words] per (bucket, chunk) tile counts
   int64_t cap_dup, cap_surv;
 };
-int radix_passes(int total_tiles);
+int sort_passes(int total_tiles, bool by_tile);
 size_t sort_hist_words(int64_t cap_dup);
 size_t order_count_words(int total_tiles);
 hipError_t launch_sort(const SortArgs& a, hipStream_t st);

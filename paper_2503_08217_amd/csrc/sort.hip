@@ -2,18 +2,23 @@
 //
 // A list entry is a (tile, record) pair; its key is (global tile << 32 |
 // depth bits) and its value the record index.  Pairs are emitted in record
-// order (records of a view are in Gaussian order), so a stable sort on the
-// key orders every tile's list by (depth bits, Gaussian index) -- the order
-// the oracle defines -- bit for bit.
+// order (records of a view are in Gaussian order), so ordering every tile's
+// list by (depth bits, emission position) gives the order the oracle defines
+// -- (depth, Gaussian index) -- bit for bit.
 //
 //   1. exclusive scan of the pairs per record (reduce-then-scan)
 //   2. k_emit_pairs: every thread writes a run of consecutive pairs (records
 //      covering thousands of tiles are spread over many threads)
-//   3. least-significant-digit radix sort on the 32 depth bits and the tile
-//      bits, 8 bits per pass: block histograms -> scan of the digit-major
-//      histogram matrix -> stable scatter, where each wave ranks its keys by
-//      matching digits with eight ballots
-//   4. tile ranges by binary search of the sorted keys
+//   3. least-significant-digit radix passes, 8 bits each: block histograms ->
+//      scan of the digit-major histogram matrix -> stable scatter, where each
+//      wave ranks its keys by matching digits with eight ballots.  The passes
+//      cover all key bits, or with S3R_SORT_TILES only the tile bits (a stable
+//      partition that leaves every list in emission order).
+//   4. tile ranges by binary search of the sorted keys; the tiles' launch
+//      order (descending list length)
+//   5. with S3R_SORT_TILES, k_tile_sort_*: each list sorted by (depth bits,
+//      position) with a bitonic network in LDS, one workgroup per list (lists
+//      too long for LDS are sorted in place in global memory by one workgroup)
 // No kernel waits on another workgroup and none uses a contended atomic.
 #include "internal.hpp"
 
@@ -418,10 +423,149 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_place(const int32_t* __
   }
 }
 
-int radix_passes(int total_tiles) {
+// ---------------------------------------------------------------------------
+// per-tile depth order
+// ---------------------------------------------------------------------------
+// A list of n entries is sorted on the composite key (depth bits << 32 |
+// position in the list), which orders equal depths by emission position as a
+// stable sort would.  The network is the bitonic sorter written so that every
+// merge compares an element with its mirror image in the first step and with
+// the element j places on in the later steps; all comparators put the smaller
+// key at the lower index, so keys padded at the end with the largest value
+// never move and lengths need not be powers of two.
+// Size classes follow the binary-logarithm buckets of the launch order, so
+// that each class above the smallest is a prefix of that order.
+constexpr int kTsSmall = 2048;    // lists shorter than this: 256 threads, 16 KB LDS
+constexpr int kTsLarge = 16384;   // shorter than this: 1024 threads, 128 KB LDS
+constexpr int kTsLargeBlocks = 256;
+
+__device__ __forceinline__ int next_pow2(int n) {
+  int m = 1;
+  while (m < n) m <<= 1;
+  return m;
+}
+
+// lower element of comparator q at distance j (a zero bit inserted at log2 j)
+__device__ __forceinline__ int cmp_lower(int q, int j) { return ((q & ~(j - 1)) << 1) | (q & (j - 1)); }
+
+template <int NTH>
+__device__ void bitonic_lds(uint64_t* s, int m) {
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int q = threadIdx.x; q < (m >> 1); q += NTH) {
+        const int i = cmp_lower(q, j);
+        const int pr = (j == (k >> 1)) ? (i ^ (k - 1)) : (i + j);
+        const uint64_t x = s[i], y = s[pr];
+        if (y < x) {
+          s[i] = y;
+          s[pr] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int NTH, int CAP>
+__device__ void sort_list_lds(uint64_t* s, const uint64_t* __restrict__ keys,
+                              const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout,
+                              int64_t s0, int n) {
+  const int m = next_pow2(n);
+  for (int i = threadIdx.x; i < m; i += NTH)
+    s[i] = i < n ? (((uint64_t)(uint32_t)keys[s0 + i] << 32) | (uint32_t)i) : ~0ull;
+  __syncthreads();
+  bitonic_lds<NTH>(s, m);
+  for (int i = threadIdx.x; i < n; i += NTH) vout[s0 + i] = vin[s0 + (uint32_t)s[i]];
+  __syncthreads();
+}
+
+__device__ __forceinline__ void list_of(const int32_t* start, const int32_t* order, int i,
+                                        int64_t cap, int64_t& s0, int& n) {
+  const int t = order[i];
+  s0 = start[t];
+  n = (int)(min((int64_t)start[t + 1], cap) - s0);
+}
+
+// lists shorter than kTsSmall, one workgroup each
+__global__ __launch_bounds__(256) void k_tile_sort_small(const uint64_t* __restrict__ keys,
+                                                         const uint32_t* __restrict__ vin,
+                                                         uint32_t* __restrict__ vout,
+                                                         const int32_t* __restrict__ start,
+                                                         const int32_t* __restrict__ order,
+                                                         int64_t cap) {
+  __shared__ uint64_t s[kTsSmall];
+  int64_t s0;
+  int n;
+  list_of(start, order, blockIdx.x, cap, s0, n);
+  if (n >= kTsSmall) return;
+  if (n <= 1) {
+    if (n == 1 && threadIdx.x == 0) vout[s0] = vin[s0];
+    return;
+  }
+  sort_list_lds<256, kTsSmall>(s, keys, vin, vout, s0, n);
+}
+
+// lists of kTsSmall .. kTsLarge - 1 entries: they follow the longer ones at the
+// head of the launch order (descending length), so a fixed grid walks that
+// prefix and stops at the first shorter list
+__global__ __launch_bounds__(1024) void k_tile_sort_large(const uint64_t* __restrict__ keys,
+                                                          const uint32_t* __restrict__ vin,
+                                                          uint32_t* __restrict__ vout,
+                                                          const int32_t* __restrict__ start,
+                                                          const int32_t* __restrict__ order,
+                                                          int total_tiles, int64_t cap) {
+  __shared__ uint64_t s[kTsLarge];
+  for (int i = blockIdx.x; i < total_tiles; i += gridDim.x) {
+    int64_t s0;
+    int n;
+    list_of(start, order, i, cap, s0, n);
+    if (n < kTsSmall) break;
+    if (n >= kTsLarge) continue;
+    sort_list_lds<1024, kTsLarge>(s, keys, vin, vout, s0, n);
+  }
+}
+
+// lists of kTsLarge entries or more: the same network on the keys in global memory
+// (rewritten in place as composite keys), one workgroup per list
+__global__ __launch_bounds__(1024) void k_tile_sort_huge(uint64_t* __restrict__ keys,
+                                                         const uint32_t* __restrict__ vin,
+                                                         uint32_t* __restrict__ vout,
+                                                         const int32_t* __restrict__ start,
+                                                         const int32_t* __restrict__ order,
+                                                         int total_tiles, int64_t cap) {
+  for (int i = blockIdx.x; i < total_tiles; i += gridDim.x) {
+    int64_t s0;
+    int n;
+    list_of(start, order, i, cap, s0, n);
+    if (n < kTsLarge) break;
+    uint64_t* g = keys + s0;
+    for (int q = threadIdx.x; q < n; q += 1024) g[q] = ((uint64_t)(uint32_t)g[q] << 32) | (uint32_t)q;
+    __syncthreads();
+    const int m = next_pow2(n);
+    for (int k = 2; k <= m; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int q = threadIdx.x; q < (m >> 1); q += 1024) {
+          const int a = cmp_lower(q, j);
+          const int b = (j == (k >> 1)) ? (a ^ (k - 1)) : (a + j);
+          if (b >= n) continue;  // the padded partner holds the largest key
+          const uint64_t x = g[a], y = g[b];
+          if (y < x) {
+            g[a] = y;
+            g[b] = x;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int q = threadIdx.x; q < n; q += 1024) vout[s0 + q] = vin[s0 + (uint32_t)g[q]];
+    __syncthreads();
+  }
+}
+
+int sort_passes(int total_tiles, bool by_tile) {
   int tb = 1;
   while ((1ll << tb) < (long long)total_tiles + 1) ++tb;
-  return (32 + tb + 7) / 8;
+  return by_tile ? (tb + 7) / 8 : (32 + tb + 7) / 8;
 }
 
 size_t sort_hist_words(int64_t cap_dup) { return (size_t)256 * scan_blocks(cap_dup); }
@@ -435,21 +579,25 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
   hipError_t e = scan_i32(a.rec_npairs, a.counters + S3R_CNT_SURV, a.cap_surv, a.pair_off,
                           a.scan_sums, a.misc, st);
   if (e != hipSuccess) return e;
-  // 2. emit (tile, depth) keys in record order
-  {
-    const int64_t want = (a.cap_dup + 256 * kEmitRun - 1) / (256 * kEmitRun);
-    const int grid = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
-    S3R_LAUNCH(K_EMIT, k_emit_pairs, dim3(grid), dim3(256), 0, st, a);
-  }
-  // 3. radix passes; the final values land in vals1 (= a.vals) on an odd
-  //    number of passes, in vals0 otherwise (the caller arranges that
-  //    vals0/vals1 make the last destination a.vals)
-  const int passes = radix_passes(a.total_tiles);
+  // radix passes over the tile bits only (then a depth sort per list) or over
+  // all key bits; the values of a full sort end in the caller's array
+  const int passes = sort_passes(a.total_tiles, a.by_tile);
+  const int shift0 = a.by_tile ? 32 : 0;
   const int nblk = scan_blocks(a.cap_dup) > 0 ? scan_blocks(a.cap_dup) : 1;
   uint64_t* kb[2] = {a.keys, a.keys_alt};
   uint32_t* vb[2] = {a.vals0, a.vals1};
+  if (!a.by_tile) vb[passes & 1] = a.vals_out;
+  // 2. emit (tile, depth) keys in record order
+  {
+    SortArgs ea = a;
+    ea.vals0 = vb[0];
+    const int64_t want = (a.cap_dup + 256 * kEmitRun - 1) / (256 * kEmitRun);
+    const int grid = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+    S3R_LAUNCH(K_EMIT, k_emit_pairs, dim3(grid), dim3(256), 0, st, ea);
+  }
+  // 3. radix passes
   for (int p = 0; p < passes; ++p) {
-    const int shift = 8 * p;
+    const int shift = shift0 + 8 * p;
     const int src = p & 1, dst = src ^ 1;
     S3R_LAUNCH(K_RADIX, k_radix_hist, dim3(nblk), dim3(kRT), 0, st, kb[src],
                a.counters + S3R_CNT_DUP, shift, nblk, a.hist);
@@ -458,12 +606,13 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
     S3R_LAUNCH(K_RADIX, k_radix_scatter, dim3(nblk), dim3(kRT), 0, st, kb[src], vb[src], kb[dst],
                vb[dst], a.counters + S3R_CNT_DUP, shift, nblk, a.hist);
   }
-  const uint64_t* sorted = kb[passes & 1];
-  // 4. tile ranges
+  uint64_t* parted = kb[passes & 1];
+  const uint32_t* pvals = vb[passes & 1];
+  // 4. tile ranges and the launch order
   {
     const int want = (a.total_tiles + 1 + 255) / 256;
     const int grid = want < 1024 ? want : 1024;
-    S3R_LAUNCH(K_TILE_RANGES, k_tile_ranges, dim3(grid), dim3(256), 0, st, sorted,
+    S3R_LAUNCH(K_TILE_RANGES, k_tile_ranges, dim3(grid), dim3(256), 0, st, parted,
                a.counters + S3R_CNT_DUP, a.total_tiles, a.tile_start, a.tile_count);
   }
   {
@@ -476,6 +625,16 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
     if (nchunk > 0)
       S3R_LAUNCH(K_TILE_ORDER, k_order_place, dim3(nchunk), dim3(kOrderThreads), 0, st,
                  a.tile_start, a.total_tiles, nchunk, a.order_cnt, a.tile_order);
+  }
+  // 5. depth order inside every list, written to the caller's value array
+  if (a.by_tile) {
+    const int big = a.total_tiles < kTsLargeBlocks ? a.total_tiles : kTsLargeBlocks;
+    S3R_LAUNCH(K_TILE_SORT_HUGE, k_tile_sort_huge, dim3(big), dim3(1024), 0, st, parted, pvals,
+               a.vals_out, a.tile_start, a.tile_order, a.total_tiles, a.cap_dup);
+    S3R_LAUNCH(K_TILE_SORT_LARGE, k_tile_sort_large, dim3(big), dim3(1024), 0, st, parted, pvals,
+               a.vals_out, a.tile_start, a.tile_order, a.total_tiles, a.cap_dup);
+    S3R_LAUNCH(K_TILE_SORT, k_tile_sort_small, dim3(a.total_tiles), dim3(256), 0, st, parted,
+               pvals, a.vals_out, a.tile_start, a.tile_order, a.cap_dup);
   }
   return hipGetLastError();
 }

@@ -228,6 +228,13 @@ class Renderer:
             flags |= A.S3R_LOD_STOCHASTIC
         if p.get("grad_sparse", False):
             flags |= A.S3R_GRAD_SPARSE
+        # per-tile sort when lists are short: by default with the LOD cull,
+        # which keeps sub-pixel Gaussians out of the lists
+        sort = p.get("sort") or ("tiles" if p.get("lod", False) else "global")
+        if sort not in ("tiles", "global"):
+            raise ValueError(f"sort must be 'tiles' or 'global', not {sort!r}")
+        if sort == "tiles":
+            flags |= A.S3R_SORT_TILES
         bg = (C.c_float * 3)(*[float(x) for x in p["bg"]])
         return A.S3RParams(int(p["tile"]), flags, float(p["lod_r"]), float(p["z_near"]),
                            float(p["z_far"]), float(p["eps2d"]), float(p["alpha_min"]),

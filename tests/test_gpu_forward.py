@@ -151,19 +151,46 @@ def test_batched_uneven_views_equal_single_views():
         np.testing.assert_array_equal(mask_bits(rb)[j], mask_bits(rs)[0])
 
 
-@pytest.mark.parametrize("n", [9000, 30000])
-def test_crowded_tiles_sorted_exactly(n):
+@pytest.mark.parametrize("n,sort", [(9000, "tiles"), (30000, "tiles"), (30000, "global")])
+def test_crowded_tiles_sorted_exactly(n, sort):
     """Tens of thousands of Gaussians pile into a few tiles: lists spanning
-    many radix-sort blocks must still match the oracle's order bit for bit."""
+    many radix-sort blocks -- with the per-tile sort, lists sorted in LDS (up
+    to 16383 entries) or in global memory (longer) -- must still match the
+    oracle's order bit for bit."""
     scene, views = scenes.micro_scene(11, n=n, width=64, height=48, n_inst=0, spread=0.05, T=1)
-    p = scenes.default_params(tile=16)
-    banner(f"crowded tiles n={n}")
+    p = dict(scenes.default_params(tile=16), sort=sort)
+    banner(f"crowded tiles n={n} sort={sort}")
     r = make_renderer(scene, views, p)
     r.forward()
     rec = records(r)
     counts = r.tile_count.cpu().numpy()
     assert counts.max() > 4096
+    if n > 20000:
+        assert counts.max() >= 16384  # the global-memory network runs
+    else:
+        assert 2048 <= counts.max() < 16384
     check_view(scene, views, p, r, rec, 0, region=(16, 16, 48, 40))
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_sort_modes_agree(tile):
+    """The per-tile sort (tile partition + per-list depth sort) and the full
+    radix sort give the same lists, entry for entry, on every view of a
+    corridor batch (six 960x640 views of 240k Gaussians, LOD off, so lists
+    are long and many)."""
+    cfg = scenes.make_config(2)
+    views = cfg.views.subset([0, 9, 19, 29, 39, 49])
+    banner(f"sort modes tile={tile}")
+    out = {}
+    for sort in ("global", "tiles"):
+        p = dict(cfg.params, tile=tile, sort=sort, lod=False, lod_r=0.0)
+        r = make_renderer(cfg.scene, views, p)
+        r.forward()
+        n = int(r.counters.cpu().numpy()[2])
+        out[sort] = (r.tile_start.cpu().numpy().copy(), r.vals.cpu().numpy()[:n].copy(),
+                     r.tile_order.cpu().numpy().copy())
+    for a, b in zip(out["global"], out["tiles"]):
+        np.testing.assert_array_equal(a, b)
 
 
 def test_tile_launch_order():

@@ -57,7 +57,8 @@ KERNEL_SOURCES = {
 
 # kernels of steps a1-a8 (instance cameras through tile ranges)
 PCS_KERNELS = ("compose", "project", "block_offsets", "records", "scan", "emit_pairs", "radix",
-               "tile_ranges", "tile_order")
+               "tile_ranges", "tile_order", "tile_sort", "tile_sort_chunks", "tile_sort_merge",
+               "tile_sort_huge")
 
 
 def sources_digest(kernel):
@@ -405,7 +406,8 @@ def visibility_sources(cfg, targets, torch, steps=16):
 
 def batched_graph(cfg, torch, replays, tiles):
     """Batched multi-view step (all timed views of the workload in one batch)
-    captured in a HIP graph; tile size picked by timing each candidate."""
+    captured in a HIP graph; tile size and sort mode picked by timing each
+    candidate."""
     from paper_2503_08217_amd import S3R_VIS_FOLD, S3R_VIS_UPDATE
     from paper_2503_08217_amd.renderer import Renderer
     import scenes
@@ -430,8 +432,8 @@ def batched_graph(cfg, torch, replays, tiles):
     torch.cuda.empty_cache()
     best = None
     tune = []
-    for tile in tiles:
-        params = dict(cfg.params, tile=tile, grad_sparse=True)
+    for tile, sort in [(t, m) for t in tiles for m in ("tiles", "global")]:
+        params = dict(cfg.params, tile=tile, grad_sparse=True, sort=sort)
         r = Renderer(cfg.scene, views, params, cap_surv=max(1024, cfg.scene.n // 2),
                      cap_dup=max(4096, 2 * cfg.scene.n))
         r.vis_s.copy_(vis_s)
@@ -465,7 +467,7 @@ def batched_graph(cfg, torch, replays, tiles):
         units = [dict(N_t=int(x[0]), N_f=int(x[1]), N_r=int(x[2]), N_dup=int(x[3])) for x in st]
         pcs_ms = sum(table[k][0] for k in PCS_KERNELS if k in table) / prof_steps
         pcs_b = pcs_batch_bytes(units, cfg.scene.sh_degree, cfg.scene.n)
-        res = {"tile": tile, "p50_ms": float(np.percentile(ms, 50)),
+        res = {"tile": tile, "sort": sort, "p50_ms": float(np.percentile(ms, 50)),
                "p99_ms": float(np.percentile(ms, 99)), "mean_ms": float(ms.mean()),
                "views_per_s": views.n_views / (ms.mean() * 1e-3),
                "mean_visible_fraction": float(st[:, 0].mean() / cfg.scene.n),
@@ -476,7 +478,7 @@ def batched_graph(cfg, torch, replays, tiles):
                                          "frac": pcs_b / (pcs_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                          "ms_per_step": pcs_ms, "bytes": pcs_b},
                "kernels_us_per_step": {k: 1000 * v[0] / prof_steps for k, v in table.items()}}
-        log(f"batched {cfg.name} tile {tile}: p50 {res['p50_ms']:.2f} ms, p99 "
+        log(f"batched {cfg.name} tile {tile} sort {sort}: p50 {res['p50_ms']:.2f} ms, p99 "
             f"{res['p99_ms']:.2f} ms, {res['views_per_s']:.1f} views/s, N_t/N "
             f"{res['mean_visible_fraction']:.3f}, project/cull/sort "
             f"{res['project_cull_sort_hbm']['ms_per_step']:.3f} ms at "

@@ -9,9 +9,9 @@ namespace s3r {
 // kernels timed by the opt-in profiler (names in profile.hip)
 enum KernelId {
   K_COMPOSE, K_PLAIN_TRANSFORM, K_PROJECT, K_STATS, K_RECORDS, K_SCAN, K_EMIT, K_RADIX,
-  K_TILE_RANGES, K_TILE_ORDER, K_TILE_SORT, K_TILE_SORT_LARGE,
-  K_TILE_SORT_HUGE, K_RASTER_FWD, K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PAIR_REDUCE,
-  K_PROJECT_BWD, K_POSE_BWD, K_POSE6, K_PLAIN_TRANSFORM_BWD, K_VISIBILITY, K_ZERO, K_COUNT
+  K_TILE_RANGES, K_TILE_ORDER, K_TILE_SORT, K_TILE_SORT_CHUNKS, K_TILE_SORT_MERGE,
+  K_TILE_SORT_HUGE, K_RASTER_FWD, K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PAIR_REDUCE, K_PROJECT_BWD,
+  K_POSE_BWD, K_POSE6, K_PLAIN_TRANSFORM_BWD, K_VISIBILITY, K_ZERO, K_COUNT
 };
 void prof_begin(int id, hipStream_t st);
 void prof_end(int id, hipStream_t st);
@@ -112,7 +112,7 @@ struct BwdArgs {
   const int32_t* rec_pair;
   const int4* rec_rect;
   // per-pair 2D gradients (workspace, [cap_dup][12] floats), summed per
-  // record into g2d ([cap_surv][12] floats)
+  // record into g2d ([cap_surv][12] floats, every record written)
   float4* part;
   // per tile: the first list entry the backward did not replay (record,
   // depth bits), or record -1 when it replayed the whole list (workspace)

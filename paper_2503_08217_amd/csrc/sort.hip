@@ -17,8 +17,8 @@
 //   4. tile ranges by binary search of the sorted keys; the tiles' launch
 //      order (descending list length)
 //   5. with S3R_SORT_TILES, k_tile_sort_*: each list sorted by (depth bits,
-//      position) with a bitonic network in LDS, one workgroup per list (lists
-//      too long for LDS are sorted in place in global memory by one workgroup)
+//      position) with bitonic networks in LDS (long lists in chunks merged by
+//      rank; lists too long for LDS in place in global memory)
 // No kernel waits on another workgroup and none uses a contended atomic.
 #include "internal.hpp"
 
@@ -433,11 +433,28 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_place(const int32_t* __
 // the element j places on in the later steps; all comparators put the smaller
 // key at the lower index, so keys padded at the end with the largest value
 // never move and lengths need not be powers of two.
-// Size classes follow the binary-logarithm buckets of the launch order, so
-// that each class above the smallest is a prefix of that order.
-constexpr int kTsSmall = 2048;    // lists shorter than this: 256 threads, 16 KB LDS
-constexpr int kTsLarge = 16384;   // shorter than this: 1024 threads, 128 KB LDS
+//
+// Inside a wave the keys live in registers: lane l holds positions l E .. l E
+// + E - 1, steps at distance below E are register compare-swaps and longer
+// ones exchange keys with the partner lane (shuffles); only steps between
+// waves go through LDS.
+//
+// Size classes follow the binary-logarithm buckets of the launch order (lists
+// by descending length), so each longer class is a prefix of that order:
+//   tiny  (< kTsTiny entries): one wave per list, E = 1 .. 8 keys per lane
+//   small (< kTsChunk): four waves per list, 8 keys per lane
+//   large (< kTsLarge): chunks of kTsChunk entries sorted like small lists by
+//         separate workgroups, then merged in LDS by rank (an entry's place
+//         is its place in its chunk plus the entries below it in the others)
+//   huge  (>= kTsLarge): one workgroup, in global memory
+constexpr int kTsTiny = 512;
+constexpr int kTsChunk = 2048;
+constexpr int kTsLarge = 16384;
+constexpr int kTsMaxChunks = kTsLarge / kTsChunk;
+constexpr int kTsChunkBlocks = 1024;
 constexpr int kTsLargeBlocks = 256;
+constexpr int kTsE = 8;                    // keys per lane of the small class
+constexpr int kTsWaveKeys = kWave * kTsE;  // 512: keys per wave
 
 __device__ __forceinline__ int next_pow2(int n) {
   int m = 1;
@@ -448,36 +465,66 @@ __device__ __forceinline__ int next_pow2(int n) {
 // lower element of comparator q at distance j (a zero bit inserted at log2 j)
 __device__ __forceinline__ int cmp_lower(int q, int j) { return ((q & ~(j - 1)) << 1) | (q & (j - 1)); }
 
-template <int NTH>
-__device__ void bitonic_lds(uint64_t* s, int m) {
-  for (int k = 2; k <= m; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int q = threadIdx.x; q < (m >> 1); q += NTH) {
-        const int i = cmp_lower(q, j);
-        const int pr = (j == (k >> 1)) ? (i ^ (k - 1)) : (i + j);
-        const uint64_t x = s[i], y = s[pr];
-        if (y < x) {
-          s[i] = y;
-          s[pr] = x;
-        }
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int mask) {
+  const int lo = __shfl_xor((int)(uint32_t)v, mask, kWave);
+  const int hi = __shfl_xor((int)(uint32_t)(v >> 32), mask, kWave);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// step (K, J) of the network on a wave's 64 E register keys
+template <int E, int K, int J>
+__device__ __forceinline__ void net_step(uint64_t (&x)[E], int lane) {
+  constexpr bool flip = J == K / 2;
+  if constexpr (J < E) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int f = flip ? (e ^ (K - 1)) : (e ^ J);
+      if (f > e) {
+        const uint64_t a = x[e], b = x[f];
+        x[e] = b < a ? b : a;
+        x[f] = b < a ? a : b;
       }
-      __syncthreads();
+    }
+  } else {
+    // partner lane and, in a mirror step, the mirrored register
+    constexpr int lmask = flip ? (K / E - 1) : (J / E);
+    constexpr int hb = flip ? (K / (2 * E)) : (J / E);
+    const bool lower = (lane & hb) == 0;
+    uint64_t y[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[e] = shfl_xor64(x[flip ? (E - 1 - e) : e], lmask);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const bool take = lower ? (y[e] < x[e]) : (x[e] < y[e]);
+      x[e] = take ? y[e] : x[e];
     }
   }
 }
 
-template <int NTH, int CAP>
-__device__ void sort_list_lds(uint64_t* s, const uint64_t* __restrict__ keys,
-                              const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout,
-                              int64_t s0, int n) {
-  const int m = next_pow2(n);
-  for (int i = threadIdx.x; i < m; i += NTH)
-    s[i] = i < n ? (((uint64_t)(uint32_t)keys[s0 + i] << 32) | (uint32_t)i) : ~0ull;
-  __syncthreads();
-  bitonic_lds<NTH>(s, m);
-  for (int i = threadIdx.x; i < n; i += NTH) vout[s0 + i] = vin[s0 + (uint32_t)s[i]];
-  __syncthreads();
-}
+// steps J, J/2, .., 1 of a merge of size K
+template <int E, int K, int J>
+struct NetMerge {
+  __device__ __forceinline__ static void run(uint64_t (&x)[E], int lane) {
+    net_step<E, K, J>(x, lane);
+    NetMerge<E, K, J / 2>::run(x, lane);
+  }
+};
+template <int E, int K>
+struct NetMerge<E, K, 0> {
+  __device__ __forceinline__ static void run(uint64_t (&)[E], int) {}
+};
+// all merges of sizes 2 .. K
+template <int E, int K>
+struct NetSort {
+  __device__ __forceinline__ static void run(uint64_t (&x)[E], int lane) {
+    NetSort<E, K / 2>::run(x, lane);
+    NetMerge<E, K, K / 2>::run(x, lane);
+  }
+};
+template <int E>
+struct NetSort<E, 1> {
+  __device__ __forceinline__ static void run(uint64_t (&)[E], int) {}
+};
 
 __device__ __forceinline__ void list_of(const int32_t* start, const int32_t* order, int i,
                                         int64_t cap, int64_t& s0, int& n) {
@@ -486,42 +533,227 @@ __device__ __forceinline__ void list_of(const int32_t* start, const int32_t* ord
   n = (int)(min((int64_t)start[t + 1], cap) - s0);
 }
 
-// lists shorter than kTsSmall, one workgroup each
-__global__ __launch_bounds__(256) void k_tile_sort_small(const uint64_t* __restrict__ keys,
-                                                         const uint32_t* __restrict__ vin,
-                                                         uint32_t* __restrict__ vout,
-                                                         const int32_t* __restrict__ start,
-                                                         const int32_t* __restrict__ order,
-                                                         int64_t cap) {
-  __shared__ uint64_t s[kTsSmall];
-  int64_t s0;
-  int n;
-  list_of(start, order, blockIdx.x, cap, s0, n);
-  if (n >= kTsSmall) return;
-  if (n <= 1) {
-    if (n == 1 && threadIdx.x == 0) vout[s0] = vin[s0];
-    return;
+// keys [at + base, at + base + 64 E) of this wave's lanes as composite keys
+// (positions from pos0), the largest key past len
+template <int E>
+__device__ __forceinline__ void load_keys(uint64_t (&x)[E], const uint64_t* __restrict__ keys,
+                                          int64_t at, int base, int len, uint32_t pos0, int lane) {
+  uint32_t d[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int p = base + lane * E + e;
+    d[e] = p < len ? (uint32_t)keys[at + p] : 0u;
   }
-  sort_list_lds<256, kTsSmall>(s, keys, vin, vout, s0, n);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int p = base + lane * E + e;
+    x[e] = p < len ? (((uint64_t)d[e] << 32) | (pos0 + (uint32_t)p)) : ~0ull;
+  }
 }
 
-// lists of kTsSmall .. kTsLarge - 1 entries: they follow the longer ones at the
-// head of the launch order (descending length), so a fixed grid walks that
-// prefix and stops at the first shorter list
-__global__ __launch_bounds__(1024) void k_tile_sort_large(const uint64_t* __restrict__ keys,
+// vout[s0 + p] = vin[s0 + position of sorted key p] for this lane's keys
+template <int E>
+__device__ __forceinline__ void gather_keys(const uint64_t (&x)[E], const uint32_t* __restrict__ vin,
+                                            uint32_t* __restrict__ vout, int64_t s0, int base,
+                                            int n, int lane) {
+  uint32_t r[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int p = base + lane * E + e;
+    r[e] = p < n ? vin[s0 + (uint32_t)x[e]] : 0u;
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int p = base + lane * E + e;
+    if (p < n) vout[s0 + p] = r[e];
+  }
+}
+
+template <int E>
+__device__ __forceinline__ void sort_tiny(const uint64_t* __restrict__ keys,
+                                          const uint32_t* __restrict__ vin,
+                                          uint32_t* __restrict__ vout, int64_t s0, int n,
+                                          int lane) {
+  uint64_t x[E];
+  load_keys<E>(x, keys, s0, 0, n, 0u, lane);
+  NetSort<E, kWave * E>::run(x, lane);
+  gather_keys<E>(x, vin, vout, s0, 0, n, lane);
+}
+
+// tiny lists, one wave each
+__global__ __launch_bounds__(kWave) void k_tile_sort_tiny(const uint64_t* __restrict__ keys,
                                                           const uint32_t* __restrict__ vin,
                                                           uint32_t* __restrict__ vout,
                                                           const int32_t* __restrict__ start,
                                                           const int32_t* __restrict__ order,
-                                                          int total_tiles, int64_t cap) {
-  __shared__ uint64_t s[kTsLarge];
-  for (int i = blockIdx.x; i < total_tiles; i += gridDim.x) {
+                                                          int64_t cap) {
+  int64_t s0;
+  int n;
+  list_of(start, order, blockIdx.x, cap, s0, n);
+  const int lane = threadIdx.x;
+  if (n >= kTsTiny || n <= 0) return;
+  if (n == 1) {
+    if (lane == 0) vout[s0] = vin[s0];
+  } else if (n <= kWave) {
+    sort_tiny<1>(keys, vin, vout, s0, n, lane);
+  } else if (n <= 2 * kWave) {
+    sort_tiny<2>(keys, vin, vout, s0, n, lane);
+  } else if (n <= 4 * kWave) {
+    sort_tiny<4>(keys, vin, vout, s0, n, lane);
+  } else {
+    sort_tiny<8>(keys, vin, vout, s0, n, lane);
+  }
+}
+
+// Launch-order positions where the lists drop below kTsLarge, kTsChunk and
+// kTsTiny entries: the starts of the corresponding length buckets, read from
+// the (bucket, chunk) offsets of the launch-order sort.
+__device__ __forceinline__ void class_bounds(const int32_t* ocnt, int nchunk, int& h, int& l,
+                                             int& t) {
+  h = ocnt[2 * nchunk];  // lengths >= 2^14
+  l = ocnt[5 * nchunk];  // lengths >= 2^11
+  t = ocnt[7 * nchunk];  // lengths >= 2^9
+}
+
+// small lists, and the chunks of large lists.  Work items are the kTsMaxChunks
+// chunks of every large list, then one item per small list.  Each wave sorts
+// its 512 keys in registers; merges of 1024 and 2048 keys take their steps
+// between waves through LDS.  A small list is written out, a large list's
+// chunk goes back in place as sorted composite keys.
+__global__ __launch_bounds__(256) void k_tile_sort_chunks(uint64_t* __restrict__ keys,
+                                                          const uint32_t* __restrict__ vin,
+                                                          uint32_t* __restrict__ vout,
+                                                          const int32_t* __restrict__ start,
+                                                          const int32_t* __restrict__ order,
+                                                          const int32_t* __restrict__ ocnt,
+                                                          int nchunk, int64_t cap) {
+  __shared__ uint64_t s[kTsChunk];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int base = wave * kTsWaveKeys;
+  int lh, ll, lt;
+  class_bounds(ocnt, nchunk, lh, ll, lt);
+  const int64_t n_large_items = (int64_t)kTsMaxChunks * (ll - lh);
+  const int64_t n_items = n_large_items + (lt - ll);
+  for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    int i, c;
+    if (item < n_large_items) {
+      i = lh + (int)(item / kTsMaxChunks);
+      c = (int)(item % kTsMaxChunks);
+    } else {
+      i = ll + (int)(item - n_large_items);
+      c = 0;
+    }
     int64_t s0;
     int n;
     list_of(start, order, i, cap, s0, n);
-    if (n < kTsSmall) break;
-    if (n >= kTsLarge) continue;
-    sort_list_lds<1024, kTsLarge>(s, keys, vin, vout, s0, n);
+    const int c0 = c * kTsChunk;
+    if (c0 >= n) continue;
+    const int len = min(kTsChunk, n - c0);
+    uint64_t x[kTsE];
+    load_keys<kTsE>(x, keys, s0 + c0, base, len, (uint32_t)c0, lane);
+    NetSort<kTsE, kTsWaveKeys>::run(x, lane);
+    const int mtop = next_pow2(len);  // merges above this size leave the keys in place
+    for (int k = 2 * kTsWaveKeys; k <= mtop; k <<= 1) {
+      for (int j = k >> 1; j >= kTsWaveKeys; j >>= 1) {
+#pragma unroll
+        for (int e = 0; e < kTsE; ++e) s[base + lane * kTsE + e] = x[e];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < kTsE; ++e) {
+          const int p = base + lane * kTsE + e;
+          const int q = (j == (k >> 1)) ? (p ^ (k - 1)) : (p ^ j);
+          const uint64_t y = s[q];
+          const bool take = p < q ? (y < x[e]) : (x[e] < y);
+          x[e] = take ? y : x[e];
+        }
+        __syncthreads();
+      }
+      NetMerge<kTsE, 4 * kTsChunk, kTsWaveKeys / 2>::run(x, lane);
+    }
+    if (n < kTsChunk) {
+      gather_keys<kTsE>(x, vin, vout, s0, base, n, lane);
+    } else {
+#pragma unroll
+      for (int e = 0; e < kTsE; ++e) {
+        const int p = base + lane * kTsE + e;
+        if (p < len) keys[s0 + c0 + p] = x[e];
+      }
+    }
+  }
+}
+
+// large lists: rank merge of their sorted chunks.  Each thread holds up to
+// kTsLarge / 1024 entries and walks the binary searches of all of them in
+// step (fixed-step, branch-free lower bounds), so their LDS reads overlap.
+__global__ __launch_bounds__(1024) void k_tile_sort_merge(const uint64_t* __restrict__ keys,
+                                                          const uint32_t* __restrict__ vin,
+                                                          uint32_t* __restrict__ vout,
+                                                          const int32_t* __restrict__ start,
+                                                          const int32_t* __restrict__ order,
+                                                          const int32_t* __restrict__ ocnt,
+                                                          int nchunk, int64_t cap) {
+  constexpr int NTH = 1024, E = kTsLarge / NTH;
+  __shared__ uint64_t s[kTsLarge];
+  int lh, ll, lt;
+  class_bounds(ocnt, nchunk, lh, ll, lt);
+  for (int i = lh + blockIdx.x; i < ll; i += gridDim.x) {
+    int64_t s0;
+    int n;
+    list_of(start, order, i, cap, s0, n);
+    uint64_t x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int q = threadIdx.x + e * NTH;
+      x[e] = q < n ? keys[s0 + q] : ~0ull;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int q = threadIdx.x + e * NTH;
+      if (q < n) s[q] = x[e];
+    }
+    __syncthreads();
+    const int nc = (n + kTsChunk - 1) / kTsChunk;
+    int pos[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int q = threadIdx.x + e * NTH;
+      pos[e] = q % kTsChunk;
+    }
+    for (int d = 0; d < nc; ++d) {
+      const int base = d * kTsChunk, len = min(kTsChunk, n - base);
+      int lo[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) lo[e] = 0;
+      // entries of chunk d below x: the largest lo with s[base + lo - 1] < x
+      // (slots past the list's end and slots of chunk d itself skip the search)
+      for (int step = kTsChunk; step > 0; step >>= 1) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int q = threadIdx.x + e * NTH;
+          if (q < n && q / kTsChunk != d) {
+            const int t = lo[e] + step;
+            if (t <= len && s[base + t - 1] < x[e]) lo[e] = t;
+          }
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int q = threadIdx.x + e * NTH;
+        if (q / kTsChunk != d) pos[e] += lo[e];
+      }
+    }
+    uint32_t r[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int q = threadIdx.x + e * NTH;
+      r[e] = q < n ? vin[s0 + (uint32_t)x[e]] : 0u;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int q = threadIdx.x + e * NTH;
+      if (q < n) vout[s0 + pos[e]] = r[e];
+    }
+    __syncthreads();
   }
 }
 
@@ -532,12 +764,14 @@ __global__ __launch_bounds__(1024) void k_tile_sort_huge(uint64_t* __restrict__ 
                                                          uint32_t* __restrict__ vout,
                                                          const int32_t* __restrict__ start,
                                                          const int32_t* __restrict__ order,
-                                                         int total_tiles, int64_t cap) {
-  for (int i = blockIdx.x; i < total_tiles; i += gridDim.x) {
+                                                         const int32_t* __restrict__ ocnt,
+                                                         int nchunk, int64_t cap) {
+  int lh, ll, lt;
+  class_bounds(ocnt, nchunk, lh, ll, lt);
+  for (int i = blockIdx.x; i < lh; i += gridDim.x) {
     int64_t s0;
     int n;
     list_of(start, order, i, cap, s0, n);
-    if (n < kTsLarge) break;
     uint64_t* g = keys + s0;
     for (int q = threadIdx.x; q < n; q += 1024) g[q] = ((uint64_t)(uint32_t)g[q] << 32) | (uint32_t)q;
     __syncthreads();
@@ -628,12 +862,16 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
   }
   // 5. depth order inside every list, written to the caller's value array
   if (a.by_tile) {
+    const int nchunk = (a.total_tiles + kOrderChunk - 1) / kOrderChunk;
     const int big = a.total_tiles < kTsLargeBlocks ? a.total_tiles : kTsLargeBlocks;
     S3R_LAUNCH(K_TILE_SORT_HUGE, k_tile_sort_huge, dim3(big), dim3(1024), 0, st, parted, pvals,
-               a.vals_out, a.tile_start, a.tile_order, a.total_tiles, a.cap_dup);
-    S3R_LAUNCH(K_TILE_SORT_LARGE, k_tile_sort_large, dim3(big), dim3(1024), 0, st, parted, pvals,
-               a.vals_out, a.tile_start, a.tile_order, a.total_tiles, a.cap_dup);
-    S3R_LAUNCH(K_TILE_SORT, k_tile_sort_small, dim3(a.total_tiles), dim3(256), 0, st, parted,
+               a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk, a.cap_dup);
+    S3R_LAUNCH(K_TILE_SORT_CHUNKS, k_tile_sort_chunks, dim3(kTsChunkBlocks), dim3(256), 0, st,
+               parted, pvals, a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk,
+               a.cap_dup);
+    S3R_LAUNCH(K_TILE_SORT_MERGE, k_tile_sort_merge, dim3(big), dim3(1024), 0, st, parted, pvals,
+               a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk, a.cap_dup);
+    S3R_LAUNCH(K_TILE_SORT, k_tile_sort_tiny, dim3(a.total_tiles), dim3(kWave), 0, st, parted,
                pvals, a.vals_out, a.tile_start, a.tile_order, a.cap_dup);
   }
   return hipGetLastError();

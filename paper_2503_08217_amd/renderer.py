@@ -19,6 +19,9 @@ import torch
 
 from . import _abi as A
 
+# lists of this many entries or more take the per-tile sort's slow path
+TILE_SORT_MAX = 16384
+
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
@@ -43,6 +46,7 @@ class Renderer:
         A.load()
         self.dev = torch.device(device)
         self.params = dict(params)
+        self._max_list = None  # longest tile list seen by fit_capacity
         self.plain = bool(plain)
         self.V = int(views.n_views)
         self.n = int(scene.mean.shape[0])
@@ -228,11 +232,15 @@ class Renderer:
             flags |= A.S3R_LOD_STOCHASTIC
         if p.get("grad_sparse", False):
             flags |= A.S3R_GRAD_SPARSE
-        # per-tile sort when lists are short: by default with the LOD cull,
-        # which keeps sub-pixel Gaussians out of the lists
-        sort = p.get("sort") or ("tiles" if p.get("lod", False) else "global")
-        if sort not in ("tiles", "global"):
-            raise ValueError(f"sort must be 'tiles' or 'global', not {sort!r}")
+        # sort mode: "tiles" (tile partition + per-list depth sort) is fastest
+        # while lists stay short; "auto" takes it when every list seen by the
+        # last capacity fit held fewer than TILE_SORT_MAX entries
+        sort = p.get("sort") or "auto"
+        if sort not in ("tiles", "global", "auto"):
+            raise ValueError(f"sort must be 'tiles', 'global' or 'auto', not {sort!r}")
+        if sort == "auto":
+            sort = "tiles" if (self._max_list is not None and
+                               self._max_list < TILE_SORT_MAX) else "global"
         if sort == "tiles":
             flags |= A.S3R_SORT_TILES
         bg = (C.c_float * 3)(*[float(x) for x in p["bg"]])
@@ -245,7 +253,10 @@ class Renderer:
                            int(p.get("step", 0)) & 0xFFFFFFFF, 0)
 
     def set_flags(self, **over):
+        """Change parameters; the longest list seen so far is forgotten (the
+        next fit_capacity measures it again for the "auto" sort mode)."""
         self.params.update(over)
+        self._max_list = None
         self.c_params = self.make_params()
 
     # ------------------------------------------------------------ entry points
@@ -364,6 +375,10 @@ class Renderer:
             need_s = c["n_surv"] + c["ovf_surv"]
             need_d = c["n_dup"] + c["ovf_dup"]
             if c["ovf_surv"] == 0 and c["ovf_dup"] == 0:
+                longest = int(self.tile_count[: self.total_tiles].max().item())
+                self._max_list = max(self._max_list or 0, longest)
+                c["max_list"] = longest
+                self.c_params = self.make_params()
                 return c
             self.cap_surv = max(self.cap_surv, int(math.ceil(need_s * margin)) + 1024)
             self.cap_dup = max(self.cap_dup, int(math.ceil(need_d * margin)) + 4096)

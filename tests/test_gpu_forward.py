@@ -193,6 +193,20 @@ def test_sort_modes_agree(tile):
         np.testing.assert_array_equal(a, b)
 
 
+def test_auto_sort_mode_follows_list_length():
+    """The renderer's default 'auto' sort: the per-tile sort after a capacity
+    fit saw only short lists, the full radix sort when a list reached 16384
+    entries (crowded tiles); both give the oracle's lists (checked above)."""
+    from paper_2503_08217_amd import _abi as A
+    from paper_2503_08217_amd.renderer import TILE_SORT_MAX
+    cfg = scenes.make_config(1)
+    r = make_renderer(cfg.scene, cfg.views, cfg.params)
+    assert r._max_list < TILE_SORT_MAX and r.c_params.flags & A.S3R_SORT_TILES
+    scene, views = scenes.micro_scene(11, n=30000, width=64, height=48, n_inst=0, spread=0.05, T=1)
+    r = make_renderer(scene, views, scenes.default_params(tile=16))
+    assert r._max_list >= TILE_SORT_MAX and not r.c_params.flags & A.S3R_SORT_TILES
+
+
 def test_tile_launch_order():
     """The rasterizer's launch order: every tile once, by descending binary
     logarithm of its list length (empty lists last), tile order within a

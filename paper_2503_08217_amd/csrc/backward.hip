@@ -76,8 +76,10 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
     dCg = a.d_color[base + npx + p];
     dCb = a.d_color[base + 2 * npx + p];
   }
-  const float bgdot = T * (a.kp.bg0 * dCr + a.kp.bg1 * dCg + a.kp.bg2 * dCb);
-  float Sr = 0.f, Sg = 0.f, Sb = 0.f;
+  // sd = (S_i + T_N bg) . dL/dC, S_i the colour blended behind entry i: only
+  // this dot product enters dL/dalpha, so it is accumulated directly, each
+  // replayed entry adding (c . dL/dC) alpha T
+  float sd = T * (a.kp.bg0 * dCr + a.kp.bg1 * dCg + a.kp.bg2 * dCb);
   // each wave replays its own list prefix (entries up to its last contributor)
   int mw = last;
 #pragma unroll
@@ -143,9 +145,9 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
         const float rinv = __builtin_amdgcn_rcpf(one_m);  // one_m >= 1 - alpha_max
         const float Tb = T * rinv;
         const float wgt = contrib ? bl.alpha * Tb : 0.f;
-        const float cdot = kr * dCr + kg * dCg + kb * dCb;
-        const float sdot = Sr * dCr + Sg * dCg + Sb * dCb;
-        const float dal = Tb * cdot - (sdot + bgdot) * rinv;
+        // gradient arithmetic (no decision depends on it) in fused form
+        const float cdot = fmaf(kb, dCb, fmaf(kg, dCg, kr * dCr));
+        const float dal = fmaf(Tb, cdot, -sd * rinv);
         // alpha clamped at alpha_max carries no gradient to o and the conic
         const bool open = contrib && (bl.raw <= a.kp.alpha_max);
         const float dpow = open ? dal * bl.alpha : 0.f;
@@ -157,9 +159,7 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
         const float dy = vv - fyp;
         const float m_x = dpow * dx, m_y = dpow * dy;
         const float m_xx = m_x * dx, m_xy = m_x * dy, m_yy = m_y * dy;
-        Sr = fmaf(kr, wgt, Sr);
-        Sg = fmaf(kg, wgt, Sg);
-        Sb = fmaf(kb, wgt, Sb);
+        sd = fmaf(cdot, wgt, sd);
         T = contrib ? Tb : T;
         // window slot q of the record receives, in order, m_x, m_y, m_xx, m_xy
         // (from s1), m_yy, o, r, g (from s2) and b (lane 63 of sb)

@@ -682,9 +682,14 @@ __global__ __launch_bounds__(256) void k_tile_sort_chunks(uint64_t* __restrict__
   }
 }
 
-// large lists: rank merge of their sorted chunks.  Each thread holds up to
-// kTsLarge / 1024 entries and walks the binary searches of all of them in
-// step (fixed-step, branch-free lower bounds), so their LDS reads overlap.
+// large lists: rank merge of their sorted chunks.  Work items are slices of
+// kTsMergeSlice entries of every large list, so the longest list is placed by
+// several workgroups at once; each stages the whole list in LDS and walks the
+// binary searches of its entries in step (fixed-step, branch-free lower
+// bounds), so their LDS reads overlap.
+constexpr int kTsMergeSlice = 2048;
+constexpr int kTsMergeBlocks = 512;
+
 __global__ __launch_bounds__(1024) void k_tile_sort_merge(const uint64_t* __restrict__ keys,
                                                           const uint32_t* __restrict__ vin,
                                                           uint32_t* __restrict__ vout,
@@ -692,31 +697,40 @@ __global__ __launch_bounds__(1024) void k_tile_sort_merge(const uint64_t* __rest
                                                           const int32_t* __restrict__ order,
                                                           const int32_t* __restrict__ ocnt,
                                                           int nchunk, int64_t cap) {
-  constexpr int NTH = 1024, E = kTsLarge / NTH;
+  constexpr int NTH = 1024, EL = kTsLarge / NTH, E = kTsMergeSlice / NTH;
+  constexpr int SLICES = kTsLarge / kTsMergeSlice;
   __shared__ uint64_t s[kTsLarge];
   int lh, ll, lt;
   class_bounds(ocnt, nchunk, lh, ll, lt);
-  for (int i = lh + blockIdx.x; i < ll; i += gridDim.x) {
+  const int64_t n_items = (int64_t)SLICES * (ll - lh);
+  for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const int i = lh + (int)(item / SLICES);
+    const int q0 = (int)(item % SLICES) * kTsMergeSlice;
     int64_t s0;
     int n;
     list_of(start, order, i, cap, s0, n);
-    uint64_t x[E];
+    if (q0 >= n) continue;
+    uint64_t v[EL];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
+    for (int e = 0; e < EL; ++e) {
       const int q = threadIdx.x + e * NTH;
-      x[e] = q < n ? keys[s0 + q] : ~0ull;
+      v[e] = q < n ? keys[s0 + q] : ~0ull;
     }
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
+    for (int e = 0; e < EL; ++e) {
       const int q = threadIdx.x + e * NTH;
-      if (q < n) s[q] = x[e];
+      if (q < n) s[q] = v[e];
     }
     __syncthreads();
     const int nc = (n + kTsChunk - 1) / kTsChunk;
-    int pos[E];
+    const int qe = min(n, q0 + kTsMergeSlice);
+    uint64_t x[E];
+    int pos[E], own[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int q = threadIdx.x + e * NTH;
+      const int q = q0 + threadIdx.x + e * NTH;
+      x[e] = q < qe ? s[q] : ~0ull;
+      own[e] = q / kTsChunk;
       pos[e] = q % kTsChunk;
     }
     for (int d = 0; d < nc; ++d) {
@@ -725,33 +739,27 @@ __global__ __launch_bounds__(1024) void k_tile_sort_merge(const uint64_t* __rest
 #pragma unroll
       for (int e = 0; e < E; ++e) lo[e] = 0;
       // entries of chunk d below x: the largest lo with s[base + lo - 1] < x
-      // (slots past the list's end and slots of chunk d itself skip the search)
       for (int step = kTsChunk; step > 0; step >>= 1) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          const int q = threadIdx.x + e * NTH;
-          if (q < n && q / kTsChunk != d) {
-            const int t = lo[e] + step;
-            if (t <= len && s[base + t - 1] < x[e]) lo[e] = t;
-          }
+          const int t = lo[e] + step;
+          if (own[e] != d && t <= len && s[base + t - 1] < x[e]) lo[e] = t;
         }
       }
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int q = threadIdx.x + e * NTH;
-        if (q / kTsChunk != d) pos[e] += lo[e];
-      }
+      for (int e = 0; e < E; ++e)
+        if (own[e] != d) pos[e] += lo[e];
     }
     uint32_t r[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int q = threadIdx.x + e * NTH;
-      r[e] = q < n ? vin[s0 + (uint32_t)x[e]] : 0u;
+      const int q = q0 + threadIdx.x + e * NTH;
+      r[e] = q < qe ? vin[s0 + (uint32_t)x[e]] : 0u;
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int q = threadIdx.x + e * NTH;
-      if (q < n) vout[s0 + pos[e]] = r[e];
+      const int q = q0 + threadIdx.x + e * NTH;
+      if (q < qe) vout[s0 + pos[e]] = r[e];
     }
     __syncthreads();
   }
@@ -869,8 +877,9 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
     S3R_LAUNCH(K_TILE_SORT_CHUNKS, k_tile_sort_chunks, dim3(kTsChunkBlocks), dim3(256), 0, st,
                parted, pvals, a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk,
                a.cap_dup);
-    S3R_LAUNCH(K_TILE_SORT_MERGE, k_tile_sort_merge, dim3(big), dim3(1024), 0, st, parted, pvals,
-               a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk, a.cap_dup);
+    S3R_LAUNCH(K_TILE_SORT_MERGE, k_tile_sort_merge, dim3(kTsMergeBlocks), dim3(1024), 0, st,
+               parted, pvals, a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk,
+               a.cap_dup);
     S3R_LAUNCH(K_TILE_SORT, k_tile_sort_tiny, dim3(a.total_tiles), dim3(kWave), 0, st, parted,
                pvals, a.vals_out, a.tile_start, a.tile_order, a.cap_dup);
   }

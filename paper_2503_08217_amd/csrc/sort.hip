@@ -493,11 +493,10 @@ __device__ __forceinline__ void net_step(uint64_t (&x)[E], int lane) {
     uint64_t y[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) y[e] = shfl_xor64(x[flip ? (E - 1 - e) : e], lmask);
+    // the lower lane keeps the smaller key, the upper the larger (keys are
+    // distinct but for the padding, where either choice is the same value)
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const bool take = lower ? (y[e] < x[e]) : (x[e] < y[e]);
-      x[e] = take ? y[e] : x[e];
-    }
+    for (int e = 0; e < E; ++e) x[e] = ((y[e] < x[e]) == lower) ? y[e] : x[e];
   }
 }
 
@@ -663,8 +662,7 @@ __global__ __launch_bounds__(256) void k_tile_sort_chunks(uint64_t* __restrict__
           const int p = base + lane * kTsE + e;
           const int q = (j == (k >> 1)) ? (p ^ (k - 1)) : (p ^ j);
           const uint64_t y = s[q];
-          const bool take = p < q ? (y < x[e]) : (x[e] < y);
-          x[e] = take ? y : x[e];
+          x[e] = ((y < x[e]) == (p < q)) ? y : x[e];
         }
         __syncthreads();
       }

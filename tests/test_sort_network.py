@@ -69,8 +69,9 @@ def wave_step(x, E, K, J):
         for lane in range(WAVE):
             low = (lane & hb) == 0
             for e in range(E):
-                take = (y[lane][e] < x[lane][e]) if low else (x[lane][e] < y[lane][e])
-                if take:
+                # lower lane keeps the smaller key, upper the larger (equal
+                # keys, the padding, give the same value either way)
+                if (y[lane][e] < x[lane][e]) == low:
                     x[lane][e] = y[lane][e]
 
 
@@ -137,8 +138,7 @@ def test_four_waves_with_steps_between_waves():
                             p = w * WK + lane * E + e
                             q = (p ^ (k - 1)) if j == (k >> 1) else (p ^ j)
                             y = flat[q]
-                            take = (y < waves[w][lane][e]) if p < q else (waves[w][lane][e] < y)
-                            if take:
+                            if (y < waves[w][lane][e]) == (p < q):
                                 waves[w][lane][e] = y
                 j >>= 1
             for w in range(4):

@@ -452,7 +452,6 @@ constexpr int kTsChunk = 2048;
 constexpr int kTsLarge = 16384;
 constexpr int kTsMaxChunks = kTsLarge / kTsChunk;
 constexpr int kTsChunkBlocks = 1024;
-constexpr int kTsLargeBlocks = 256;
 constexpr int kTsE = 8;                    // keys per lane of the small class
 constexpr int kTsWaveKeys = kWave * kTsE;  // 512: keys per wave
 
@@ -680,15 +679,44 @@ __global__ __launch_bounds__(256) void k_tile_sort_chunks(uint64_t* __restrict__
   }
 }
 
+// lists of kTsLarge entries or more: the same network on the keys in global
+// memory (rewritten in place as composite keys), by one workgroup
+__device__ void sort_list_global(uint64_t* __restrict__ keys, const uint32_t* __restrict__ vin,
+                                 uint32_t* __restrict__ vout, int64_t s0, int n) {
+  uint64_t* g = keys + s0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x)
+    g[q] = ((uint64_t)(uint32_t)g[q] << 32) | (uint32_t)q;
+  __syncthreads();
+  const int m = next_pow2(n);
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int q = threadIdx.x; q < (m >> 1); q += blockDim.x) {
+        const int a = cmp_lower(q, j);
+        const int b = (j == (k >> 1)) ? (a ^ (k - 1)) : (a + j);
+        if (b >= n) continue;  // the padded partner holds the largest key
+        const uint64_t x = g[a], y = g[b];
+        if (y < x) {
+          g[a] = y;
+          g[b] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int q = threadIdx.x; q < n; q += blockDim.x) vout[s0 + q] = vin[s0 + (uint32_t)g[q]];
+  __syncthreads();
+}
+
 // large lists: rank merge of their sorted chunks.  Work items are slices of
 // kTsMergeSlice entries of every large list, so the longest list is placed by
 // several workgroups at once; each stages the whole list in LDS and walks the
 // binary searches of its entries in step (fixed-step, branch-free lower
-// bounds), so their LDS reads overlap.
+// bounds), so their LDS reads overlap.  The first items are the huge lists,
+// one workgroup each (sort_list_global).
 constexpr int kTsMergeSlice = 2048;
 constexpr int kTsMergeBlocks = 512;
 
-__global__ __launch_bounds__(1024) void k_tile_sort_merge(const uint64_t* __restrict__ keys,
+__global__ __launch_bounds__(1024) void k_tile_sort_merge(uint64_t* __restrict__ keys,
                                                           const uint32_t* __restrict__ vin,
                                                           uint32_t* __restrict__ vout,
                                                           const int32_t* __restrict__ start,
@@ -700,12 +728,17 @@ __global__ __launch_bounds__(1024) void k_tile_sort_merge(const uint64_t* __rest
   __shared__ uint64_t s[kTsLarge];
   int lh, ll, lt;
   class_bounds(ocnt, nchunk, lh, ll, lt);
-  const int64_t n_items = (int64_t)SLICES * (ll - lh);
+  const int64_t n_items = lh + (int64_t)SLICES * (ll - lh);
   for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-    const int i = lh + (int)(item / SLICES);
-    const int q0 = (int)(item % SLICES) * kTsMergeSlice;
     int64_t s0;
     int n;
+    if (item < lh) {
+      list_of(start, order, (int)item, cap, s0, n);
+      sort_list_global(keys, vin, vout, s0, n);
+      continue;
+    }
+    const int i = lh + (int)((item - lh) / SLICES);
+    const int q0 = (int)((item - lh) % SLICES) * kTsMergeSlice;
     list_of(start, order, i, cap, s0, n);
     if (q0 >= n) continue;
     uint64_t v[EL];
@@ -763,44 +796,6 @@ __global__ __launch_bounds__(1024) void k_tile_sort_merge(const uint64_t* __rest
   }
 }
 
-// lists of kTsLarge entries or more: the same network on the keys in global memory
-// (rewritten in place as composite keys), one workgroup per list
-__global__ __launch_bounds__(1024) void k_tile_sort_huge(uint64_t* __restrict__ keys,
-                                                         const uint32_t* __restrict__ vin,
-                                                         uint32_t* __restrict__ vout,
-                                                         const int32_t* __restrict__ start,
-                                                         const int32_t* __restrict__ order,
-                                                         const int32_t* __restrict__ ocnt,
-                                                         int nchunk, int64_t cap) {
-  int lh, ll, lt;
-  class_bounds(ocnt, nchunk, lh, ll, lt);
-  for (int i = blockIdx.x; i < lh; i += gridDim.x) {
-    int64_t s0;
-    int n;
-    list_of(start, order, i, cap, s0, n);
-    uint64_t* g = keys + s0;
-    for (int q = threadIdx.x; q < n; q += 1024) g[q] = ((uint64_t)(uint32_t)g[q] << 32) | (uint32_t)q;
-    __syncthreads();
-    const int m = next_pow2(n);
-    for (int k = 2; k <= m; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int q = threadIdx.x; q < (m >> 1); q += 1024) {
-          const int a = cmp_lower(q, j);
-          const int b = (j == (k >> 1)) ? (a ^ (k - 1)) : (a + j);
-          if (b >= n) continue;  // the padded partner holds the largest key
-          const uint64_t x = g[a], y = g[b];
-          if (y < x) {
-            g[a] = y;
-            g[b] = x;
-          }
-        }
-        __syncthreads();
-      }
-    }
-    for (int q = threadIdx.x; q < n; q += 1024) vout[s0 + q] = vin[s0 + (uint32_t)g[q]];
-    __syncthreads();
-  }
-}
 
 int sort_passes(int total_tiles, bool by_tile) {
   int tb = 1;
@@ -869,9 +864,6 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
   // 5. depth order inside every list, written to the caller's value array
   if (a.by_tile) {
     const int nchunk = (a.total_tiles + kOrderChunk - 1) / kOrderChunk;
-    const int big = a.total_tiles < kTsLargeBlocks ? a.total_tiles : kTsLargeBlocks;
-    S3R_LAUNCH(K_TILE_SORT_HUGE, k_tile_sort_huge, dim3(big), dim3(1024), 0, st, parted, pvals,
-               a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk, a.cap_dup);
     S3R_LAUNCH(K_TILE_SORT_CHUNKS, k_tile_sort_chunks, dim3(kTsChunkBlocks), dim3(256), 0, st,
                parted, pvals, a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk,
                a.cap_dup);

@@ -278,9 +278,12 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
  * s3r_sort -- builds per-tile contributor lists ordered by (depth bits,
  * Gaussian index), the blending order of Eq. (2), bit-exactly: one (tile,
  * record) pair per tile a record covers, keyed (tile << 32 | depth bits) in
- * record order, then a stable radix sort on the key.  Reads the records of
- * s3r_project_cull (only scene->n is read from `scene`); `ws` holds
- * s3r_workspace_size(S3R_WS_SORT) bytes.
+ * record order, then a stable radix sort on the key -- or, with
+ * S3R_SORT_TILES, a stable radix partition on the tile bits followed by a
+ * per-list sort on (depth bits, position), which gives the same lists.  Also
+ * writes bins->rec_pair (each record's first pair) and the rasterizers'
+ * launch order.  Reads the records of s3r_project_cull (only scene->n is read
+ * from `scene`); `ws` holds s3r_workspace_size(S3R_WS_SORT) bytes.
  */
 int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* views,
              const S3RParams* params, S3RBins* bins, void* ws, size_t ws_bytes, void* stream);
@@ -306,7 +309,10 @@ int s3r_l1_loss(const S3RImage* img, const float* target, const S3RViews* views,
  * (chain of Eq. 1 and the SH colour), written to `g` (every per-Gaussian
  * entry; no caller-side zeroing).  The projection gradient is gathered per
  * Gaussian over the views of the batch, using `proj->surv` and `proj->bstat`
- * to find each Gaussian's records.  Pose gradients are chained through
+ * to find each Gaussian's records; the blending gradients of each (record,
+ * tile) pair go to the pair's own slot in `ws` (found from bins->rec_pair
+ * and the record's tile rectangle) and are summed per record, so no
+ * gradient atomics contend across tiles.  Pose gradients are chained through
  * W_{t,i} = W_t W_{t,i2g} and also given in 6-DoF form.  In the plain route
  * the world-frame gradients g->mean_w / g->rot_w (every slot of the batch)
  * are written instead of mean / quat; s3r_plain_transform_bwd finishes them.

@@ -845,17 +845,25 @@ __global__ __launch_bounds__(256) void k_plain_transform_bwd(
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-// zero the per-record gradient slots of the records that exist
+// zero the per-record gradient slots of the records that exist, and the two
+// small accumulators of the call (camera and pose gradients)
 __global__ __launch_bounds__(256) void k_zero_g2d(float4* __restrict__ g2d,
-                                                  const int32_t* __restrict__ counters) {
+                                                  const int32_t* __restrict__ counters,
+                                                  float* __restrict__ za, int64_t na,
+                                                  float* __restrict__ zb, int64_t nb) {
   const int64_t n = 3 * (int64_t)counters[S3R_CNT_SURV];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    g2d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = i0; i < n; i += stride) g2d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (za)
+    for (int64_t i = i0; i < na; i += stride) za[i] = 0.f;
+  if (zb)
+    for (int64_t i = i0; i < nb; i += stride) zb[i] = 0.f;
 }
 
 hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st) {
-  S3R_LAUNCH(K_ZERO_G2D, k_zero_g2d, dim3(1024), dim3(256), 0, st, a.g2d, a.counters);
+  S3R_LAUNCH(K_ZERO_G2D, k_zero_g2d, dim3(1024), dim3(256), 0, st, a.g2d, a.counters, a.zero_a,
+             a.n_zero_a, a.zero_b, a.n_zero_b);
   if (a.total_tiles <= 0) return hipGetLastError();
   switch (a.kp.tile) {
     case 8:

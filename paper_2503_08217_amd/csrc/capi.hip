@@ -242,10 +242,9 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
   const hipStream_t st = as_stream(stream);
   const int nblk = project_blocks(scene->n);
 
-  S3R_HIP(launch_zero(out->counters, 64, out->stats, (size_t)views->n_views * 16, nullptr, 0,
-                      nullptr, 0, st));
   S3R_HIP(launch_compose(views->W, views->tstep, scene->pose, scene->n_slots, scene->n_timesteps,
-                         views->n_views, out->cam, out->cen, out->t_norm, st));
+                         views->n_views, out->cam, out->cen, out->t_norm, out->counters,
+                         out->stats, st));
   ProjArgs a{};
   a.mean = scene->mean;
   a.scale = scene->scale;
@@ -469,14 +468,14 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
     // (Gaussians without records keep these zeros) and the accumulators
     const size_t N = (size_t)scene->n;
     const size_t B = (size_t)(scene->sh_degree + 1) * (scene->sh_degree + 1);
-    const bool dense = !sparse;
-    void* ps[7] = {w.d_cam, g->pose, dense ? g->scale : nullptr, dense ? g->opacity : nullptr,
-                   dense ? g->sh : nullptr, (plain || !dense) ? nullptr : g->mean,
-                   (plain || !dense) ? nullptr : g->quat};
-    const size_t bs[7] = {(size_t)views->n_views * scene->n_slots * 48,
-                          (size_t)scene->n_timesteps * scene->n_slots * 48, N * 12, N * 4,
-                          N * B * 12, N * 12, N * 16};
-    S3R_HIP(launch_zero_n(ps, bs, 7, st));
+    // (the camera and pose accumulators are cleared with the per-record
+    // gradient slots, inside launch_raster_bwd)
+    if (!sparse) {
+      void* ps[5] = {g->scale, g->opacity, g->sh, plain ? nullptr : g->mean,
+                     plain ? nullptr : g->quat};
+      const size_t bs[5] = {N * 12, N * 4, N * B * 12, N * 12, N * 16};
+      S3R_HIP(launch_zero_n(ps, bs, 5, st));
+    }
     if (sparse)
       S3R_HIP(launch_clear_rows(g->rows, g->n_rows, scene->n, (int)B, g->mean, g->scale, g->quat,
                                 g->opacity, g->sh, params->cap_surv, st));
@@ -503,6 +502,10 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   b.rec_rect = reinterpret_cast<const int4*>(proj->rec_rect);
   b.part = w.part;
   b.tile_cut = w.tile_cut;
+  b.zero_a = w.d_cam;
+  b.n_zero_a = (int64_t)views->n_views * scene->n_slots * 12;
+  b.zero_b = g->pose;
+  b.n_zero_b = (int64_t)scene->n_timesteps * scene->n_slots * 12;
   b.g2d = w.g2d;
   b.kp = kp;
   S3R_HIP(launch_raster_bwd(b, st));

@@ -111,6 +111,11 @@ struct BwdArgs {
   // rectangles: the slot of a (record, tile) pair in `part`
   const int32_t* rec_pair;
   const int4* rec_rect;
+  // small accumulators the g2d clear also zeroes (nullable)
+  float* zero_a;
+  int64_t n_zero_a;
+  float* zero_b;
+  int64_t n_zero_b;
   // per-pair 2D gradients (workspace, [cap_dup][12] floats), summed per
   // record into g2d ([cap_surv][12] floats, every record written)
   float4* part;
@@ -163,7 +168,8 @@ struct ProjBwdArgs {
 
 // project.hip
 hipError_t launch_compose(const float* W, const int32_t* tstep, const float* pose, int S, int T,
-                          int nv, float* cam, float* cen, float* t_norm, hipStream_t st);
+                          int nv, float* cam, float* cen, float* t_norm, int32_t* counters,
+                          int32_t* stats, hipStream_t st);
 hipError_t launch_plain_transform(const float* mean, const float* quat, const int32_t* inst,
                                   const float* pose, int n, int S, const int32_t* tsteps, int n_ts,
                                   float* mean_w, float* rot_w, hipStream_t st);

@@ -27,9 +27,13 @@ namespace s3r {
 __global__ void k_compose(const float* __restrict__ W, const int32_t* __restrict__ tstep,
                           const float* __restrict__ pose, int S, int T, int nv,
                           float* __restrict__ cam, float* __restrict__ cen,
-                          float* __restrict__ t_norm) {
+                          float* __restrict__ t_norm, int32_t* __restrict__ counters,
+                          int32_t* __restrict__ stats) {
   const int v = blockIdx.x;
   const int tau = clampi(tstep[v], 0, T - 1);
+  // the call's device counters and this view's statistics start at zero
+  if (threadIdx.x < 4) stats[4 * v + threadIdx.x] = 0;
+  if (v == 0 && threadIdx.x < 16) counters[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
     t_norm[v] = (T > 1) ? (float)(-1.0 + (2.0 * (double)tau) / (double)(T - 1)) : 0.0f;
   }
@@ -478,9 +482,10 @@ __global__ __launch_bounds__(kProjBlock) void k_records(ProjArgs a) {
 // host launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_compose(const float* W, const int32_t* tstep, const float* pose, int S, int T,
-                          int nv, float* cam, float* cen, float* t_norm, hipStream_t st) {
+                          int nv, float* cam, float* cen, float* t_norm, int32_t* counters,
+                          int32_t* stats, hipStream_t st) {
   S3R_LAUNCH(K_COMPOSE, k_compose, dim3(nv), dim3(128), 0, st, W, tstep, pose, S, T, nv, cam, cen,
-                     t_norm);
+             t_norm, counters, stats);
   return hipGetLastError();
 }
 

@@ -13,8 +13,10 @@
 // box meets its sub-tile.  A record's nine gradient components are summed
 // over the wave (permlane swaps pack four sums into one register, DPP row sums
 // finish) and added into an LDS slot shared by the tile's waves; the list is
-// walked in windows of twice the tile's pixel count of entries, each flushed with one set of global
-// atomics per record and tile.
+// walked in windows of twice the tile's pixel count of entries, and at each
+// window's end every entry stores its record's sums for this tile into the
+// (record, tile) pair's own slot.  k_pair_reduce then sums each record's
+// slots (no gradient atomics contend across the tiles a record covers).
 //
 // k_project_bwd chains those 2D gradients through the conic inverse, the EWA
 // covariance J R Sigma R^T J^T (Eq. 1), the quaternion/scale parameterisation,

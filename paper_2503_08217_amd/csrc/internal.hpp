@@ -10,7 +10,7 @@ namespace s3r {
 enum KernelId {
   K_COMPOSE, K_PLAIN_TRANSFORM, K_PROJECT, K_STATS, K_RECORDS, K_SCAN, K_EMIT, K_RADIX,
   K_TILE_RANGES, K_TILE_ORDER, K_TILE_SORT, K_TILE_SORT_CHUNKS, K_TILE_SORT_MERGE,
-  K_TILE_SORT_HUGE, K_RASTER_FWD, K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PAIR_REDUCE, K_PROJECT_BWD,
+  K_RASTER_FWD, K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PAIR_REDUCE, K_PROJECT_BWD,
   K_POSE_BWD, K_POSE6, K_PLAIN_TRANSFORM_BWD, K_VISIBILITY, K_ZERO, K_COUNT
 };
 void prof_begin(int id, hipStream_t st);

@@ -12,9 +12,10 @@
 //   k_off_*          an exclusive scan of the counts (chunk sums, one small
 //                    top scan, chunk rescans) gives the first record of every
 //                    (block, view)
-//   k_records        survivors (only, packed densely over the block's
-//                    threads) re-project, query their colour and write their
-//                    record at base + rank within the block
+//   k_records        one wave per Gaussian block: its survivors (only,
+//                    packed densely over the lanes) re-project, query their
+//                    colour and write their record at base + rank within the
+//                    block
 // Records come out ordered by Gaussian block, then view, then Gaussian.
 #include "internal.hpp"
 
@@ -382,17 +383,19 @@ __device__ __forceinline__ int select_bit(uint64_t x, int k) {
 }
 
 // The block's survivors of all views are processed densely: survivor k of
-// view v (in Gaussian order) is item prefix[v] + k of the block, and thread
-// t takes items t, t + 256, ...  (lanes are not tied to Gaussians: in a
-// batch of many views only a few per cent of the (Gaussian, view) pairs of a
-// block survive).
-__global__ __launch_bounds__(kProjBlock) void k_records(ProjArgs a) {
+// view v (in Gaussian order) is item prefix[v] + k of the block, and lane l
+// of the block's one wave takes items l, l + 64, ...  Lanes are not tied to
+// Gaussians: only a few per cent of a block's (Gaussian, view) pairs survive,
+// so a 256-thread workgroup would leave three of its four waves idle while
+// holding their slots.
+constexpr int kRecThreads = kWave;
+__global__ __launch_bounds__(kRecThreads) void k_records(ProjArgs a) {
   __shared__ uint64_t s_w[kMaxViews][kProjWaves];
   __shared__ int s_pre[kMaxViews + 1];
   const int tid = threadIdx.x;
   const int vb = blockIdx.x;
   const bool plain = (a.kp.flags & S3R_PLAIN) != 0;
-  for (int q = tid; q < a.nv * kProjWaves; q += kProjBlock) {
+  for (int q = tid; q < a.nv * kProjWaves; q += kRecThreads) {
     const int v = q / kProjWaves, w = q % kProjWaves;
     const int gw = vb * kProjWaves + w;
     uint64_t word = 0;
@@ -414,7 +417,7 @@ __global__ __launch_bounds__(kProjBlock) void k_records(ProjArgs a) {
   __syncthreads();
   const int total = s_pre[a.nv];
   const int B = (a.sh_deg + 1) * (a.sh_deg + 1);
-  for (int item = tid; item < total; item += kProjBlock) {
+  for (int item = tid; item < total; item += kRecThreads) {
     int v = 0;
     while (s_pre[v + 1] <= item) ++v;
     int k = item - s_pre[v];
@@ -519,7 +522,7 @@ hipError_t launch_project(const ProjArgs& a, int32_t* stats, hipStream_t st) {
   if (nchunk > 0)
     S3R_LAUNCH(K_STATS, k_off_down, dim3(nchunk), dim3(kOffThreads), 0, st, a.bstat, total,
                a.chunk_sum, a.kp.cap_surv);
-  if (a.nblk > 0) S3R_LAUNCH(K_RECORDS, k_records, dim3(a.nblk), dim3(kProjBlock), 0, st, a);
+  if (a.nblk > 0) S3R_LAUNCH(K_RECORDS, k_records, dim3(a.nblk), dim3(kRecThreads), 0, st, a);
   return hipGetLastError();
 }
 

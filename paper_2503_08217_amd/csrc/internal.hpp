@@ -213,7 +213,7 @@ struct SortArgs {
   uint32_t* vals_out;  // [cap_dup]: the sorted lists (S3RBins.vals)
   int32_t* hist;       // [256 * scan_blocks(cap_dup)]
   int32_t* scan_sums;
-  int32_t* misc;       // [0] total pairs, [1] histogram total
+  int32_t* misc;       // [0] total pairs, [1] histogram total, [2] histogram length
   int32_t* order_cnt;  // [order_count_words] per (bucket, chunk) tile counts
   int64_t cap_dup, cap_surv;
 };

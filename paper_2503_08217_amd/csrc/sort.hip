@@ -10,8 +10,9 @@
 //   2. k_emit_pairs: every thread writes a run of consecutive pairs (records
 //      covering thousands of tiles are spread over many threads)
 //   3. least-significant-digit radix passes, 8 bits each: block histograms ->
-//      scan of the digit-major histogram matrix -> stable scatter, where each
-//      wave ranks its keys by matching digits with eight ballots.  The passes
+//      scan of the digit-major histogram matrix (sized by the pair count on
+//      the device, not by the capacity) -> stable scatter, where each wave
+//      ranks its keys by matching digits with eight ballots.  The passes
 //      cover all key bits, or with S3R_SORT_TILES only the tile bits (a stable
 //      partition that leaves every list in emission order).
 //   4. tile ranges by binary search of the sorted keys; the tiles' launch
@@ -201,17 +202,23 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
   return eq;
 }
 
+// The histogram is digit-major over the blocks that hold keys (nb of them,
+// from the device-side key count), so the scan that follows covers 256 nb
+// counts however large the capacity; its length is left in *hist_len.
 __global__ __launch_bounds__(kRT) void k_radix_hist(const uint64_t* __restrict__ keys,
                                                     const int32_t* __restrict__ n_dev,
-                                                    int shift, int nblk,
-                                                    int32_t* __restrict__ hist) {
+                                                    int shift, int32_t* __restrict__ hist,
+                                                    int32_t* __restrict__ hist_len) {
   __shared__ uint32_t h[kRWaves][256];
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int64_t n = *n_dev;
+  const int nb = (int)((n + kRTile - 1) / kRTile);
+  if (blockIdx.x == 0 && tid == 0) *hist_len = 256 * nb;
+  if ((int)blockIdx.x >= nb) return;  // uniform over the workgroup
   for (int q = tid; q < kRWaves * 256; q += kRT) (&h[0][0])[q] = 0u;
   __syncthreads();
-  const int64_t n = *n_dev;
   const int64_t base = (int64_t)blockIdx.x * kRTile;
-  if (base < n) {
+  {
     for (int k = 0; k < kRI; ++k) {
       const int64_t idx = base + (int64_t)k * kRT + tid;
       const bool valid = idx < n;
@@ -223,7 +230,7 @@ __global__ __launch_bounds__(kRT) void k_radix_hist(const uint64_t* __restrict__
   __syncthreads();
   uint32_t s = 0;
   for (int w = 0; w < kRWaves; ++w) s += h[w][tid];
-  hist[(size_t)tid * nblk + blockIdx.x] = (int32_t)s;
+  hist[(size_t)tid * nb + blockIdx.x] = (int32_t)s;
 }
 
 __global__ __launch_bounds__(kRT) void k_radix_scatter(const uint64_t* __restrict__ kin,
@@ -231,12 +238,13 @@ __global__ __launch_bounds__(kRT) void k_radix_scatter(const uint64_t* __restric
                                                        uint64_t* __restrict__ kout,
                                                        uint32_t* __restrict__ vout,
                                                        const int32_t* __restrict__ n_dev,
-                                                       int shift, int nblk,
+                                                       int shift,
                                                        const int32_t* __restrict__ off) {
   __shared__ uint16_t cnt[kRI][kRWaves][256];
   __shared__ uint32_t s_base[256];
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   const int64_t n = *n_dev;
+  const int64_t nb = (n + kRTile - 1) / kRTile;
   const int64_t base = (int64_t)blockIdx.x * kRTile;
   if (base >= n) return;
   for (int q = tid; q < kRI * kRWaves * 256; q += kRT) (&cnt[0][0][0])[q] = 0;
@@ -267,7 +275,7 @@ __global__ __launch_bounds__(kRT) void k_radix_scatter(const uint64_t* __restric
         cnt[k][w][d] = (uint16_t)run;
         run += c;
       }
-    s_base[d] = (uint32_t)off[(size_t)d * nblk + blockIdx.x];
+    s_base[d] = (uint32_t)off[(size_t)d * nb + blockIdx.x];
   }
   __syncthreads();
 #pragma unroll
@@ -835,11 +843,11 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
     const int shift = shift0 + 8 * p;
     const int src = p & 1, dst = src ^ 1;
     S3R_LAUNCH(K_RADIX, k_radix_hist, dim3(nblk), dim3(kRT), 0, st, kb[src],
-               a.counters + S3R_CNT_DUP, shift, nblk, a.hist);
-    e = scan_i32(a.hist, nullptr, (int64_t)256 * nblk, a.hist, a.scan_sums, a.misc + 1, st);
+               a.counters + S3R_CNT_DUP, shift, a.hist, a.misc + 2);
+    e = scan_i32(a.hist, a.misc + 2, (int64_t)256 * nblk, a.hist, a.scan_sums, a.misc + 1, st);
     if (e != hipSuccess) return e;
     S3R_LAUNCH(K_RADIX, k_radix_scatter, dim3(nblk), dim3(kRT), 0, st, kb[src], vb[src], kb[dst],
-               vb[dst], a.counters + S3R_CNT_DUP, shift, nblk, a.hist);
+               vb[dst], a.counters + S3R_CNT_DUP, shift, a.hist);
   }
   uint64_t* parted = kb[passes & 1];
   const uint32_t* pvals = vb[passes & 1];

@@ -1,9 +1,13 @@
 // Front-to-back alpha blending of Eq. (2) over every tile of every view in
 // one launch.
 //
-// One workgroup per tile, one thread per pixel; each wave64 owns an 8x8
-// sub-tile of the 16x16 tile and walks the tile's sorted list independently
-// of the other waves (no LDS, no barriers).  A batch of 64 entries is fetched
+// One thread per pixel; each wave64 owns an 8x8 sub-tile of its tile and
+// walks the tile's sorted list independently of the other waves (no LDS, no
+// barriers), so every wave is a workgroup of its own: the sub-tiles of a tile
+// are consecutive workgroups, tiles in their launch order, and a wave slot
+// freed by a short sub-tile takes the next one at once (a workgroup of the
+// whole tile would wait for four free slots on one CU).  A batch of 64
+// entries is fetched
 // lane-parallel; entries whose cutoff box misses the sub-tile (no pixel there
 // could pass the Mahalanobis cut) are dropped with one ballot, and the rest
 // are broadcast from their lane into scalar registers and blended in list
@@ -14,10 +18,12 @@
 namespace s3r {
 
 template <int TS>
-__global__ __launch_bounds__(RasterShape<TS>::NT) void k_raster_fwd(RasterArgs a) {
-  const int tid = threadIdx.x;
-  const int lane = tid % kWave;
-  const int t = a.tile_order[blockIdx.x];
+__global__ __launch_bounds__(kWave)
+__attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a) {
+  constexpr int NW = RasterShape<TS>::NW;
+  const int lane = threadIdx.x;
+  const int tid = (int)(blockIdx.x % NW) * kWave + lane;  // pixel slot in the tile
+  const int t = a.tile_order[blockIdx.x / NW];
   const int v = find_view(a.tile_offset, a.nv, t);
   const int lt = t - a.tile_offset[v];
   const int W = a.wh[2 * v], H = a.wh[2 * v + 1];
@@ -128,18 +134,17 @@ hipError_t launch_raster_mask(const int32_t* rec_taken, const int32_t* rec_gid,
 
 hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st) {
   if (a.total_tiles <= 0) return hipSuccess;
+  // one wave64 workgroup per 8x8 sub-tile
+  const dim3 grid((unsigned)a.total_tiles * (unsigned)(a.kp.tile * a.kp.tile / kWave));
   switch (a.kp.tile) {
     case 8:
-      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<8>, dim3(a.total_tiles), dim3(RasterShape<8>::NT), 0,
-                 st, a);
+      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<8>, grid, dim3(kWave), 0, st, a);
       break;
     case 16:
-      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<16>, dim3(a.total_tiles), dim3(RasterShape<16>::NT),
-                 0, st, a);
+      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<16>, grid, dim3(kWave), 0, st, a);
       break;
     case 32:
-      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<32>, dim3(a.total_tiles), dim3(RasterShape<32>::NT),
-                 0, st, a);
+      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<32>, grid, dim3(kWave), 0, st, a);
       break;
     default:
       return hipErrorInvalidValue;

@@ -99,8 +99,9 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
   // windows the WIN-entry blocks [s + WIN k, s + WIN k + WIN); both are walked
   // back to front.  Inside a window every wave replays its batches (those
   // below its own end) and adds each record's wave total into the shared
-  // window slot, flushed with one set of global atomics.  Loads are pipelined:
-  // record ids two batches ahead, record fields one batch ahead.
+  // window slot, stored to the (record, tile) pair slots at the window's end.
+  // Loads are pipelined: record ids two batches ahead, record fields one
+  // batch ahead.
   constexpr int BPW = WIN / kWave;  // batches per window
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
   int mb = (int)((wave_end - s + kWave - 1) / kWave) - 1;  // next batch of this wave

@@ -16,6 +16,9 @@
 namespace s3r {
 
 constexpr int kWave = 64;
+// dies (XCDs) of the chip, each with its own L2; consecutive workgroup ids are
+// dealt to them round-robin
+constexpr int kXcds = 8;
 constexpr int kMaxViews = 64;
 
 // ---------------------------------------------------------------------------

@@ -3,11 +3,13 @@
 //
 // One thread per pixel; each wave64 owns an 8x8 sub-tile of its tile and
 // walks the tile's sorted list independently of the other waves (no LDS, no
-// barriers), so every wave is a workgroup of its own: the sub-tiles of a tile
-// are consecutive workgroups, tiles in their launch order, and a wave slot
-// freed by a short sub-tile takes the next one at once (a workgroup of the
-// whole tile would wait for four free slots on one CU).  A batch of 64
-// entries is fetched
+// barriers), so every wave is a workgroup of its own and a wave slot freed
+// by a short sub-tile takes the next one at once (a workgroup of the whole
+// tile would wait for four free slots on one CU).  Workgroups are dealt
+// round-robin to the chip's kXcds dies, each with its own L2; the sub-tiles
+// of a tile take workgroup ids congruent modulo kXcds, so they run on one die
+// and read the tile's records through one L2, and tiles start in their
+// launch order.  A batch of 64 entries is fetched
 // lane-parallel; entries whose cutoff box misses the sub-tile (no pixel there
 // could pass the Mahalanobis cut) are dropped with one ballot, and the rest
 // are broadcast from their lane into scalar registers and blended in list
@@ -21,9 +23,13 @@ template <int TS>
 __global__ __launch_bounds__(kWave)
 __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a) {
   constexpr int NW = RasterShape<TS>::NW;
+  // id = kXcds (NW q + w) + x  ->  tile rank kXcds q + x, sub-tile w
+  const int xcd = (int)(blockIdx.x % kXcds), k = (int)(blockIdx.x / kXcds);
+  const int rank = (k / NW) * kXcds + xcd;
+  if (rank >= a.total_tiles) return;  // padding of the last group of tiles
   const int lane = threadIdx.x;
-  const int tid = (int)(blockIdx.x % NW) * kWave + lane;  // pixel slot in the tile
-  const int t = a.tile_order[blockIdx.x / NW];
+  const int tid = (k % NW) * kWave + lane;  // pixel slot in the tile
+  const int t = a.tile_order[rank];
   const int v = find_view(a.tile_offset, a.nv, t);
   const int lt = t - a.tile_offset[v];
   const int W = a.wh[2 * v], H = a.wh[2 * v + 1];
@@ -134,8 +140,9 @@ hipError_t launch_raster_mask(const int32_t* rec_taken, const int32_t* rec_gid,
 
 hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st) {
   if (a.total_tiles <= 0) return hipSuccess;
-  // one wave64 workgroup per 8x8 sub-tile
-  const dim3 grid((unsigned)a.total_tiles * (unsigned)(a.kp.tile * a.kp.tile / kWave));
+  // one wave64 workgroup per 8x8 sub-tile, tiles padded to a multiple of kXcds
+  const unsigned groups = ((unsigned)a.total_tiles + kXcds - 1) / kXcds;
+  const dim3 grid(groups * kXcds * (unsigned)(a.kp.tile * a.kp.tile / kWave));
   switch (a.kp.tile) {
     case 8:
       S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<8>, grid, dim3(kWave), 0, st, a);

@@ -6,7 +6,8 @@
 // list by (depth bits, emission position) gives the order the oracle defines
 // -- (depth, Gaussian index) -- bit for bit.
 //
-//   1. exclusive scan of the pairs per record (reduce-then-scan)
+//   1. exclusive scan of the pairs per record (reduce-then-scan; up to 1024
+//      blocks, each block of the second pass adds up the block sums before it)
 //   2. k_emit_pairs: every thread writes a run of consecutive pairs (records
 //      covering thousands of tiles are spread over many threads)
 //   3. least-significant-digit radix passes, 8 bits each: block histograms ->
@@ -101,10 +102,15 @@ __global__ __launch_bounds__(1024) void k_scan_top(int32_t* __restrict__ sums, i
   if (tid == 1023) *total = (int32_t)run;
 }
 
+// kPrefix: sums[] holds the raw block sums and each block adds up those
+// before it itself (at most kScanFuseMax of them), in place of k_scan_top;
+// the last block then stores the total
+template <bool kPrefix>
 __global__ __launch_bounds__(kST) void k_scan_down(const int32_t* __restrict__ in,
                                                    const int32_t* n_dev, int64_t n_host,
                                                    const int32_t* __restrict__ sums,
-                                                   int32_t* __restrict__ out) {
+                                                   int32_t* __restrict__ out,
+                                                   int32_t* __restrict__ total) {
   const int64_t n = dev_n(n_dev, n_host);
   const int64_t base = (int64_t)blockIdx.x * kSTile + (int64_t)threadIdx.x * kSI;
   uint32_t v[kSI], s = 0;
@@ -113,9 +119,20 @@ __global__ __launch_bounds__(kST) void k_scan_down(const int32_t* __restrict__ i
     v[q] = (base + q < n) ? (uint32_t)in[base + q] : 0u;
     s += v[q];
   }
+  uint32_t before;
+  if (kPrefix) {
+    uint32_t p = 0;
+    for (int q = threadIdx.x; q < (int)blockIdx.x; q += kST) p += (uint32_t)sums[q];
+    uint32_t unused;
+    before = block_excl_scan(p, unused);
+  } else {
+    before = (uint32_t)sums[blockIdx.x];
+  }
   uint32_t excl;
-  block_excl_scan(s, excl);
-  uint32_t run = (uint32_t)sums[blockIdx.x] + excl;
+  const uint32_t mine = block_excl_scan(s, excl);
+  if (kPrefix && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+    *total = (int32_t)(before + mine);
+  uint32_t run = before + excl;
 #pragma unroll
   for (int q = 0; q < kSI; ++q) {
     if (base + q < n) out[base + q] = (int32_t)run;
@@ -123,12 +140,22 @@ __global__ __launch_bounds__(kST) void k_scan_down(const int32_t* __restrict__ i
   }
 }
 
+// up to this many blocks, each block of the down sweep sums the block sums
+// before it (a few KB from L2) instead of a third launch scanning them
+constexpr int kScanFuseMax = 1024;
+
 static hipError_t scan_i32(const int32_t* in, const int32_t* n_dev, int64_t n_cap, int32_t* out,
                            int32_t* sums, int32_t* total, hipStream_t st) {
   const int nb = scan_blocks(n_cap) > 0 ? scan_blocks(n_cap) : 1;
   S3R_LAUNCH(K_SCAN, k_scan_reduce, dim3(nb), dim3(kST), 0, st, in, n_dev, n_cap, sums);
-  S3R_LAUNCH(K_SCAN, k_scan_top, dim3(1), dim3(1024), 0, st, sums, nb, total);
-  S3R_LAUNCH(K_SCAN, k_scan_down, dim3(nb), dim3(kST), 0, st, in, n_dev, n_cap, sums, out);
+  if (nb <= kScanFuseMax) {
+    S3R_LAUNCH(K_SCAN, k_scan_down<true>, dim3(nb), dim3(kST), 0, st, in, n_dev, n_cap, sums, out,
+               total);
+  } else {
+    S3R_LAUNCH(K_SCAN, k_scan_top, dim3(1), dim3(1024), 0, st, sums, nb, total);
+    S3R_LAUNCH(K_SCAN, k_scan_down<false>, dim3(nb), dim3(kST), 0, st, in, n_dev, n_cap, sums,
+               out, nullptr);
+  }
   return hipGetLastError();
 }
 

@@ -265,3 +265,24 @@ def test_rendering_visibility_parity(which):
         sure = ~unc
         np.testing.assert_array_equal(gpu[v][sure], took[sure], err_msg=f"view {v}")
         assert took.sum() > 0
+
+
+def test_scan_paths_agree():
+    """The pair-offset scan takes two launches up to 1024 blocks of 4096
+    records and three beyond; a record capacity of 4.4M (1075 blocks) gives
+    the same first pairs, lists and image as the default capacity."""
+    cfg = scenes.make_config(1)
+    banner("scan paths")
+    out = []
+    for cap in (None, 4_400_000):
+        r = make_renderer(cfg.scene, cfg.views, cfg.params, cap_surv=cap, cap_dup=1_000_000)
+        r.forward()
+        c = r.read_counters()
+        n, nd = c["n_surv"], int(r.counters.cpu().numpy()[2])
+        out.append((r.rec_pair[:n].cpu().numpy().copy(), r.tile_start.cpu().numpy().copy(),
+                    r.vals.cpu().numpy()[:nd].copy(),
+                    np.stack([image_np(r, v) for v in range(r.V)])))
+    first = out[0][0]
+    assert first[0] == 0 and np.all(np.diff(first) >= 0) and first[-1] < out[0][2].shape[0]
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)

@@ -252,11 +252,10 @@ __global__ __launch_bounds__(kProjBlock) void k_cull(ProjArgs a) {
 
 // Exclusive scan of the per-(block, view) survivor counts in (block, view)
 // order -> first record of each (block, view); totals -> counters and stats.
-// One workgroup of 1024 threads, each owning a contiguous run of entries.
-// Phase B: first record of every (block, view) -- an exclusive scan of the
-// record counts in (block, view) order, over chunks of kOffChunk entries:
-// chunk sums (and per-view partial stats), a one-workgroup scan of the chunk
-// sums, then each chunk rescanned with its offset.  No contended atomics.
+// Over chunks of kOffChunk entries: chunk sums (and per-view partial stats),
+// then each chunk rescanned with its offset, the sum of the chunk sums before
+// it -- added up by the chunk itself when there are at most kOffFuseMax
+// chunks, else scanned by one workgroup in between.  No contended atomics.
 constexpr int kOffChunk = 1024;
 constexpr int kOffThreads = 256;
 constexpr int kOffPer = kOffChunk / kOffThreads;
@@ -337,13 +336,40 @@ __global__ __launch_bounds__(1024) void k_off_top(int32_t* __restrict__ csum, in
   }
 }
 
+// kPrefix (at most kOffFuseMax chunks): in place of k_off_top, each chunk
+// adds up the chunk sums before it, the chunks share out the per-view
+// statistics, and the last chunk stores the survivor counters
+constexpr int kOffFuseMax = 1024;
+
+template <bool kPrefix>
 __global__ __launch_bounds__(kOffThreads) void k_off_down(int32_t* __restrict__ bstat,
                                                          int64_t total,
                                                          const int32_t* __restrict__ csum,
-                                                         int64_t cap_surv) {
+                                                         int64_t cap_surv, int nchunk, int nv,
+                                                         const int32_t* __restrict__ cstat,
+                                                         int32_t* __restrict__ counters,
+                                                         int32_t* __restrict__ stats) {
   __shared__ int s_w[kOffThreads / kWave];
   const int tid = threadIdx.x;
   const int64_t c = blockIdx.x;
+  int before;
+  if (kPrefix) {
+    int p = 0;
+    for (int q = tid; q < (int)c; q += kOffThreads) p += csum[q];
+    (void)block_exclusive_scan(p, s_w, before);
+    // statistic q of the views (3 per view) is summed over the chunks by
+    // chunk q mod nchunk
+    for (int q = (int)c; q < nv * 3; q += nchunk) {
+      int acc = 0;
+      for (int k = tid; k < nchunk; k += kOffThreads)
+        acc += cstat[((int64_t)k * nv + q / 3) * 3 + q % 3];
+      int all;
+      (void)block_exclusive_scan(acc, s_w, all);
+      if (tid == 0) stats[(q / 3) * 4 + (q % 3)] = all;
+    }
+  } else {
+    before = csum[c];
+  }
   // thread t takes the kOffPer consecutive entries c*kOffChunk + t*kOffPer + m
   int cnt[kOffPer];
   int sum = 0;
@@ -354,7 +380,12 @@ __global__ __launch_bounds__(kOffThreads) void k_off_down(int32_t* __restrict__ 
     sum += cnt[m];
   }
   int tot;
-  int64_t run = (int64_t)csum[c] + block_exclusive_scan(sum, s_w, tot);
+  int64_t run = (int64_t)before + block_exclusive_scan(sum, s_w, tot);
+  if (kPrefix && c == (int64_t)gridDim.x - 1 && tid == 0) {
+    const int64_t all = (int64_t)before + tot;
+    counters[S3R_CNT_SURV] = (int32_t)min(all, cap_surv);
+    counters[S3R_CNT_OVF_SURV] = (int32_t)max((int64_t)0, all - cap_surv);
+  }
 #pragma unroll
   for (int m = 0; m < kOffPer; ++m) {
     const int64_t e = c * kOffChunk + (int64_t)tid * kOffPer + m;
@@ -517,11 +548,16 @@ hipError_t launch_project(const ProjArgs& a, int32_t* stats, hipStream_t st) {
   if (nchunk > 0)
     S3R_LAUNCH(K_STATS, k_off_reduce, dim3(nchunk), dim3(kOffThreads), 0, st, a.bstat, total, a.nv,
                a.chunk_sum, a.chunk_stat);
-  S3R_LAUNCH(K_STATS, k_off_top, dim3(1), dim3(1024), 0, st, a.chunk_sum, nchunk, a.nv,
-             a.chunk_stat, a.counters, stats, a.kp.cap_surv);
-  if (nchunk > 0)
-    S3R_LAUNCH(K_STATS, k_off_down, dim3(nchunk), dim3(kOffThreads), 0, st, a.bstat, total,
-               a.chunk_sum, a.kp.cap_surv);
+  if (nchunk > 0 && nchunk <= kOffFuseMax) {
+    // counters and statistics start at zero (k_compose), so no chunks, no launch
+    S3R_LAUNCH(K_STATS, k_off_down<true>, dim3(nchunk), dim3(kOffThreads), 0, st, a.bstat, total,
+               a.chunk_sum, a.kp.cap_surv, nchunk, a.nv, a.chunk_stat, a.counters, stats);
+  } else if (nchunk > 0) {
+    S3R_LAUNCH(K_STATS, k_off_top, dim3(1), dim3(1024), 0, st, a.chunk_sum, nchunk, a.nv,
+               a.chunk_stat, a.counters, stats, a.kp.cap_surv);
+    S3R_LAUNCH(K_STATS, k_off_down<false>, dim3(nchunk), dim3(kOffThreads), 0, st, a.bstat, total,
+               a.chunk_sum, a.kp.cap_surv, nchunk, a.nv, a.chunk_stat, a.counters, stats);
+  }
   if (a.nblk > 0) S3R_LAUNCH(K_RECORDS, k_records, dim3(a.nblk), dim3(kRecThreads), 0, st, a);
   return hipGetLastError();
 }

@@ -61,10 +61,13 @@ PCS_KERNELS = ("compose", "project", "block_offsets", "records", "scan", "emit_p
 
 
 def sources_digest(kernel):
+    """Digest of the kernel's source files and the compiler flags."""
+    from paper_2503_08217_amd.build import FLAGS
     h = hashlib.sha256()
     for f in KERNEL_SOURCES.get(kernel, ()):
         with open(os.path.join(ROOT, "paper_2503_08217_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(FLAGS).encode())
     return h.hexdigest()[:16]
 
 

@@ -29,6 +29,11 @@ FLAGS = [
     "-munsafe-fp-atomics",
     # no packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # an atomic at a wave-uniform address stays one instruction: no kernel
+    # here has contended uniform-address atomics, and the optimizer's per-lane
+    # combining loop cost the raster backward's LDS slot update a dozen
+    # instructions per blended entry
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
 ]
 
 

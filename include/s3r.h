@@ -114,7 +114,7 @@ typedef struct S3RParams {
   float lod_r;        /* LOD threshold r in pixels (Sec. 3.3, "Adaptive LOD") */
   float z_near, z_far;
   float eps2d;        /* low-pass added to the 2D covariance (px^2)         */
-  float alpha_min, alpha_max, t_min;
+  float alpha_min, alpha_max, t_min; /* skip (> 0), clamp (in (0, 1)), stop (> 0) */
   float cutoff;       /* skip where the Mahalanobis power is below -cutoff  */
   float jac_clamp;    /* EWA Jacobian clamp, multiple of the half FOV tangent */
   float bg[3];        /* background colour                                  */

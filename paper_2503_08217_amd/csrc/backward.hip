@@ -139,11 +139,12 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
         m &= ~(1ull << j);
         const float u = bcast(g.x, j), vv = bcast(g.y, j), o = bcast(g.z, j);
         const float A = bcast(c.x, j), B = bcast(c.y, j), C = bcast(c.z, j);
-        const float kr = bcast(col.x, j), kg = bcast(col.y, j), kb = bcast(col.z, j);
         const int pos = (int)(b0 - s) + j;
         const Blend bl = blend_eval(u, vv, A, B, C, o, fxp, fyp, a.kp);
         const bool contrib = bl.hit && (pos < last);
         if (ballot(contrib) == 0ull) continue;
+        // (the colour is broadcast only for entries some pixel of the wave takes)
+        const float kr = bcast(col.x, j), kg = bcast(col.y, j), kb = bcast(col.z, j);
         const float one_m = 1.0f - bl.alpha;
         const float rinv = __builtin_amdgcn_rcpf(one_m);  // one_m >= 1 - alpha_max
         const float Tb = T * rinv;

@@ -121,7 +121,9 @@ int check_params(const S3RParams* p) {
   if (p->tile != 8 && p->tile != 16 && p->tile != 32) return S3R_E_SIZE;
   if (p->cap_surv <= 0 || p->cap_surv >= (int64_t(1) << 31)) return S3R_E_SIZE;
   if (p->cap_dup <= 0 || p->cap_dup >= (int64_t(1) << 31)) return S3R_E_SIZE;
-  if (!(p->alpha_max > 0.f) || !(p->alpha_max < 1.f) || !(p->t_min > 0.f)) return S3R_E_ARG;
+  if (!(p->alpha_min > 0.f) || !(p->alpha_max > 0.f) || !(p->alpha_max < 1.f) ||
+      !(p->t_min > 0.f))
+    return S3R_E_ARG;
   if ((p->flags & S3R_LOD_STOCHASTIC) && !(p->lod_D > 0.f)) return S3R_E_ARG;
   return S3R_OK;
 }

@@ -344,7 +344,11 @@ __device__ __forceinline__ Blend blend_eval(float u, float v, float A, float Bc,
   b.power = fmaf(-0.5f, fmaf(A * dx, dx, C * dy * dy), -Bc * dx * dy);
   b.ex = __expf(b.power);
   b.raw = o * b.ex;
-  b.alpha = fminf(kp.alpha_max, b.raw);
+  // min(alpha_max, raw) as one v_med3 clamp to [0, alpha_max]: raw is finite
+  // (the power of a positive-definite conic exceeds zero by at most a
+  // rounding error), equal to the minimum for raw >= 0, and for raw < 0 (a
+  // negative opacity) both fall below alpha_min, so no pixel takes the entry
+  b.alpha = __builtin_amdgcn_fmed3f(b.raw, 0.0f, kp.alpha_max);
   b.hit = !(-b.power > kp.cutoff) && !(b.alpha < kp.alpha_min);
   return b;
 }

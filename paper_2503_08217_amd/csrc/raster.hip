@@ -81,9 +81,10 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a) {
       m &= m - 1ull;
       const float u = bcast(g.x, j), vv = bcast(g.y, j), o = bcast(g.z, j);
       const float A = bcast(c.x, j), B = bcast(c.y, j), C = bcast(c.z, j);
-      const float kr = bcast(col.x, j), kg = bcast(col.y, j), kb = bcast(col.z, j);
       const Blend bl = blend_eval(u, vv, A, B, C, o, fxp, fyp, a.kp);
       const bool hit = bl.hit && !done;
+      if (ballot(hit) == 0ull) continue;  // no pixel of the wave takes it
+      const float kr = bcast(col.x, j), kg = bcast(col.y, j), kb = bcast(col.z, j);
       const float Tn = T * (1.0f - bl.alpha);
       const bool stop = Tn < a.kp.t_min;  // this entry would push T under the floor
       const bool take = hit && !stop;

@@ -103,9 +103,10 @@ enum {
   S3R_CNT_OVF_SURV = 1, /* survivors dropped for lack of capacity        */
   S3R_CNT_DUP = 2,      /* number of (tile, record) pairs                 */
   S3R_CNT_OVF_DUP = 3,  /* pairs dropped for lack of capacity             */
-  S3R_CNT_SPIN = 4,     /* nonzero if a bounded wait gave up (never expected) */
-  S3R_CNT_TICKET = 5,   /* internal: project workgroup tickets             */
-  S3R_CNT_TICKET2 = 6   /* internal: scan workgroup tickets                */
+  S3R_CNT_SPIN = 4,     /* reserved, always 0: no kernel waits on another
+                           workgroup                                        */
+  S3R_CNT_TICKET = 5,   /* reserved                                        */
+  S3R_CNT_TICKET2 = 6   /* reserved                                        */
 };
 
 typedef struct S3RParams {

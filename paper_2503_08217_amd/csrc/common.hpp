@@ -428,48 +428,4 @@ __device__ __forceinline__ int find_view(const int32_t* __restrict__ tile_offset
   return v;
 }
 
-__device__ __forceinline__ uint64_t ld_acquire(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_release(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Decoupled look-back (single-pass exclusive scan across workgroups).
-// Called by one full wave; `flags` holds (status << 32 | value) per virtual
-// block: status 1 = aggregate of that block, 2 = inclusive prefix.  Returns
-// the exclusive prefix of block `vb`.  Predecessors take their ticket before
-// this block does, so they are resident and publish without waiting on
-// anything; the wait is still bounded, and gives up (flagging `spin_err`) so
-// that every wave always exits.
-constexpr uint32_t kSpinLimit = 1u << 20;
-
-__device__ __forceinline__ uint32_t lookback(uint64_t* flags, int vb, int32_t* spin_err) {
-  const int lane = lane_id();
-  uint32_t excl = 0;
-  int base = vb - 1;
-  uint32_t spins = 0;
-  while (base >= 0) {
-    int j = base - lane;
-    uint64_t f = (j >= 0) ? ld_acquire(flags + j) : (2ull << 32);
-    uint32_t st = (uint32_t)(f >> 32);
-    uint64_t zero = ballot(st == 0u);
-    uint64_t incl = ballot(st == 2u);
-    int first = incl ? (__ffsll((unsigned long long)incl) - 1) : 64;
-    uint64_t need = (first >= 63) ? ~0ull : ((1ull << (first + 1)) - 1ull);
-    if ((zero & need) != 0ull) {
-      if (++spins < kSpinLimit) {
-        __builtin_amdgcn_s_sleep(1);
-        continue;
-      }
-      if (lane == 0) atomicExch(spin_err, 1);
-    }
-    uint32_t val = (lane <= first && st != 0u) ? (uint32_t)f : 0u;
-    excl += wave_sum_u32(val);
-    if (first < 64) break;
-    base -= kWave;
-  }
-  return excl;
-}
-
 }  // namespace s3r

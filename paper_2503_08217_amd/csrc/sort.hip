@@ -16,8 +16,8 @@
 //      ranks its keys by matching digits with eight ballots.  The passes
 //      cover all key bits, or with S3R_SORT_TILES only the tile bits (a stable
 //      partition that leaves every list in emission order).
-//   4. tile ranges by binary search of the sorted keys; the tiles' launch
-//      order (descending list length)
+//   4. tile ranges from where the tile changes between neighbouring keys; the
+//      tiles' launch order (descending list length)
 //   5. with S3R_SORT_TILES, k_tile_sort_*: each list sorted by (depth bits,
 //      position) with bitonic networks in LDS (long lists in chunks merged by
 //      rank; lists too long for LDS in place in global memory)
@@ -320,28 +320,21 @@ __global__ __launch_bounds__(kRT) void k_radix_scatter(const uint64_t* __restric
 // ---------------------------------------------------------------------------
 // tile ranges and per-view pair counts
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t lower_bound_tile(const uint64_t* keys, int64_t n, uint32_t t) {
-  int64_t lo = 0, hi = n;
-  const uint64_t k = (uint64_t)t << 32;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (keys[mid] < k) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
+// List ranges from the partitioned keys in one streaming pass: key i opens
+// the lists of the tiles t in (tile(i - 1), tile(i)] at position i, with
+// tile(-1) = -1 and tile(n) = total_tiles, so every start[t], t <= total_tiles,
+// is written exactly once.  The lengths (start differences) are written by
+// k_order_count, which reads them anyway.
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict__ keys,
                                                      const int32_t* __restrict__ n_dev,
                                                      int total_tiles,
-                                                     int32_t* __restrict__ start,
-                                                     int32_t* __restrict__ count) {
+                                                     int32_t* __restrict__ start) {
   const int64_t n = *n_dev;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t <= total_tiles;
-       t += gridDim.x * blockDim.x) {
-    const int64_t s = lower_bound_tile(keys, n, (uint32_t)t);
-    start[t] = (int32_t)s;
-    if (t < total_tiles) count[t] = (int32_t)(lower_bound_tile(keys, n, (uint32_t)t + 1u) - s);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int lo = i == 0 ? -1 : (int)(keys[i - 1] >> 32);
+    const int hi = i == n ? total_tiles : min((int)(keys[i] >> 32), total_tiles);
+    for (int t = lo + 1; t <= hi; ++t) start[t] = (int32_t)i;
   }
 }
 
@@ -364,14 +357,18 @@ __device__ __forceinline__ int order_bucket(const int32_t* start, int t) {
 
 __global__ __launch_bounds__(kOrderThreads) void k_order_count(const int32_t* __restrict__ start,
                                                               int total_tiles, int nchunk,
-                                                              int32_t* __restrict__ cnt) {
+                                                              int32_t* __restrict__ cnt,
+                                                              int32_t* __restrict__ len) {
   __shared__ int s_c[kOrderBuckets];
   const int tid = threadIdx.x, c = blockIdx.x;
   if (tid < kOrderBuckets) s_c[tid] = 0;
   __syncthreads();
   for (int m = 0; m < kOrderPer; ++m) {
     const int t = c * kOrderChunk + m * kOrderThreads + tid;
-    if (t < total_tiles) atomicAdd(&s_c[order_bucket(start, t)], 1);
+    if (t < total_tiles) {
+      len[t] = start[t + 1] - start[t];
+      atomicAdd(&s_c[order_bucket(start, t)], 1);
+    }
   }
   __syncthreads();
   if (tid < kOrderBuckets) cnt[tid * nchunk + c] = s_c[tid];  // bucket-major
@@ -880,16 +877,16 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
   const uint32_t* pvals = vb[passes & 1];
   // 4. tile ranges and the launch order
   {
-    const int want = (a.total_tiles + 1 + 255) / 256;
-    const int grid = want < 1024 ? want : 1024;
+    const int64_t want = (a.cap_dup + 1 + 255) / 256;
+    const int grid = (int)(want < 1024 ? want : 1024);
     S3R_LAUNCH(K_TILE_RANGES, k_tile_ranges, dim3(grid), dim3(256), 0, st, parted,
-               a.counters + S3R_CNT_DUP, a.total_tiles, a.tile_start, a.tile_count);
+               a.counters + S3R_CNT_DUP, a.total_tiles, a.tile_start);
   }
   {
     const int nchunk = (a.total_tiles + kOrderChunk - 1) / kOrderChunk;
     if (nchunk > 0)
       S3R_LAUNCH(K_TILE_ORDER, k_order_count, dim3(nchunk), dim3(kOrderThreads), 0, st,
-                 a.tile_start, a.total_tiles, nchunk, a.order_cnt);
+                 a.tile_start, a.total_tiles, nchunk, a.order_cnt, a.tile_count);
     S3R_LAUNCH(K_TILE_ORDER, k_order_top, dim3(1), dim3(1024), 0, st, a.order_cnt,
                kOrderBuckets * nchunk, a.tile_start, a.tile_offset, a.nv, a.stats);
     if (nchunk > 0)

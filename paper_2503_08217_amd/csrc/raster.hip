@@ -167,11 +167,15 @@ hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st) {
 // changes rarely; per-thread sums are reduced over the wave when its lanes
 // share a view, then per workgroup, and a workgroup adds one value per view it
 // touched to the loss (few same-address atomics: they serialise).
+// 1024 threads per workgroup: the ~512 workgroups of a 1080p view then fill
+// every wave slot of the chip, with one 4-pixel group per thread
+constexpr int kL1Threads = 1024;
+
 __device__ __forceinline__ float l1_sign(float d, float inv) {
   return d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
 }
 
-__global__ __launch_bounds__(256) void k_l1(const float* __restrict__ color,
+__global__ __launch_bounds__(kL1Threads) void k_l1(const float* __restrict__ color,
                                             const float* __restrict__ target,
                                             const int64_t* __restrict__ pxo,
                                             const int32_t* __restrict__ wh, int nv, int64_t total,
@@ -246,11 +250,11 @@ hipError_t launch_l1_loss(const float* color, const float* target, const int64_t
   hipError_t e = launch_zero(loss, (size_t)nv * 4, nullptr, 0, nullptr, 0, nullptr, 0, st);
   if (e != hipSuccess) return e;
   if (total_px <= 0) return hipGetLastError();
-  // about 512 workgroups of 256 threads, each over a contiguous range (a
-  // multiple of 1024 pixels, so 4-pixel groups never straddle chunks)
+  // about 512 workgroups of kL1Threads threads, each over a contiguous range
+  // (a multiple of 1024 pixels, so 4-pixel groups never straddle chunks)
   const int64_t chunk = max((int64_t)256 * 8, ((total_px + 511) / 512 + 1023) / 1024 * 1024);
   const int64_t grid = (total_px + chunk - 1) / chunk;
-  S3R_LAUNCH(K_L1, k_l1, dim3((unsigned)grid), dim3(256), 0, st, color, target, px_offset, wh, nv,
+  S3R_LAUNCH(K_L1, k_l1, dim3((unsigned)grid), dim3(kL1Threads), 0, st, color, target, px_offset, wh, nv,
              total_px, chunk, loss, d_color);
   return hipGetLastError();
 }

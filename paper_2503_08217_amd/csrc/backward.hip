@@ -918,6 +918,11 @@ __global__ __launch_bounds__(256) void k_zero_plain_w(const int32_t* __restrict_
 
 // Sparse gradient mode: clear the rows the previous call wrote, and record
 // the Gaussians whose rows this call writes (its records' Gaussians).
+// kClearLanes consecutive lanes clear one listed row: its SH coefficients
+// as contiguous 16-byte stores (whole cache lines), and one lane each its
+// mean, scale, quaternion and opacity
+constexpr int kClearLanes = 16;
+
 __global__ __launch_bounds__(256) void k_clear_rows(const int32_t* __restrict__ rows,
                                                     const int32_t* __restrict__ n_rows, int64_t n,
                                                     int B, float* __restrict__ mean,
@@ -925,24 +930,27 @@ __global__ __launch_bounds__(256) void k_clear_rows(const int32_t* __restrict__ 
                                                     float* __restrict__ quat,
                                                     float* __restrict__ opac,
                                                     float* __restrict__ sh) {
-  const int cnt = *n_rows;
-  const int stride = gridDim.x * blockDim.x;
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += stride) {
-    const int i = rows[j];
+  const int64_t cnt = *n_rows;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < cnt * kClearLanes;
+       q += stride) {
+    const int i = rows[q / kClearLanes];
+    const int sub = (int)(q % kClearLanes);
     if (i < 0 || i >= n) continue;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      mean[3 * (size_t)i + c] = 0.f;
-      scale[3 * (size_t)i + c] = 0.f;
-    }
-    reinterpret_cast<float4*>(quat)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    opac[i] = 0.f;
     float* s = sh + (size_t)i * 3 * B;
     if (((3 * B) & 3) == 0) {
       float4* s4 = reinterpret_cast<float4*>(s);
-      for (int t = 0; t < (3 * B) / 4; ++t) s4[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int t = sub; t < (3 * B) / 4; t += kClearLanes) s4[t] = make_float4(0.f, 0.f, 0.f, 0.f);
     } else {
-      for (int t = 0; t < 3 * B; ++t) s[t] = 0.f;
+      for (int t = sub; t < 3 * B; t += kClearLanes) s[t] = 0.f;
+    }
+    if (sub < 3) {
+      mean[3 * (size_t)i + sub] = 0.f;
+      scale[3 * (size_t)i + sub] = 0.f;
+    } else if (sub == 3) {
+      reinterpret_cast<float4*>(quat)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else if (sub == 4) {
+      opac[i] = 0.f;
     }
   }
 }
@@ -950,7 +958,7 @@ __global__ __launch_bounds__(256) void k_clear_rows(const int32_t* __restrict__ 
 hipError_t launch_clear_rows(const int32_t* rows, const int32_t* n_rows, int64_t n, int B,
                              float* mean, float* scale, float* quat, float* opac, float* sh,
                              int64_t cap, hipStream_t st) {
-  const int64_t want = (cap + 255) / 256;
+  const int64_t want = (cap * kClearLanes + 255) / 256;
   const int grid = (int)(want < 2048 ? (want > 0 ? want : 1) : 2048);
   S3R_LAUNCH(K_ZERO, k_clear_rows, dim3(grid), dim3(256), 0, st, rows, n_rows, n, B, mean, scale,
              quat, opac, sh);

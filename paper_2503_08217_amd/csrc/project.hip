@@ -420,7 +420,9 @@ __device__ __forceinline__ int select_bit(uint64_t x, int k) {
 // so a 256-thread workgroup would leave three of its four waves idle while
 // holding their slots.
 constexpr int kRecThreads = kWave;
-__global__ __launch_bounds__(kRecThreads) void k_records(ProjArgs a) {
+// (at most 128 VGPRs, no spills: four waves per SIMD)
+__global__ __launch_bounds__(kRecThreads)
+__attribute__((amdgpu_waves_per_eu(4))) void k_records(ProjArgs a) {
   __shared__ uint64_t s_w[kMaxViews][kProjWaves];
   __shared__ int s_pre[kMaxViews + 1];
   const int tid = threadIdx.x;
@@ -469,6 +471,14 @@ __global__ __launch_bounds__(kRecThreads) void k_records(ProjArgs a) {
     Proj o;
     project_canonical(P, e.mx, e.my, e.mz, e.R, e.s0, e.s1, e.s2, fx, fy, cx, cy, W, H, a.kp, o,
                       i, v);
+    // the geometric part of the record is stored before the colour is
+    // evaluated, so its registers are free for the SH coefficients
+    a.rec_gid[slot] = i;
+    a.rec_view[slot] = v;
+    a.rec_geo[slot] = make_float4(o.u, o.v, a.opac[i], o.pz);
+    a.rec_conic[slot] = make_float4(o.c / o.det, (-o.b) / o.det, o.a / o.det, 0.f);
+    a.rec_rect[slot] = make_int4(o.x0, o.y0, o.x1, o.y1);
+    a.rec_npairs[slot] = (o.x1 - o.x0) * (o.y1 - o.y0);
 
     // viewing direction in the instance-local frame
     float dx, dy, dz;
@@ -502,13 +512,7 @@ __global__ __launch_bounds__(kRecThreads) void k_records(ProjArgs a) {
     gg = fmaxf(gg + 0.5f, 0.f);
     bb = fmaxf(bb + 0.5f, 0.f);
 
-    a.rec_gid[slot] = i;
-    a.rec_view[slot] = v;
-    a.rec_geo[slot] = make_float4(o.u, o.v, a.opac[i], o.pz);
-    a.rec_conic[slot] = make_float4(o.c / o.det, (-o.b) / o.det, o.a / o.det, 0.f);
     a.rec_rgb[slot] = make_float4(r, gg, bb, 0.f);
-    a.rec_rect[slot] = make_int4(o.x0, o.y0, o.x1, o.y1);
-    a.rec_npairs[slot] = (o.x1 - o.x0) * (o.y1 - o.y0);
   }
 }
 

@@ -720,7 +720,9 @@ __device__ __forceinline__ void project_bwd_owner(const ProjBwdArgs& a, int r0, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
+// (at most 256 VGPRs, no spills: two waves per SIMD instead of one)
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(2))) void k_project_bwd(ProjBwdArgs a) {
   const int nrec = (int)min((int64_t)a.counters[S3R_CNT_SURV], a.kp.cap_surv);
   const int stride = gridDim.x * blockDim.x;
   for (int base = blockIdx.x * blockDim.x; base < nrec; base += stride)

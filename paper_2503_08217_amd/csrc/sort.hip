@@ -8,8 +8,9 @@
 //
 //   1. exclusive scan of the pairs per record (reduce-then-scan; up to 1024
 //      blocks, each block of the second pass adds up the block sums before it)
-//   2. k_emit_pairs: every thread writes a run of consecutive pairs (records
-//      covering thousands of tiles are spread over many threads)
+//   2. k_emit_pairs: every thread computes a run of consecutive pairs
+//      (records covering thousands of tiles are spread over many threads),
+//      stored coalesced through LDS
 //   3. least-significant-digit radix passes, 8 bits each: block histograms ->
 //      scan of the digit-major histogram matrix (sized by the pair count on
 //      the device, not by the capacity) -> stable scatter, where each wave
@@ -163,49 +164,75 @@ static hipError_t scan_i32(const int32_t* in, const int32_t* n_dev, int64_t n_ca
 // pair emission
 // ---------------------------------------------------------------------------
 constexpr int kEmitRun = 8;  // consecutive pairs per thread
+constexpr int kEmitThreads = 256;
+constexpr int kEmitBlock = kEmitThreads * kEmitRun;  // pairs per workgroup pass
+constexpr int kEmitPad = kEmitRun + 1;  // a thread's LDS row, padded against bank conflicts
 
-__global__ __launch_bounds__(256) void k_emit_pairs(SortArgs a) {
+// Each thread finds the record of its first pair by binary search and walks
+// its run of kEmitRun pairs; the runs are staged in LDS and the workgroup
+// then stores the kEmitBlock pairs lane-consecutively (whole cache lines,
+// where run-per-lane stores would leave lines partly written).
+__global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(SortArgs a) {
+  __shared__ uint64_t s_key[kEmitThreads * kEmitPad];
+  __shared__ uint32_t s_val[kEmitThreads * kEmitPad];
   const int nrec = a.counters[S3R_CNT_SURV];
   const int64_t total = a.misc[0];
   const int64_t ndup = min(total, a.cap_dup);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) {
     a.counters[S3R_CNT_DUP] = (int32_t)ndup;
     a.counters[S3R_CNT_OVF_DUP] = (int32_t)(total - ndup);
   }
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x * kEmitRun;
-  for (int64_t p0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kEmitRun; p0 < ndup;
-       p0 += stride) {
-    // last record whose first pair is at or before p0
-    int lo = 0, hi = nrec - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (a.pair_off[mid] <= p0) lo = mid;
-      else hi = mid - 1;
-    }
-    int r = lo;
-    int64_t next = (r + 1 < nrec) ? (int64_t)a.pair_off[r + 1] : total;
-    int4 rc = a.rec_rect[r];
-    int v = a.rec_view[r];
-    uint32_t db = __float_as_uint(a.rec_geo[r].w);
-    int gx = (a.wh[2 * v] + a.tile - 1) / a.tile;
-    const int64_t p1 = min(ndup, p0 + kEmitRun);
-    for (int64_t p = p0; p < p1; ++p) {
-      while (p >= next) {
-        ++r;
-        next = (r + 1 < nrec) ? (int64_t)a.pair_off[r + 1] : total;
-        rc = a.rec_rect[r];
-        v = a.rec_view[r];
-        db = __float_as_uint(a.rec_geo[r].w);
-        gx = (a.wh[2 * v] + a.tile - 1) / a.tile;
+  // the loop bounds are uniform over the workgroup (it holds barriers)
+  for (int64_t P = (int64_t)blockIdx.x * kEmitBlock; P < ndup;
+       P += (int64_t)gridDim.x * kEmitBlock) {
+    const int64_t p0 = P + (int64_t)tid * kEmitRun;
+    if (p0 < ndup) {
+      // last record whose first pair is at or before p0
+      int lo = 0, hi = nrec - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.pair_off[mid] <= p0) lo = mid;
+        else hi = mid - 1;
       }
-      const int j = (int)(p - a.pair_off[r]);
-      const int w = rc.z - rc.x;
-      const int tx = rc.x + j % w;
-      const int ty = rc.y + j / w;
-      const uint32_t t = (uint32_t)(a.tile_offset[v] + ty * gx + tx);
-      a.keys[p] = ((uint64_t)t << 32) | db;
-      a.vals0[p] = (uint32_t)r;
+      int r = lo;
+      int64_t next = (r + 1 < nrec) ? (int64_t)a.pair_off[r + 1] : total;
+      int4 rc = a.rec_rect[r];
+      int v = a.rec_view[r];
+      uint32_t db = __float_as_uint(a.rec_geo[r].w);
+      int gx = (a.wh[2 * v] + a.tile - 1) / a.tile;
+      const int64_t p1 = min(ndup, p0 + kEmitRun);
+      for (int64_t p = p0; p < p1; ++p) {
+        while (p >= next) {
+          ++r;
+          next = (r + 1 < nrec) ? (int64_t)a.pair_off[r + 1] : total;
+          rc = a.rec_rect[r];
+          v = a.rec_view[r];
+          db = __float_as_uint(a.rec_geo[r].w);
+          gx = (a.wh[2 * v] + a.tile - 1) / a.tile;
+        }
+        const int j = (int)(p - a.pair_off[r]);
+        const int w = rc.z - rc.x;
+        const int tx = rc.x + j % w;
+        const int ty = rc.y + j / w;
+        const uint32_t t = (uint32_t)(a.tile_offset[v] + ty * gx + tx);
+        const int slot = tid * kEmitPad + (int)(p - p0);
+        s_key[slot] = ((uint64_t)t << 32) | db;
+        s_val[slot] = (uint32_t)r;
+      }
     }
+    __syncthreads();
+    // pair P + e lives in row e / kEmitRun, column e % kEmitRun
+#pragma unroll
+    for (int m = 0; m < kEmitRun; ++m) {
+      const int e = tid + kEmitThreads * m;
+      if (P + e < ndup) {
+        const int slot = (e / kEmitRun) * kEmitPad + e % kEmitRun;
+        a.keys[P + e] = s_key[slot];
+        a.vals0[P + e] = s_val[slot];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -858,9 +885,9 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
   {
     SortArgs ea = a;
     ea.vals0 = vb[0];
-    const int64_t want = (a.cap_dup + 256 * kEmitRun - 1) / (256 * kEmitRun);
+    const int64_t want = (a.cap_dup + kEmitBlock - 1) / kEmitBlock;
     const int grid = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
-    S3R_LAUNCH(K_EMIT, k_emit_pairs, dim3(grid), dim3(256), 0, st, ea);
+    S3R_LAUNCH(K_EMIT, k_emit_pairs, dim3(grid), dim3(kEmitThreads), 0, st, ea);
   }
   // 3. radix passes
   for (int p = 0; p < passes; ++p) {

@@ -81,9 +81,9 @@ def render_view(scene, views, v, params, plain=False, region=None, with_image=Tr
 
 def raster_visible(scene, views, v, params, plain=False):
     """Rendering-derived visibility of view v: the Gaussians blended into at
-    least one pixel (one reading of the visibility "obtained by the rendering
-    process"), plus those whose status rests on a guard-band decision.
-    Returns (took, uncertain) as boolean (N,) arrays."""
+    least one pixel (one reading of the visibility that the Fig. 1 caption
+    attributes to the rendering process), plus those whose status rests on a
+    guard-band decision.  Returns (took, uncertain) as boolean (N,) arrays."""
     tr = {"took": set(), "uncertain": set()}
     W34, Kv, wh, tau = views.W[v], views.K[v], views.wh[v], int(views.tstep[v])
     d = decide32.project_cull32(scene, W34, Kv, wh, tau, params, plain=plain, view_index=v)

@@ -3,8 +3,8 @@ temporal-visibility lifecycle of Sec. 3.3 over epochs.
 
 Every training step renders a batch of views, backpropagates the L1 loss and
 updates the point life l with the batch's visible masks (Eq. 5).  At the end
-of an epoch ("after iterating through all training times") the visibility is
-folded from the point life (Eq. 6); every `reset_every` epochs it is instead
+of an epoch, once every training time has been rendered, the visibility is
+folded from the point life (Sec. 3.3, Eq. 6); every `reset_every` epochs it is instead
 reset to visible at all times.  Gaussians appended during training start
 visible at all times.  Parameters are updated with Adam on the activated
 quantities (scale is kept positive, opacity inside (0, 1)); the optimiser is

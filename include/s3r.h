@@ -70,7 +70,9 @@ enum {
   S3R_E_SIZE = -3,      /* a size is out of range (n, views, degree, tile) */
   S3R_E_WORKSPACE = -4, /* workspace smaller than s3r_workspace_size()    */
   S3R_E_HIP = -5,       /* a kernel launch failed                          */
-  S3R_E_ARG = -6        /* an argument value is invalid                    */
+  S3R_E_ARG = -6,       /* an argument value is invalid                    */
+  S3R_E_SCRATCH = -7    /* the problem needs more than the fixed scratch of
+                           s3r_project_cull_noalloc                         */
 };
 
 /* S3RParams.flags */
@@ -274,6 +276,24 @@ int s3r_workspace_size(const S3RSizes* sizes, int32_t which, size_t* bytes);
  */
 int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RParams* params,
                      S3RProjected* out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * s3r_project_cull_noalloc -- s3r_project_cull without a workspace argument,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, outputs and errors otherwise; it calls no allocating routine.
+ * Its scratch is a fixed 4 MiB device array in the library, one per device
+ * (held until the process ends, its address looked up on the first call on
+ * each device).  A problem whose workspace, s3r_workspace_size(
+ * S3R_WS_PROJECT), exceeds 4 MiB is rejected with S3R_E_SCRATCH before
+ * anything is enqueued; 4 MiB holds e.g. 100M Gaussians x 24 views or 20M x 64.
+ * Every call on a device shares that device's scratch: calls that overlap in
+ * time on one device (different streams, or several threads) race and must
+ * be serialised by the caller.  Nothing in the scratch needs clearing between
+ * calls (each call writes what it reads).
+ */
+int s3r_project_cull_noalloc(const S3RScene* scene, const S3RViews* views,
+                             const S3RParams* params, S3RProjected* out, void* stream);
 
 /*
  * s3r_sort -- builds per-tile contributor lists ordered by (depth bits,

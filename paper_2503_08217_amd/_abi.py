@@ -14,6 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libs3r.so")
 
 S3R_OK = 0
+S3R_E_NULL, S3R_E_ALIGN, S3R_E_SIZE, S3R_E_WORKSPACE, S3R_E_HIP, S3R_E_ARG = -1, -2, -3, -4, -5, -6
+S3R_E_SCRATCH = -7
 S3R_TEMPORAL, S3R_LOD, S3R_PLAIN, S3R_LOD_STOCHASTIC, S3R_GRAD_SPARSE = 1, 2, 4, 8, 16
 S3R_SORT_TILES = 32
 S3R_VIS_UPDATE, S3R_VIS_FOLD, S3R_VIS_RESET = 0, 1, 2
@@ -80,6 +82,8 @@ SIGNATURES = {
     "s3r_workspace_size": ([C.POINTER(S3RSizes), C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
     "s3r_project_cull": ([C.POINTER(S3RScene), C.POINTER(S3RViews), C.POINTER(S3RParams),
                           C.POINTER(S3RProjected), P, C.c_size_t, P], C.c_int),
+    "s3r_project_cull_noalloc": ([C.POINTER(S3RScene), C.POINTER(S3RViews), C.POINTER(S3RParams),
+                                  C.POINTER(S3RProjected), P], C.c_int),
     "s3r_sort": ([C.POINTER(S3RScene), C.POINTER(S3RProjected), C.POINTER(S3RViews),
                   C.POINTER(S3RParams), C.POINTER(S3RBins), P, C.c_size_t, P], C.c_int),
     "s3r_raster_fwd": ([C.POINTER(S3RProjected), C.POINTER(S3RBins), C.POINTER(S3RViews),

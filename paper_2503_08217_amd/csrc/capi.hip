@@ -1,11 +1,37 @@
 // extern "C" entry points: argument validation, workspace carving, launches.
 #include <algorithm>
+#include <mutex>
 
 #include "internal.hpp"
 
 using namespace s3r;
 
+// Fixed device scratch of s3r_project_cull_noalloc (the block-offset scan's
+// chunk sums and per-view chunk statistics).  Each device holds its own copy
+// for the life of the process; every call on a device reuses it.
+constexpr size_t kScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// Device address of the current device's `scratch`, looked up once per
+// device (the array's name is only a host-side stand-in).
+int scratch_base(char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return S3R_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return S3R_E_HIP;
+    g_scratch[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch[dev];
+  return S3R_OK;
+}
 
 constexpr size_t kAlign = 256;
 
@@ -173,41 +199,9 @@ S3RSizes sizes_of(const S3RScene* s, const S3RViews* v, const S3RParams* p) {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-}  // namespace
 
-extern "C" {
-
-int s3r_abi_version(void) { return S3R_ABI_VERSION; }
-
-const char* s3r_status_string(int code) {
-  switch (code) {
-    case S3R_OK: return "ok";
-    case S3R_E_NULL: return "a required pointer is NULL";
-    case S3R_E_ALIGN: return "a pointer is not 16-byte aligned";
-    case S3R_E_SIZE: return "a size is out of range";
-    case S3R_E_WORKSPACE: return "workspace too small";
-    case S3R_E_HIP: return "HIP kernel launch failed";
-    case S3R_E_ARG: return "invalid argument value";
-    default: return "unknown status";
-  }
-}
-
-int s3r_workspace_size(const S3RSizes* z, int32_t which, size_t* bytes) {
-  if (!z || !bytes) return S3R_E_NULL;
-  if (z->n < 0 || z->n_views < 1 || z->n_views > kMaxViews || z->total_tiles < 0 ||
-      z->cap_surv < 0 || z->cap_dup < 0 || z->n_slots < 1)
-    return S3R_E_SIZE;
-  switch (which) {
-    case S3R_WS_PROJECT: *bytes = ws_project(*z, nullptr, nullptr); break;
-    case S3R_WS_SORT: *bytes = ws_sort(*z, nullptr, nullptr); break;
-    case S3R_WS_BACKWARD: *bytes = ws_bwd(*z, nullptr, nullptr); break;
-    default: return S3R_E_ARG;
-  }
-  return S3R_OK;
-}
-
-int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RParams* params,
-                     S3RProjected* out, void* ws, size_t ws_bytes, void* stream) {
+int check_project_args(const S3RScene* scene, const S3RViews* views, const S3RParams* params,
+                       const S3RProjected* out) {
   int rc = check_params(params);
   if (rc) return rc;
   const bool plain = (params->flags & S3R_PLAIN) != 0;
@@ -235,15 +229,13 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
   S3R_REQUIRE(out->rec_npairs);
   S3R_REQUIRE(out->surv);
   S3R_REQUIRE(out->bstat);
-  const S3RSizes z = sizes_of(scene, views, params);
-  if (!ws && ws_bytes) return S3R_E_NULL;
-  if (ws_bytes < ws_project(z, nullptr, nullptr) || !ws) return S3R_E_WORKSPACE;
-  if (!aligned16(ws)) return S3R_E_ALIGN;
-  WsProject w;
-  ws_project(z, &w, static_cast<char*>(ws));
-  const hipStream_t st = as_stream(stream);
-  const int nblk = project_blocks(scene->n);
+  return S3R_OK;
+}
 
+// a1-a5 on `st` with the workspace carved into `w` (arguments validated)
+int project_cull_launch(const S3RScene* scene, const S3RViews* views, const S3RParams* params,
+                        S3RProjected* out, const WsProject& w, hipStream_t st) {
+  const int nblk = project_blocks(scene->n);
   S3R_HIP(launch_compose(views->W, views->tstep, scene->pose, scene->n_slots, scene->n_timesteps,
                          views->n_views, out->cam, out->cen, out->t_norm, out->counters,
                          out->stats, st));
@@ -290,6 +282,67 @@ int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RPara
   a.kp = kparams(*params);
   S3R_HIP(launch_project(a, out->stats, st));
   return S3R_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int s3r_abi_version(void) { return S3R_ABI_VERSION; }
+
+const char* s3r_status_string(int code) {
+  switch (code) {
+    case S3R_OK: return "ok";
+    case S3R_E_NULL: return "a required pointer is NULL";
+    case S3R_E_ALIGN: return "a pointer is not 16-byte aligned";
+    case S3R_E_SIZE: return "a size is out of range";
+    case S3R_E_WORKSPACE: return "workspace too small";
+    case S3R_E_HIP: return "HIP kernel launch failed";
+    case S3R_E_ARG: return "invalid argument value";
+    case S3R_E_SCRATCH:
+      return "problem too large for the fixed scratch of the no-allocation entry point";
+    default: return "unknown status";
+  }
+}
+
+int s3r_workspace_size(const S3RSizes* z, int32_t which, size_t* bytes) {
+  if (!z || !bytes) return S3R_E_NULL;
+  if (z->n < 0 || z->n_views < 1 || z->n_views > kMaxViews || z->total_tiles < 0 ||
+      z->cap_surv < 0 || z->cap_dup < 0 || z->n_slots < 1)
+    return S3R_E_SIZE;
+  switch (which) {
+    case S3R_WS_PROJECT: *bytes = ws_project(*z, nullptr, nullptr); break;
+    case S3R_WS_SORT: *bytes = ws_sort(*z, nullptr, nullptr); break;
+    case S3R_WS_BACKWARD: *bytes = ws_bwd(*z, nullptr, nullptr); break;
+    default: return S3R_E_ARG;
+  }
+  return S3R_OK;
+}
+
+int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RParams* params,
+                     S3RProjected* out, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_project_args(scene, views, params, out);
+  if (rc) return rc;
+  const S3RSizes z = sizes_of(scene, views, params);
+  if (!ws && ws_bytes) return S3R_E_NULL;
+  if (ws_bytes < ws_project(z, nullptr, nullptr) || !ws) return S3R_E_WORKSPACE;
+  if (!aligned16(ws)) return S3R_E_ALIGN;
+  WsProject w;
+  ws_project(z, &w, static_cast<char*>(ws));
+  return project_cull_launch(scene, views, params, out, w, as_stream(stream));
+}
+
+int s3r_project_cull_noalloc(const S3RScene* scene, const S3RViews* views,
+                             const S3RParams* params, S3RProjected* out, void* stream) {
+  int rc = check_project_args(scene, views, params, out);
+  if (rc) return rc;
+  const S3RSizes z = sizes_of(scene, views, params);
+  if (ws_project(z, nullptr, nullptr) > kScratchBytes) return S3R_E_SCRATCH;
+  char* base = nullptr;
+  if ((rc = scratch_base(&base))) return rc;
+  WsProject w;
+  ws_project(z, &w, base);
+  return project_cull_launch(scene, views, params, out, w, as_stream(stream));
 }
 
 int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* views,

@@ -271,6 +271,13 @@ class Renderer:
                                           C.byref(self.c_params), C.byref(self.c_proj), _ptr(ws),
                                           nb, _stream()), "s3r_project_cull")
 
+    def project_cull_noalloc(self):
+        """s3r_project_cull with the library's fixed scratch instead of a
+        workspace (no device allocation in the call)."""
+        A.check(A.load().s3r_project_cull_noalloc(C.byref(self.c_scene), C.byref(self.c_views),
+                                                  C.byref(self.c_params), C.byref(self.c_proj),
+                                                  _stream()), "s3r_project_cull_noalloc")
+
     def sort(self):
         ws, nb = self.ws[A.S3R_WS_SORT]
         A.check(A.load().s3r_sort(C.byref(self.c_scene), C.byref(self.c_proj), C.byref(self.c_views),

@@ -118,3 +118,30 @@ def test_host_validation_codes(lib):
     # plain transform: timestep out of range
     ts = (C.c_int32 * 1)(5)
     assert lib.s3r_plain_transform(C.byref(scene), ts, 1, ptr, ptr, None) == -6
+
+
+def test_noalloc_rejects_problem_beyond_its_scratch(lib):
+    """s3r_project_cull_noalloc refuses, on the host and before anything is
+    enqueued, a problem whose projection workspace exceeds its fixed 4 MiB
+    scratch (60M Gaussians x 64 views), and validates arguments like
+    s3r_project_cull."""
+    buf = (C.c_float * 64)()
+    base = C.addressof(buf)
+    al = base + (16 - base % 16) % 16
+    ptr = C.c_void_p(al)
+    views = A.S3RViews(*([ptr] * 6), C.c_void_p(0), 64, 1, 64)
+    proj = A.S3RProjected(*([ptr] * 15))
+    p = _params()
+    big = A.S3RScene(*([ptr] * 9), C.c_void_p(0), C.c_void_p(0), 60_000_000, 0, 1, 1, 0)
+    z = A.S3RSizes(60_000_000, 64, 1, 16, 64, 1, 0)
+    nb = C.c_size_t(0)
+    assert lib.s3r_workspace_size(C.byref(z), A.S3R_WS_PROJECT, C.byref(nb)) == 0
+    assert nb.value > 4 << 20
+    assert lib.s3r_project_cull_noalloc(C.byref(big), C.byref(views), C.byref(p), C.byref(proj),
+                                        None) == A.S3R_E_SCRATCH
+    assert b"scratch" in lib.s3r_status_string(A.S3R_E_SCRATCH)
+    assert lib.s3r_project_cull_noalloc(None, C.byref(views), C.byref(p), C.byref(proj),
+                                        None) == A.S3R_E_NULL
+    p_bad = _params(tile=12)
+    assert lib.s3r_project_cull_noalloc(C.byref(big), C.byref(views), C.byref(p_bad),
+                                        C.byref(proj), None) == A.S3R_E_SIZE

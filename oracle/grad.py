@@ -175,11 +175,32 @@ def loss_and_grads(scene, views, view_ids, orders, rp, targets, route="instance"
         imgs[v] = (img.detach().numpy(), T.detach().numpy())
         loss = loss + l1_loss_t(img, targets[v])
     loss.backward()
+    return float(loss.detach()), imgs, _grads_of(pt, scene)
+
+
+def _grads_of(pt, scene):
     g = {k: (t.grad.numpy().copy() if t.grad is not None else np.zeros(t.shape))
          for k, t in pt.items()}
     g["pose"][:, 0] = 0.0            # slot 0 is the fixed identity of static Gaussians
     g["pose6"] = pose6(scene.pose, g["pose"])
-    return float(loss.detach()), imgs, g
+    return g
+
+
+def image_vjp(scene, views, rp, parts, route="instance"):
+    """Gradients of sum_parts <dC, image of view v over region>: the backward
+    of the image for a given dL/dC that is zero outside the regions.
+
+    parts: list of (v, region (x0, y0, x1, y1), contributor ids of the region
+    in blending order, dC (3, y1 - y0, x1 - x0)).  Returns the grads dict."""
+    pt = to_torch_params(scene)
+    total = torch.zeros((), dtype=TD)
+    for v, region, order_ids, dC in parts:
+        img, _ = render_t(pt, scene, views, v, np.asarray(order_ids), rp, region=region,
+                          route=route)
+        total = total + (img * torch.as_tensor(np.asarray(dC, np.float64))).sum()
+    if total.requires_grad:
+        total.backward()
+    return _grads_of(pt, scene)
 
 
 def pose6(pose34, dpose34):

@@ -34,7 +34,24 @@ def survivor_colours(scene, d, ids):
     return rgb, raw, dv
 
 
-def render_view(scene, views, v, params, plain=False, region=None, with_image=True):
+def region_candidates(d, ids, region, params):
+    """The survivors `ids` that can pass the Mahalanobis cut somewhere in
+    region (x0, y0, x1, y1).  The others are skipped at every pixel of the
+    region, so leaving them out changes nothing there:
+    -power >= |d|^2 / (2 lam_max) > cutoff when |d|^2 > 2 cutoff lam_max."""
+    if not ids.size:
+        return ids
+    x0, y0, x1, y1 = region
+    uu = d["u"][ids].astype(np.float64)
+    vv = d["v"][ids].astype(np.float64)
+    ddx = np.maximum(0.0, np.maximum(x0 - uu, uu - (x1 - 1)))
+    ddy = np.maximum(0.0, np.maximum(y0 - vv, vv - (y1 - 1)))
+    lim = 2.0 * params["cutoff"] * d["lam_d"][ids].astype(np.float64) * 1.0001 + 1e-9
+    return ids[ddx * ddx + ddy * ddy <= lim]
+
+
+def render_view(scene, views, v, params, plain=False, region=None, with_image=True,
+                delta=1e-4):
     W34, Kv, wh, tau = views.W[v], views.K[v], views.wh[v], int(views.tstep[v])
     d = decide32.project_cull32(scene, W34, Kv, wh, tau, params, plain=plain, view_index=v)
     ids = np.nonzero(d["surv"])[0]
@@ -47,23 +64,12 @@ def render_view(scene, views, v, params, plain=False, region=None, with_image=Tr
         return out
     w, h = int(wh[0]), int(wh[1])
     xs, ys = view_pixels(w, h, region)
-    cand = ids
-    if region is not None and ids.size:
-        # Gaussians that cannot pass the Mahalanobis cut anywhere in the region
-        # are skipped at every pixel; dropping them first changes nothing:
-        # -power >= |d|^2 / (2 lam_max) > cutoff when |d|^2 > 2 cutoff lam_max.
-        x0, y0, x1, y1 = region
-        uu = d["u"][ids].astype(np.float64)
-        vv = d["v"][ids].astype(np.float64)
-        ddx = np.maximum(0.0, np.maximum(x0 - uu, uu - (x1 - 1)))
-        ddy = np.maximum(0.0, np.maximum(y0 - vv, vv - (y1 - 1)))
-        lim = 2.0 * params["cutoff"] * d["lam_d"][ids].astype(np.float64) * 1.0001 + 1e-9
-        cand = ids[ddx * ddx + ddy * ddy <= lim]
+    cand = ids if region is None else region_candidates(d, ids, region, params)
     ordr = order.global_order(cand, d["depth_bits"])
     conic = np.stack([d["conic_a"], d["conic_b"], d["conic_c"]], 1).astype(np.float64)
     C, T, ncon, flag = comp.composite(xs, ys, ordr, d["u"].astype(np.float64),
                                       d["v"].astype(np.float64), conic,
-                                      scene.opacity.astype(np.float64), rgb, params)
+                                      scene.opacity.astype(np.float64), rgb, params, delta=delta)
     if region is None:
         out["image"] = C.T.reshape(3, h, w)
         out["T"] = T.reshape(h, w)

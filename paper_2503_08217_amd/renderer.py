@@ -71,6 +71,7 @@ class Renderer:
         self.life_s = up(scene.life_s)
         self.life_e = up(scene.life_e)
         self.pose = up(np.asarray(scene.pose).reshape(self.T, self.S, 12))
+        self._fwd_gen = 0  # raster forwards so far (the backward replays the last one)
         self.set_views(views)
         self.cap_surv = int(cap_surv) if cap_surv else max(1, self.n * self.V)
         self.cap_dup = int(cap_dup) if cap_dup else max(1024, 4 * self.cap_surv)
@@ -285,6 +286,7 @@ class Renderer:
                                   _stream()), "s3r_sort")
 
     def raster_fwd(self):
+        self._fwd_gen += 1
         A.check(A.load().s3r_raster_fwd(C.byref(self.c_proj), C.byref(self.c_bins),
                                         C.byref(self.c_views), C.byref(self.c_params),
                                         C.byref(self.c_img), _stream()), "s3r_raster_fwd")
@@ -365,6 +367,13 @@ class Renderer:
         return graph
 
     # ---------------------------------------------------------------- helpers
+    def parameters(self):
+        """The scene parameters as the renderer's own device tensors, in the
+        argument order of `RenderFn` / `render` (mean, scale, quat, opacity,
+        sh, pose).  They alias the buffers the library reads, so an
+        optimiser step on them changes what the next forward renders."""
+        return (self.mean, self.scale, self.quat, self.opacity, self.sh, self.pose)
+
     def read_counters(self):
         torch.cuda.synchronize()
         c = self.counters.cpu().numpy()
@@ -405,20 +414,40 @@ class Renderer:
 
 
 class RenderFn(torch.autograd.Function):
-    """Image of every view of `renderer` as a function of the scene parameters.
+    """Images of every view of `renderer` (its colour buffer, planar per view)
+    as a function of the scene parameters.
 
-    The renderer's own tensors are the parameters (they are passed in so that
-    autograd tracks them); backward returns the library's gradients."""
+    The library reads the parameters from the renderer's own buffers, so the
+    tensors passed in must be exactly those (`Renderer.parameters()`); they
+    are passed so that autograd tracks them.  The backward replays the
+    forward from its stored final transmittance and last contributors, so it
+    must follow its own forward: a backward after another raster forward of
+    the same renderer raises instead of returning gradients of the wrong
+    image."""
 
     @staticmethod
     def forward(ctx, renderer, mean, scale, quat, opacity, sh, pose):
+        for mine, given, name in zip(renderer.parameters(), (mean, scale, quat, opacity, sh, pose),
+                                     ("mean", "scale", "quat", "opacity", "sh", "pose")):
+            if given.data_ptr() != mine.data_ptr() or given.shape != mine.shape:
+                raise ValueError(f"RenderFn: `{name}` is not the renderer's own {name} buffer")
         renderer.forward()
         ctx.renderer = renderer
+        ctx.gen = renderer._fwd_gen
         return renderer.color.clone()
 
     @staticmethod
     def backward(ctx, d_color):
         r = ctx.renderer
+        if r._fwd_gen != ctx.gen:
+            raise RuntimeError("RenderFn.backward: the renderer ran another forward since this "
+                               "image was rendered; its stored transmittance belongs to that one")
         r.raster_bwd(d_color.contiguous())
         return (None, r.g_mean.clone(), r.g_scale.clone(), r.g_quat.clone(),
                 r.g_opacity.clone(), r.g_sh.clone(), r.g_pose.view(r.T, r.S, 12).clone())
+
+
+def render(renderer, *params):
+    """`RenderFn.apply(renderer, *params)`: the differentiable image of the
+    renderer's views (params default to `renderer.parameters()`)."""
+    return RenderFn.apply(renderer, *(params or renderer.parameters()))

@@ -4,65 +4,18 @@ Decisions (M_t, survivor sets, footprint rectangles, depth keys, per-tile
 order) must match bit for bit; projected attributes that feed decisions
 (u, v, depth) too; colours within 1e-5; blended pixels within 1e-4 absolute
 except pixels the FP64 oracle flags as within rounding distance of a
-blending threshold (bounded by 0.03 x the largest colour, counted)."""
+blending threshold (bounded by what one flipped decision can change, about
+0.023 x the largest colour; counted and reported)."""
 
 import numpy as np
 import pytest
 
 import scenes
-from oracle import decide32, render
+from oracle import render
 
-from gpu_util import banner, image_np, make_renderer, mask_bits, needs_gpu, records, T_np, \
-    tile_lists_gpu
+from gpu_util import banner, check_view, image_np, make_renderer, mask_bits, needs_gpu, records
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
-
-
-def check_view(scene, views, params, r, rec, v, plain=False, region=None, full_lists=True):
-    o = render.render_view(scene, views, v, params, plain=plain, region=region)
-    d = o["dec"]
-    gm = mask_bits(r)[v]
-    np.testing.assert_array_equal(gm, d["visible"], err_msg=f"M_t view {v}")
-    sel = rec["view"] == v
-    gid = rec["gid"][sel]
-    assert np.all(np.diff(gid) > 0), "records of a view must be in Gaussian order"
-    np.testing.assert_array_equal(gid, np.nonzero(d["surv"])[0], err_msg=f"survivors view {v}")
-    geo = rec["geo"][sel]
-    np.testing.assert_array_equal(geo[:, 0].view(np.uint32), d["u"][gid].view(np.uint32))
-    np.testing.assert_array_equal(geo[:, 1].view(np.uint32), d["v"][gid].view(np.uint32))
-    np.testing.assert_array_equal(geo[:, 3].view(np.uint32), d["depth_bits"][gid])
-    np.testing.assert_array_equal(geo[:, 2], scene.opacity[gid])
-    rect = rec["rect"][sel]
-    np.testing.assert_array_equal(rect[:, 0], d["x0"][gid])
-    np.testing.assert_array_equal(rect[:, 1], d["y0"][gid])
-    np.testing.assert_array_equal(rect[:, 2], d["x1"][gid])
-    np.testing.assert_array_equal(rect[:, 3], d["y1"][gid])
-    con = rec["conic"][sel][:, :3]
-    ref = np.stack([d["conic_a"], d["conic_b"], d["conic_c"]], 1)[gid]
-    np.testing.assert_array_equal(con.view(np.uint32), ref.view(np.uint32))
-    np.testing.assert_allclose(rec["rgb"][sel][:, :3], o["rgb"][gid], atol=1e-5, rtol=0)
-    st = rec["stats"][v]
-    assert st[1] == d["visible"].sum() and st[2] == d["surv"].sum()
-    if params.get("temporal"):
-        assert st[0] == d["pass_t"].sum()
-    if full_lists:
-        a = render.tile_lists_of(d, np.nonzero(d["surv"])[0], params)
-        g = tile_lists_gpu(r, rec)[v]
-        np.testing.assert_array_equal(g[0], a[0])
-        np.testing.assert_array_equal(g[1], a[1])
-    img = image_np(r, v)
-    T = T_np(r, v)
-    if region is not None:
-        x0, y0, x1, y1 = region
-        img = img[:, y0:y1, x0:x1]
-        T = T[y0:y1, x0:x1]
-    ok = ~o["flag"]
-    err = np.abs(img - o["image"])
-    assert err[:, ok].max(initial=0) <= 1e-4, (v, err[:, ok].max())
-    cmax = max(1e-6, o["rgb"].max())
-    assert err.max(initial=0) <= 0.03 * cmax
-    assert np.abs(T - o["T"])[ok].max(initial=0) <= 1e-4
-    return o
 
 
 @pytest.mark.parametrize("plain", [False, True])

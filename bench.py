@@ -37,9 +37,14 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 METRIC = "fwd+bwd views/s at 1080p, 2M Gaussians: streamlined vs plain, same GPU"
 
-# algorithmic work per unit (see the design notes)
-FLOP_FWD_PAIR = 22.0     # blending one (pixel, list entry) pair
-FLOP_BWD_PAIR = 60.0     # replaying one (pixel, list entry) pair backwards
+# algorithmic work per unit (see the design notes): FP32 operations of Eq. (2)
+# and its derivative, counted on the work census of the forward
+FLOP_EVAL = 15.0         # exponent of one evaluated (pixel, entry) pair: offsets,
+                         # quadratic form, o exp(power), clamp, two tests (+1 exp)
+FLOP_FWD_BLEND = 8.0     # blending a contributing pair: T (1 - alpha), 3 colour FMAs
+FLOP_BWD_BLEND = 25.0    # its backward: T recovery (+1 rcp), dL/dalpha, dL/dpower,
+                         # five conic moments, opacity and colour gradients
+FLOP_LAST_PAIR = 60.0    # the coarser model: every list entry up to the pixel's last
 REC_BYTES = 72           # record written per survivor (gid, view, geo, conic, rgb, rect)
 GEOM_BYTES = 44          # mean, scale, quat, instance id of a Gaussian that passes
 
@@ -139,16 +144,18 @@ def warmup_temporal(r, cfg, torch, source="frustum"):
 
 
 def view_units(r, handles, targets, torch):
-    """Per timed view: stats and the algorithmic units of each kernel."""
+    """Per timed view: stats and the algorithmic units of each kernel (the
+    forward's work census: evaluated and blended (pixel, entry) pairs)."""
     out = []
     for h, tg in zip(handles, targets):
         r.use_views(h)
-        r.forward()
+        cen = r.work_census()
         torch.cuda.synchronize()
         st = r.stats.cpu().numpy()[0].astype(np.int64)
         last = r.last[: r.total_px].to(torch.int64).sum().item()
         out.append(dict(N_t=int(st[0]), N_f=int(st[1]), N_r=int(st[2]), N_dup=int(st[3]),
-                        pairs_last=int(last)))
+                        pairs_last=int(last), pairs_eval=cen["evaluated"],
+                        pairs_blend=cen["blended"]))
     return out
 
 
@@ -156,21 +163,27 @@ def timed(r, handles, targets, steps, warmup, torch, profile=True):
     """Warm-up steps with every kernel timed (this picks the dominant kernel),
     then the timed region: `steps` steps with only the dominant kernel
     bracketed by HIP events.  Returns (seconds, {kernel: (ms, launches)} of
-    the warm-up, (dominant name, ms, launches) of the timed region)."""
+    the profiled warm-up steps, the handle index of each of those steps,
+    (dominant name, ms, launches) of the timed region).  The first warm-up
+    step carries one-time costs and is left out of the table when there are
+    more."""
     from paper_2503_08217_amd import _abi
     lib = _abi.load()
     _abi.check(lib.s3r_profile_reset(), "profile reset")
     _abi.check(lib.s3r_profile_only(-1), "profile only")
     _abi.check(lib.s3r_profile_enable(1), "profile enable")
+    profiled = []
     for i in range(warmup):
         h = i % len(handles)
         r.use_views(handles[h])
         r.step(targets[h])
+        profiled.append(h)
         if i == 0 and warmup > 1:
             # first launches carry one-time costs: they do not pick the
             # dominant kernel
             torch.cuda.synchronize()
             _abi.check(lib.s3r_profile_reset(), "profile reset")
+            profiled = []
     torch.cuda.synchronize()
     table = _abi.profile_table()
     dom = max(table.items(), key=lambda kv: kv[1][0])[0]
@@ -187,42 +200,72 @@ def timed(r, handles, targets, steps, warmup, torch, profile=True):
     live = _abi.profile_table()
     _abi.check(lib.s3r_profile_enable(0), "profile disable")
     _abi.check(lib.s3r_profile_only(-1), "profile only")
-    return t1 - t0, table, (dom,) + tuple(live.get(dom, (0.0, 0)))
+    return t1 - t0, table, profiled, (dom,) + tuple(live.get(dom, (0.0, 0)))
 
 
 def kernel_roofline(name, total_ms, launches, units, steps, sh_degree, n):
-    """Algorithmic work of the timed steps for kernel `name` -> roofline entry."""
+    """Algorithmic work of the timed steps for kernel `name` -> (bound,
+    achieved, peak, unit, basis, extra)."""
     nviews = len(units)
     # the timed steps cycle over the views: work of step i is that of view i % nviews
     per = [units[i % nviews] for i in range(steps)]
     sh_bytes = 12 * (sh_degree + 1) ** 2
-    if name == "raster_bwd":
-        work = sum(u["pairs_last"] for u in per) * FLOP_BWD_PAIR
-        return "alu", work / (total_ms * 1e-3) / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s", \
-            f"{FLOP_BWD_PAIR:.0f} FLOP per replayed (pixel, entry) pair, pairs = sum of last"
-    if name == "raster_fwd":
-        work = sum(u["pairs_last"] for u in per) * FLOP_FWD_PAIR
-        return "alu", work / (total_ms * 1e-3) / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s", \
-            f"{FLOP_FWD_PAIR:.0f} FLOP per blended (pixel, entry) pair, pairs = sum of last"
+    sec = total_ms * 1e-3
+    if name in ("raster_bwd", "raster_fwd"):
+        blend = FLOP_BWD_BLEND if name == "raster_bwd" else FLOP_FWD_BLEND
+        work = sum(FLOP_EVAL * u["pairs_eval"] + blend * u["pairs_blend"] for u in per)
+        coarse = sum(u["pairs_last"] for u in per) * FLOP_LAST_PAIR
+        extra = {"pairs_per_launch": {
+                     "list_entries_to_last": sum(u["pairs_last"] for u in per) / steps,
+                     "evaluated": sum(u["pairs_eval"] for u in per) / steps,
+                     "blended": sum(u["pairs_blend"] for u in per) / steps},
+                 "flop_per_launch": work / steps,
+                 "coarse_model": {"achieved": coarse / sec / 1e12,
+                                  "frac": coarse / sec / 1e12 / FP32_PEAK_TFLOPS,
+                                  "work": f"{FLOP_LAST_PAIR:.0f} FLOP per list entry up to each "
+                                          "pixel's last contributor (counts entries the cutoff "
+                                          "box skips: an upper bound)"}}
+        return "alu", work / sec / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s", \
+            (f"{FLOP_EVAL:.0f} FLOP + 1 exp per evaluated (pixel, entry) pair, {blend:.0f} FLOP "
+             "per blended pair (work census of the forward)"), extra
     if name == "project":
         b = sum(8 * n + GEOM_BYTES * u["N_t"] + n / 8 + (4 + sh_bytes + REC_BYTES) * u["N_r"]
                 for u in per)
-        return "hbm", b / (total_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", \
-            "8 N + 44 N_t + N/8 + (4 + 12(L+1)^2 + 72) N_r bytes"
+        return "hbm", b / sec / 1e9, HBM_PEAK_GBS, "GB/s", \
+            "8 N + 44 N_t + N/8 + (4 + 12(L+1)^2 + 72) N_r bytes", {}
     if name == "radix":
         passes = launches // steps // 2
         b = sum((8 + 24) * passes * u["N_dup"] for u in per)
-        return "hbm", b / (total_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", \
-            "per radix pass 8 B read (histogram) + 12 B read + 12 B written per pair"
+        return "hbm", b / sec / 1e9, HBM_PEAK_GBS, "GB/s", \
+            "per radix pass 8 B read (histogram) + 12 B read + 12 B written per pair", {}
     if name == "records":
         b = sum((GEOM_BYTES + 4 + sh_bytes + REC_BYTES + 4) * u["N_r"] for u in per)
-        return "hbm", b / (total_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", \
-            "(44 + 4 + 12(L+1)^2 + 76) N_r bytes"
+        return "hbm", b / sec / 1e9, HBM_PEAK_GBS, "GB/s", \
+            "(44 + 4 + 12(L+1)^2 + 76) N_r bytes", {}
     if name == "project_bwd":
         b = sum((48 + 4 + 2 * sh_bytes + 40 + 48) * u["N_r"] for u in per)
-        return "hbm", b / (total_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", \
-            "(read 48 + 4 + 12(L+1)^2 + g2d 48, write 40 + 12(L+1)^2) N_r bytes"
+        return "hbm", b / sec / 1e9, HBM_PEAK_GBS, "GB/s", \
+            "(read 48 + 4 + 12(L+1)^2 + g2d 48, write 40 + 12(L+1)^2) N_r bytes", {}
     return None
+
+
+def pcs_span(r, handles, torch, reps=3):
+    """Wall time on the GPU of steps a1-a8 (s3r_project_cull + s3r_sort) per
+    call, launch gaps included, between two events on the renderer's stream;
+    mean over `reps` passes over the handles."""
+    ev = []
+    for _ in range(reps):
+        for h in handles:
+            r.use_views(h)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r.project_cull()
+            r.sort()
+            e1.record()
+            ev.append((e0, e1))
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
 
 def pcs_batch_bytes(batch, sh_degree, n):
@@ -237,9 +280,9 @@ def pcs_batch_bytes(batch, sh_degree, n):
             + sum(n / 8 + (4 + sh_bytes + REC_BYTES) * u["N_r"] + 36 * u["N_dup"] for u in batch))
 
 
-def pcs_bytes(units, steps, sh_degree, n):
-    """pcs_batch_bytes over `steps` one-view steps cycling through `units`."""
-    return sum(pcs_batch_bytes([units[i % len(units)]], sh_degree, n) for i in range(steps))
+def pcs_bytes(units, view_ids, sh_degree, n):
+    """pcs_batch_bytes over one-view steps rendering units[i] for i in view_ids."""
+    return sum(pcs_batch_bytes([units[i]], sh_degree, n) for i in view_ids)
 
 
 def cpu_baseline(cfg, n_tiles_sample=160):
@@ -411,10 +454,10 @@ def visibility_sources(cfg, targets, torch, steps=16):
     return out
 
 
-def batched_graph(cfg, torch, replays, tiles):
+def batched_graph(cfg, torch, replays, tiles, sorts=("tiles", "global")):
     """Batched multi-view step (all timed views of the workload in one batch)
     captured in a HIP graph; tile size and sort mode picked by timing each
-    candidate."""
+    candidate (tiles x sorts)."""
     from paper_2503_08217_amd import S3R_VIS_FOLD, S3R_VIS_UPDATE
     from paper_2503_08217_amd.renderer import Renderer
     import scenes
@@ -439,7 +482,7 @@ def batched_graph(cfg, torch, replays, tiles):
     torch.cuda.empty_cache()
     best = None
     tune = []
-    for tile, sort in [(t, m) for t in tiles for m in ("tiles", "global")]:
+    for tile, sort in [(t, m) for t in tiles for m in sorts]:
         params = dict(cfg.params, tile=tile, grad_sparse=True, sort=sort)
         r = Renderer(cfg.scene, views, params, cap_surv=max(1024, cfg.scene.n // 2),
                      cap_dup=max(4096, 2 * cfg.scene.n))
@@ -477,7 +520,8 @@ def batched_graph(cfg, torch, replays, tiles):
         res = {"tile": tile, "sort": sort, "p50_ms": float(np.percentile(ms, 50)),
                "p99_ms": float(np.percentile(ms, 99)), "mean_ms": float(ms.mean()),
                "views_per_s": views.n_views / (ms.mean() * 1e-3),
-               "mean_visible_fraction": float(st[:, 0].mean() / cfg.scene.n),
+               "temporal_pass_fraction": float(st[:, 0].mean() / cfg.scene.n),
+               "frustum_visible_fraction": float(st[:, 1].mean() / cfg.scene.n),
                "records": c["n_surv"], "pairs": c["n_dup"],
                "gaussians_per_s": cfg.scene.n * views.n_views / (ms.mean() * 1e-3),
                "project_cull_sort_hbm": {"achieved": pcs_b / (pcs_ms * 1e-3) / 1e9,
@@ -487,7 +531,8 @@ def batched_graph(cfg, torch, replays, tiles):
                "kernels_us_per_step": {k: 1000 * v[0] / prof_steps for k, v in table.items()}}
         log(f"batched {cfg.name} tile {tile} sort {sort}: p50 {res['p50_ms']:.2f} ms, p99 "
             f"{res['p99_ms']:.2f} ms, {res['views_per_s']:.1f} views/s, N_t/N "
-            f"{res['mean_visible_fraction']:.3f}, project/cull/sort "
+            f"{res['temporal_pass_fraction']:.3f}, N_f/N {res['frustum_visible_fraction']:.3f}, "
+            f"project/cull/sort "
             f"{res['project_cull_sort_hbm']['ms_per_step']:.3f} ms at "
             f"{100 * res['project_cull_sort_hbm']['frac']:.1f}% of HBM peak")
         for k, v in sorted(res["kernels_us_per_step"].items(), key=lambda kv: -kv[1])[:12]:
@@ -513,6 +558,9 @@ def main():
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the LOD threshold x temporal filter grid")
     ap.add_argument("--replays", type=int, default=100)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched 24-view graph replays of the rig and city workloads")
+    ap.add_argument("--batched-replays", type=int, default=30)
     ap.add_argument("--scale-up", action="store_true",
                     help="per-view time vs corridor length (125 m .. 3 km), then exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -560,32 +608,41 @@ def main():
             r.fit_capacity()
         handles = r.prepare_views([cfg.views.subset([v]) for v in cfg.timed_views])
         units = view_units(r, handles, targets, torch)
-        log(f"{name}: per view {[(u['N_t'], u['N_f'], u['N_r'], u['N_dup']) for u in units]}")
-        elapsed, table, live = timed(r, handles, targets, a.steps, a.warmup, torch)
+        log(f"{name}: per view (N_t, N_f, N_r, N_dup, evaluated, blended) "
+            f"{[(u['N_t'], u['N_f'], u['N_r'], u['N_dup'], u['pairs_eval'], u['pairs_blend']) for u in units]}")
+        span = pcs_span(r, handles, torch)
+        elapsed, table, profiled, live = timed(r, handles, targets, a.steps, a.warmup, torch)
         vps = a.steps / elapsed
         log(f"{name}: {vps:.1f} views/s, {1000 * elapsed / a.steps:.3f} ms/step; dominant "
-            f"{live[0]} {1000 * live[1] / max(live[2], 1):.1f} us x {live[2]} (timed region)")
+            f"{live[0]} {1000 * live[1] / max(live[2], 1):.1f} us x {live[2]} (timed region); "
+            f"project/cull/sort span {1000 * span:.1f} us per view")
         for k, (ms, cnt) in sorted(table.items(), key=lambda kv: -kv[1][0]):
             log(f"   {k:22s} {1000 * ms / cnt:9.1f} us x {cnt}  (warm-up)")
         results[name] = dict(vps=vps, ms=1000 * elapsed / a.steps, table=table, units=units,
-                             live=live)
+                             live=live, profiled=profiled, span=span)
         del r
         torch.cuda.empty_cache()
 
     s = results["streamlined"]
-    table, units = s["table"], s["units"]
+    table, units, profiled = s["table"], s["units"], s["profiled"]
     dname, dms, dcnt = s["live"]
     rl = kernel_roofline(dname, dms, dcnt, units, a.steps, cfg.scene.sh_degree, cfg.scene.n)
     roof = None
     if rl:
-        bound, ach, peak, unit, basis = rl
+        bound, ach, peak, unit, basis, extra = rl
         roof = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
                 "traffic": measured_traffic(dname, cfg.name), "kernel": dname,
                 "avg_us": 1000 * dms / dcnt, "work": basis,
-                "sources_sha256_16": sources_digest(dname)}
-    # warm-up steps (every kernel timed) give the project/cull/sort time
+                "sources_sha256_16": sources_digest(dname), **extra}
+    # the profiled warm-up steps (every kernel timed) give the project/cull/sort
+    # kernel time; bytes are those of the views those steps rendered
+    npro = max(len(profiled), 1)
     pcs_ms = sum(table[k][0] for k in PCS_KERNELS if k in table)
-    pcs_gbs = pcs_bytes(units, a.warmup, cfg.scene.sh_degree, cfg.scene.n) / (pcs_ms * 1e-3) / 1e9
+    pcs_b = pcs_bytes(units, profiled, cfg.scene.sh_degree, cfg.scene.n)
+    pcs_gbs = pcs_b / (pcs_ms * 1e-3) / 1e9
+    span_b = pcs_bytes(units, range(len(units)), cfg.scene.sh_degree, cfg.scene.n) / len(units)
+    span_gbs = span_b / (s["span"] * 1e-3) / 1e9
+    wh = cfg.views.wh[cfg.timed_views[0]]
     out = {
         "metric": METRIC,
         "value": s["vps"],
@@ -600,22 +657,52 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": cfg.name, "gaussians": int(cfg.scene.n), "instances": 30,
-                   "resolution": "1920x1080", "views_per_step": 1, "sh_degree": 3,
-                   "lod_r_px": 1.0, "temporal": "on (after warm-up fold)"},
+        "config": {"workload": cfg.name, "gaussians": int(cfg.scene.n),
+                   "instances": int(cfg.scene.n_slots - 1),
+                   "resolution": f"{int(wh[0])}x{int(wh[1])}", "views_per_step": 1,
+                   "sh_degree": int(cfg.scene.sh_degree), "tile": int(cfg.params["tile"]),
+                   "lod_r_px": float(cfg.params["lod_r"]) if cfg.params.get("lod") else 0.0,
+                   "temporal": ("on (after warm-up fold)" if cfg.params.get("temporal")
+                                and cfg.warmup_fold else
+                                "on" if cfg.params.get("temporal") else "off")},
         "roofline": roof,
-        "project_cull_sort_hbm": {"achieved": pcs_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                  "frac": pcs_gbs / HBM_PEAK_GBS, "ms_per_step": pcs_ms / a.warmup},
-        "kernels_us_warmup": {k: 1000 * ms / cnt for k, (ms, cnt) in table.items()},
+        "project_cull_sort_hbm": {
+            "achieved": pcs_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": pcs_gbs / HBM_PEAK_GBS, "ms_per_step": pcs_ms / npro,
+            "bytes_per_step": pcs_b / npro, "profiled_steps": npro,
+            "basis": "algorithmic bytes of the profiled warm-up steps / the sum of their a1-a8 "
+                     "kernel times (HIP events around each launch)",
+            "span": {"achieved": span_gbs, "frac": span_gbs / HBM_PEAK_GBS,
+                     "ms_per_view": s["span"],
+                     "basis": "mean algorithmic bytes per timed view / GPU time from the first "
+                              "a1 launch to the end of the last a8 launch (gaps included)"}},
+        "kernels_us_per_step_warmup": {k: 1000 * ms / npro for k, (ms, cnt) in table.items()},
+        "launches_per_step_warmup": {k: cnt / npro for k, (ms, cnt) in table.items()},
     }
     if "plain" in results:
         p = results["plain"]
         out["plain_views_per_s"] = p["vps"]
         out["speedup_vs_plain"] = s["vps"] / p["vps"]
-        out["plain_kernels_us_warmup"] = {k: 1000 * ms / cnt for k, (ms, cnt) in p["table"].items()}
+        npp = max(len(p["profiled"]), 1)
+        out["plain_kernels_us_per_step_warmup"] = {k: 1000 * ms / npp
+                                                   for k, (ms, cnt) in p["table"].items()}
     if not a.no_sweep and a.config == 3:
         out["sweep"] = lod_temporal_sweep(cfg, targets, torch)
         out["visibility_source"] = visibility_sources(cfg, targets, torch)
+    if not a.no_batched and a.config == 3:
+        # the batched workloads at one tile and sort mode (the full search:
+        # --config 4 / --config 5)
+        del targets
+        torch.cuda.empty_cache()
+        out["batched"] = {}
+        for cid, tile in ((4, 16), (5, 32)):
+            t0 = time.perf_counter()
+            bc = scenes.make_config(cid)
+            log(f"config {cid} ({bc.name}) generated in {time.perf_counter() - t0:.1f}s")
+            res = batched_graph(bc, torch, a.batched_replays, (tile,), ("tiles",))
+            out["batched"][bc.name] = res["best"]
+            del bc
+            torch.cuda.empty_cache()
     if not a.no_cpu:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -217,6 +217,13 @@ typedef struct S3RImage {
   uint32_t* m_raster; /* [V][ceil(N/64)*2], layout of S3RProjected.mask     */
   int32_t* rec_taken;
   int64_t n;
+  /* optional work census (NULL: not counted), two device counters that
+     s3r_raster_fwd adds to (the caller clears them): [0] the evaluated
+     (pixel, list entry) pairs -- a pixel still blending and an entry whose
+     Mahalanobis cutoff box meets the pixel's 8x8 sub-tile, so Eq. (2)'s
+     exponent is computed -- and [1] the blended ones (the entry contributed
+     to the pixel).  One atomic per wave and counter: for measurement runs. */
+  uint64_t* census;
 } S3RImage;
 
 typedef struct S3RGrads {

@@ -62,7 +62,7 @@ class S3RBins(C.Structure):
 
 class S3RImage(C.Structure):
     _fields_ = [("color", P), ("T_final", P), ("last", P), ("m_raster", P), ("rec_taken", P),
-                ("n", C.c_int64)]
+                ("n", C.c_int64), ("census", P)]
 
 
 class S3RGrads(C.Structure):

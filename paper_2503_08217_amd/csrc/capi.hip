@@ -433,6 +433,10 @@ int s3r_raster_fwd(const S3RProjected* proj, const S3RBins* bins, const S3RViews
   a.T_final = img->T_final;
   a.last = img->last;
   a.kp = kparams(*params);
+  if (img->census) {
+    if ((reinterpret_cast<uintptr_t>(img->census) & 7u) != 0) return S3R_E_ALIGN;
+    a.census = reinterpret_cast<unsigned long long*>(img->census);
+  }
   const hipStream_t st = as_stream(stream);
   const int64_t mw = ((img->n + 63) / 64) * 2;
   if (img->m_raster) {

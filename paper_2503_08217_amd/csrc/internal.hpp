@@ -86,6 +86,7 @@ struct RasterArgs {
   float* T_final;
   int32_t* last;
   int32_t* rec_taken;  // optional: record blended into some pixel (rendering-derived M_t)
+  unsigned long long* census;  // optional: evaluated and blended (pixel, entry) pairs
   KParams kp;
 };
 

@@ -47,6 +47,7 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a) {
   float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f;
   bool done = !inside;
   int last = 0;
+  unsigned long long n_eval = 0, n_blend = 0;  // work census (optional)
   // Each wave walks the tile's list on its own, 64 entries at a time: lane l
   // holds entry b0 + l, one ballot keeps the entries whose cutoff box meets
   // the wave's sub-tile, and those are broadcast lane by lane.  Loads are
@@ -82,12 +83,14 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a) {
       const float u = bcast(g.x, j), vv = bcast(g.y, j), o = bcast(g.z, j);
       const float A = bcast(c.x, j), B = bcast(c.y, j), C = bcast(c.z, j);
       const Blend bl = blend_eval(u, vv, A, B, C, o, fxp, fyp, a.kp);
+      if (a.census) n_eval += __popcll(ballot(!done));
       const bool hit = bl.hit && !done;
       if (ballot(hit) == 0ull) continue;  // no pixel of the wave takes it
       const float kr = bcast(col.x, j), kg = bcast(col.y, j), kb = bcast(col.z, j);
       const float Tn = T * (1.0f - bl.alpha);
       const bool stop = Tn < a.kp.t_min;  // this entry would push T under the floor
       const bool take = hit && !stop;
+      if (a.census) n_blend += __popcll(ballot(take));
       done = done || (hit && stop);
       const float w = bl.alpha * T;
       cr = take ? fmaf(kr, w, cr) : cr;
@@ -99,6 +102,10 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a) {
       if (a.rec_taken && ballot(take) != 0ull && lane == 0)
         a.rec_taken[__builtin_amdgcn_readlane(rb, j)] = 1;
     }
+  }
+  if (a.census && lane == 0) {
+    atomicAdd(a.census, n_eval);
+    atomicAdd(a.census + 1, n_blend);
   }
   if (inside) {
     const int64_t npx = (int64_t)W * H;

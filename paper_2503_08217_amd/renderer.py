@@ -165,6 +165,7 @@ class Renderer:
             self.rec_taken = torch.zeros(max(1, cs), device=d, dtype=i32)
         else:
             self.m_raster = self.rec_taken = None
+        self.census = torch.zeros(2, device=d, dtype=torch.int64)
         self.d_color = torch.zeros(3 * self.total_px, device=d, dtype=f32)
         self.loss_v = torch.zeros(max(V, 4), device=d, dtype=f32)
         n_ts = len(self.plain_ts)
@@ -214,7 +215,10 @@ class Renderer:
         self.c_bins = A.S3RBins(_ptr(self.tile_count), _ptr(self.tile_start), _ptr(self.vals),
                                 _ptr(self.tile_order), _ptr(self.rec_pair))
         self.c_img = A.S3RImage(_ptr(self.color), _ptr(self.T_final), _ptr(self.last),
-                                _ptr(self.m_raster), _ptr(self.rec_taken), self.n)
+                                _ptr(self.m_raster), _ptr(self.rec_taken), self.n, None)
+        self.c_img_census = A.S3RImage(_ptr(self.color), _ptr(self.T_final), _ptr(self.last),
+                                       _ptr(self.m_raster), _ptr(self.rec_taken), self.n,
+                                       _ptr(self.census))
         self.c_grads = A.S3RGrads(
             _ptr(self.g_mean), _ptr(self.g_scale), _ptr(self.g_quat), _ptr(self.g_opacity),
             _ptr(self.g_sh), _ptr(self.g_pose), _ptr(self.g_pose6), _ptr(self.g_mean_w),
@@ -285,11 +289,27 @@ class Renderer:
                                   C.byref(self.c_params), C.byref(self.c_bins), _ptr(ws), nb,
                                   _stream()), "s3r_sort")
 
-    def raster_fwd(self):
+    def raster_fwd(self, census=False):
+        """Eq. (2) for every view.  With census=True the call also adds its
+        evaluated and blended (pixel, entry) pair counts to `self.census`."""
         self._fwd_gen += 1
+        img = self.c_img_census if census else self.c_img
         A.check(A.load().s3r_raster_fwd(C.byref(self.c_proj), C.byref(self.c_bins),
                                         C.byref(self.c_views), C.byref(self.c_params),
-                                        C.byref(self.c_img), _stream()), "s3r_raster_fwd")
+                                        C.byref(img), _stream()), "s3r_raster_fwd")
+
+    def work_census(self):
+        """Forward of the current batch with the work census: returns the
+        (pixel, entry) pairs evaluated (cutoff box met, pixel still blending)
+        and blended, summed over the batch."""
+        self.census.zero_()
+        if self.plain:
+            self.plain_transform()
+        self.project_cull()
+        self.sort()
+        self.raster_fwd(census=True)
+        c = self.census.cpu().numpy()
+        return dict(evaluated=int(c[0]), blended=int(c[1]))
 
     def l1_loss(self, target):
         A.check(A.load().s3r_l1_loss(C.byref(self.c_img), _ptr(target), C.byref(self.c_views),

@@ -47,7 +47,7 @@ def test_struct_sizes_match_c_layout():
     assert C.sizeof(A.S3RProjected) == 15 * 8
     assert C.sizeof(A.S3RBins) == 5 * 8
     assert C.sizeof(A.S3RGrads) == 11 * 8
-    assert C.sizeof(A.S3RImage) == 6 * 8
+    assert C.sizeof(A.S3RImage) == 7 * 8
     assert C.sizeof(A.S3RSizes) == 40
 
 

@@ -239,3 +239,29 @@ def test_scan_paths_agree():
     assert first[0] == 0 and np.all(np.diff(first) >= 0) and first[-1] < out[0][2].shape[0]
     for a, b in zip(out[0], out[1]):
         np.testing.assert_array_equal(a, b)
+
+
+def test_work_census():
+    """The forward's work census: the blended (pixel, entry) pairs are the
+    oracle's contributor counts summed over the pixels (the terms of Eq. 2),
+    up to the pixels whose decisions lie in the guard band; the evaluated
+    pairs lie between the blended ones and the pixels' whole tile lists."""
+    c = scenes.make_config(1)
+    banner("work census")
+    r = make_renderer(c.scene, c.views, c.params)
+    cen = r.work_census()
+    ncon = slack = full = 0
+    for v in range(c.views.n_views):
+        o = render.render_view(c.scene, c.views, v, c.params)
+        ncon += int(o["ncon"].sum())
+        d = o["dec"]
+        start, _ = render.tile_lists_of(d, o["ids"], c.params)
+        lens = np.diff(start).reshape(d["gy"], d["gx"])
+        per_px = np.kron(lens, np.ones((16, 16), np.int64))[:64, :64]
+        full += int(per_px.sum())
+        slack += int(per_px[o["flag"]].sum())
+    banner(f"census: evaluated {cen['evaluated']}, blended {cen['blended']}, oracle {ncon}, "
+           f"list entries {full}")
+    assert abs(cen["blended"] - ncon) <= slack
+    assert cen["blended"] <= cen["evaluated"] <= full
+    assert cen["blended"] > 0

@@ -114,3 +114,27 @@ def test_routes_agree_on_6dof_pose_gradient():
     for k in ("mean", "scale", "quat", "opacity", "sh", "pose6"):
         np.testing.assert_allclose(a[k], b[k], rtol=1e-5, atol=1e-7 * np.abs(b[k]).max())
     assert np.abs(a["pose"] - b["pose"]).max() > 1e-9     # raw pose gradients differ
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_image_vjp_is_the_region_backward(seed):
+    """image_vjp over regions that tile the view, with dC = dL/dC of the
+    mean-L1 loss (sign(C - target) / (3 w h)), gives the L1 loss gradients;
+    splitting the view into regions with each region's Mahalanobis-cut
+    candidates changes nothing (the pre-filter drops only Gaussians that are
+    skipped at every pixel of the region)."""
+    from oracle import order
+    scene, views, p, orders, tg = _setup(seed)
+    _, imgs, g = grad.loss_and_grads(scene, views, list(orders), orders, p, tg)
+    parts = []
+    for v in orders:
+        img = imgs[v][0]
+        dC = np.sign(img - tg[v]) / img.size
+        o = render.render_view(scene, views, v, p, with_image=False)
+        for reg in ((0, 0, 11, 16), (11, 0, 20, 9), (11, 9, 20, 16)):
+            cand = render.region_candidates(o["dec"], o["ids"], reg, p)
+            parts.append((v, reg, order.global_order(cand, o["dec"]["depth_bits"]),
+                          dC[:, reg[1]:reg[3], reg[0]:reg[2]]))
+    g2 = grad.image_vjp(scene, views, p, parts)
+    for k in ("mean", "scale", "quat", "opacity", "sh", "pose", "pose6"):
+        np.testing.assert_allclose(g2[k], g[k], rtol=1e-10, atol=1e-14, err_msg=k)

@@ -454,6 +454,36 @@ def visibility_sources(cfg, targets, torch, steps=16):
     return out
 
 
+def lifecycle(cfg, torch, epochs=6, reset_every=3):
+    """The temporal-visibility lifecycle over training epochs (Sec. 3.3,
+    Eqs. 5-6): every epoch renders all timesteps one view per step (forward,
+    L1 loss, backward, point-life update, Adam), then folds the visibility,
+    or resets it every `reset_every` epochs.  Returns per epoch the action,
+    the mean loss and the mean fraction of Gaussians passing the temporal
+    test."""
+    import scenes
+    from paper_2503_08217_amd.train import Trainer
+    r = make_renderer(cfg, plain=False)
+    r.zero_grads()
+    views = list(range(cfg.views.n_views))
+    batches = [cfg.views.subset([v]) for v in views]
+    targets = [torch.as_tensor(t.ravel()).cuda() for t in scenes.targets(cfg.cfg, cfg.views, views)]
+    tr = Trainer(r, batches, targets, reset_every=reset_every)
+    out = []
+    for e in range(epochs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec = tr.epoch(e)
+        rec["ms_per_step"] = 1000 * (time.perf_counter() - t0) / len(views)
+        out.append(rec)
+        log(f"lifecycle epoch {e}: loss {rec['loss']:.5f}, temporal pass "
+            f"{rec['temporal_pass']:.3f}, then {rec['action']} ({rec['ms_per_step']:.2f} ms/step "
+            f"incl. Adam)")
+    del tr, r, targets
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_graph(cfg, torch, replays, tiles, sorts=("tiles", "global")):
     """Batched multi-view step (all timed views of the workload in one batch)
     captured in a HIP graph; tile size and sort mode picked by timing each
@@ -561,6 +591,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched 24-view graph replays of the rig and city workloads")
     ap.add_argument("--batched-replays", type=int, default=30)
+    ap.add_argument("--no-lifecycle", action="store_true",
+                    help="skip the training epochs with fold / reset of the visibility")
     ap.add_argument("--scale-up", action="store_true",
                     help="per-view time vs corridor length (125 m .. 3 km), then exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -689,6 +721,8 @@ def main():
     if not a.no_sweep and a.config == 3:
         out["sweep"] = lod_temporal_sweep(cfg, targets, torch)
         out["visibility_source"] = visibility_sources(cfg, targets, torch)
+    if not a.no_lifecycle and a.config == 3:
+        out["lifecycle"] = lifecycle(cfg, torch)
     if not a.no_batched and a.config == 3:
         # the batched workloads at one tile and sort mode (the full search:
         # --config 4 / --config 5)

@@ -76,12 +76,18 @@ class Trainer:
         return dict(mean=r.g_mean, scale=r.g_scale, quat=r.g_quat, opacity=r.g_opacity,
                     sh=r.g_sh)
 
-    def epoch(self, e):
+    def epoch(self, e, on_step=None):
+        """One pass over the batches, then FOLD or RESET.  `on_step(r)`, if
+        given, runs after each batch's step (forward, backward, point-life
+        update) and before the optimiser moves the parameters, so it sees the
+        parameters and the visible mask that step used."""
         r = self.r
         losses, visible = [], []
         for h, tg in zip(self.handles, self.targets):
             r.use_views(h)
             r.step(tg)
+            if on_step is not None:
+                on_step(r)
             self.opt.step(self.params(), self.grads())
             with torch.no_grad():
                 r.scale.clamp_(min=1e-4)

@@ -70,3 +70,53 @@ def test_appended_gaussians_start_visible():
     tr.r.fit_capacity()
     rec = tr.epoch(1)
     assert np.isfinite(rec["loss"])
+
+
+def test_lifecycle_matches_oracle():
+    """Four epochs of training (Adam moves the Gaussians between steps) with
+    a fold after epochs 0, 1, 3 and a reset after epoch 2: at every step the
+    oracle takes the visibility decisions from the parameters the GPU
+    rendered with and its own temporal state, and M_t must match bit for
+    bit; its UPDATE (Eq. 5) per step and FOLD (Eq. 6) or RESET per epoch must
+    give the GPU's point life and visibility intervals bit for bit after
+    every epoch."""
+    from oracle import decide32, visibility
+    from paper_2503_08217_amd.train import Trainer
+    c = scenes.make_config(2, scale_n=0.02)
+    p = dict(c.params, temporal=True, lod=True, lod_r=1.0)
+    taus = [2, 9, 17, 25, 33, 41, 49]
+    batches = [c.views.subset([t]) for t in taus]
+    tg = scenes.targets(2, c.views, taus)
+    targets = [torch.as_tensor(t.ravel()).cuda() for t in tg]
+    banner("training lifecycle against the oracle")
+    r = make_renderer(c.scene, batches[0], p)
+    tr = Trainer(r, batches, targets, reset_every=3)
+    st = dict(life_s=c.scene.life_s.copy(), life_e=c.scene.life_e.copy(),
+              vis_s=c.scene.vis_s.copy(), vis_e=c.scene.vis_e.copy())
+    sc = c.scene.copy()
+    trajectory = []
+
+    def on_step(rr):
+        for k in ("mean", "scale", "quat", "opacity"):
+            setattr(sc, k, getattr(rr, k).cpu().numpy().reshape(getattr(sc, k).shape).copy())
+        sc.vis_s, sc.vis_e = st["vis_s"], st["vis_e"]
+        tau = int(rr.tstep_np[0])
+        d = decide32.project_cull32(sc, rr._vs["W"].cpu().numpy().reshape(3, 4),
+                                    rr._vs["K"].cpu().numpy()[0], rr.wh_np[0], tau, p)
+        np.testing.assert_array_equal(mask_bits(rr)[0], d["visible"], err_msg=f"M_t tau {tau}")
+        assert int(rr.stats[0, 0]) == int(d["pass_t"].sum())
+        st["life_s"], st["life_e"] = visibility.update(st["life_s"], st["life_e"],
+                                                       d["visible"][None], [d["t"]])
+
+    for e in range(4):
+        rec = tr.epoch(e, on_step=on_step)
+        if rec["action"] == "fold":
+            st["vis_s"], st["vis_e"] = visibility.fold(st["life_s"], st["life_e"])
+        else:
+            st["vis_s"], st["vis_e"], st["life_s"], st["life_e"] = visibility.reset(sc.n)
+        for k in ("life_s", "life_e", "vis_s", "vis_e"):
+            np.testing.assert_array_equal(getattr(tr.r, k).cpu().numpy(), st[k],
+                                          err_msg=f"{k} after epoch {e}")
+        trajectory.append((rec["action"], rec["temporal_pass"]))
+    banner(f"temporal-pass fraction per epoch: {trajectory}")
+    assert trajectory[0][1] == 1.0 and trajectory[1][1] < 1.0 and trajectory[3][1] == 1.0

@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define S3R_ABI_VERSION 1
+#define S3R_ABI_VERSION 2
 
 
 enum {
@@ -108,7 +108,9 @@ enum {
   S3R_CNT_SPIN = 4,     /* reserved, always 0: no kernel waits on another
                            workgroup                                        */
   S3R_CNT_TICKET = 5,   /* reserved                                        */
-  S3R_CNT_TICKET2 = 6   /* reserved                                        */
+  S3R_CNT_TICKET2 = 6,  /* reserved                                        */
+  S3R_CNT_PAIRS = 7     /* (tile, record) pairs of every survivor, before the
+                           capacities (saturates at 2^31 - 1)               */
 };
 
 typedef struct S3RParams {
@@ -185,10 +187,18 @@ typedef struct S3RProjected {
   int32_t* rec_npairs;/* [cap_surv] number of tiles each record covers          */
   uint32_t* surv;     /* [V][ceil(N/64)*2] bit i of view v: Gaussian i has a record
                          (M_t and kept by the LOD test); same layout as mask     */
-  int32_t* bstat;     /* [ceil(N/256)][V][4] per block of 256 Gaussians and view:
-                         temporal passes, M_t count, records, first record.  The
+  int32_t* bstat;     /* [ceil(N/256)][V][8] per block of 256 Gaussians and view:
+                         temporal passes, M_t count, records, first record,
+                         (tile, record) pairs, first pair, 2 unused.  The
                          records of a batch are ordered by (block, view, Gaussian);
                          s3r_raster_bwd uses this to find each Gaussian's records */
+  int32_t* rec_pair;  /* [cap_surv] index of each record's first (record, tile)
+                         pair in emission order: a record emits the tiles of
+                         its rectangle row by row, records in record order, so
+                         the pair of record r and tile (tx, ty) is rec_pair[r] +
+                         (ty - y0) (x1 - x0) + (tx - x0).  s3r_sort bins the
+                         pairs by it and s3r_raster_bwd gives every pair its
+                         own gradient slot by it */
 } S3RProjected;
 
 typedef struct S3RBins {
@@ -197,12 +207,6 @@ typedef struct S3RBins {
   uint32_t* vals;      /* [cap_dup] record index of each list entry, sorted  */
   int32_t* tile_order; /* [total_tiles] tiles by descending list length (the
                           rasterizer's launch order; ties in tile order)      */
-  int32_t* rec_pair;   /* [cap_surv] index of each record's first (record,
-                          tile) pair in emission order: a record emits the
-                          tiles of its rectangle row by row, so the pair of
-                          record r and tile (tx, ty) is rec_pair[r] +
-                          (ty - y0) (x1 - x0) + (tx - x0); read back by the
-                          backward to give each pair its own gradient slot */
 } S3RBins;
 
 typedef struct S3RImage {
@@ -278,7 +282,9 @@ int s3r_workspace_size(const S3RSizes* sizes, int32_t which, size_t* bytes);
  *   LOD", drop probability 1), SH colour of the survivors only.
  * Writes one record per (view, surviving Gaussian), ordered by Gaussian block
  * then view then Gaussian index (so record index increases with the Gaussian
- * index within a view), plus M_t bits, stats and per-tile pair counts.
+ * index within a view), each record's first (tile, record) pair, M_t bits and
+ * stats; counters[S3R_CNT_DUP] / [S3R_CNT_OVF_DUP] get the pairs kept (those
+ * of the kept records, at most cap_dup) and dropped.
  * `ws` must hold s3r_workspace_size(S3R_WS_PROJECT) bytes.
  */
 int s3r_project_cull(const S3RScene* scene, const S3RViews* views, const S3RParams* params,
@@ -304,14 +310,16 @@ int s3r_project_cull_noalloc(const S3RScene* scene, const S3RViews* views,
 
 /*
  * s3r_sort -- builds per-tile contributor lists ordered by (depth bits,
- * Gaussian index), the blending order of Eq. (2), bit-exactly: one (tile,
- * record) pair per tile a record covers, keyed (tile << 32 | depth bits) in
- * record order, then a stable radix sort on the key -- or, with
- * S3R_SORT_TILES, a stable radix partition on the tile bits followed by a
- * per-list sort on (depth bits, position), which gives the same lists.  Also
- * writes bins->rec_pair (each record's first pair) and the rasterizers'
- * launch order.  Reads the records of s3r_project_cull (only scene->n is read
- * from `scene`); `ws` holds s3r_workspace_size(S3R_WS_SORT) bytes.
+ * Gaussian index), the blending order of Eq. (2), bit-exactly, from the
+ * (tile, record) pairs of s3r_project_cull (proj->rec_pair): keyed (tile <<
+ * 32 | depth bits) in record order and sorted by a stable radix sort -- or,
+ * with S3R_SORT_TILES, binned by tile and each list sorted on (depth bits,
+ * record index) (a stable radix partition on the tile bits and a sort on
+ * (depth bits, position) when the batch has more tiles than the binning
+ * holds), which gives the same lists.  Also writes the rasterizers' launch
+ * order and stats[v][3].  Reads the records of s3r_project_cull (only
+ * scene->n is read from `scene`); `ws` holds s3r_workspace_size(S3R_WS_SORT)
+ * bytes.
  */
 int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* views,
              const S3RParams* params, S3RBins* bins, void* ws, size_t ws_bytes, void* stream);
@@ -338,7 +346,7 @@ int s3r_l1_loss(const S3RImage* img, const float* target, const S3RViews* views,
  * entry; no caller-side zeroing).  The projection gradient is gathered per
  * Gaussian over the views of the batch, using `proj->surv` and `proj->bstat`
  * to find each Gaussian's records; the blending gradients of each (record,
- * tile) pair go to the pair's own slot in `ws` (found from bins->rec_pair
+ * tile) pair go to the pair's own slot in `ws` (found from proj->rec_pair
  * and the record's tile rectangle) and are summed per record, so no
  * gradient atomics contend across tiles.  Pose gradients are chained through
  * W_{t,i} = W_t W_{t,i2g} and also given in 6-DoF form.  In the plain route
@@ -375,6 +383,36 @@ int s3r_plain_transform(const S3RScene* scene, const int32_t* tsteps, int32_t n_
  */
 int s3r_plain_transform_bwd(const S3RScene* scene, const int32_t* tsteps, int32_t n_ts,
                             S3RGrads* g, void* stream);
+
+/*
+ * Launch-shape knobs, process-wide (every device, every later call; a value
+ * is read when a call enqueues its kernels, so a captured graph keeps the
+ * values of its capture).  None changes any result: every path gives the
+ * same records, lists, images and gradients, bit for bit.  Calls that set
+ * knobs while other threads enqueue work race with them.
+ *   S3R_TUNE_OFFSET_FUSE_MAX  the per-(block, view) record/pair offset scan
+ *       of s3r_project_cull runs in two launches while it has at most this
+ *       many chunks of 1024 entries, in three beyond (0..1024, default 1024)
+ *   S3R_TUNE_SCAN_FUSE_MAX    the same for the library's other prefix scans
+ *       (radix histograms; chunks of 4096 entries)
+ *   S3R_TUNE_BIN_MAX_TILES    with S3R_SORT_TILES, batches of at most this
+ *       many tiles are binned through LDS histograms, larger ones partitioned
+ *       by radix passes (0..12288, default 12288; 0: always partition)
+ *   S3R_TUNE_RASTER_WAVES     waves per workgroup of s3r_raster_fwd: 1 (each
+ *       8x8 sub-tile its own workgroup, default) or the tile's sub-tiles
+ *       together (TILE^2 / 64; the value is clamped to that)
+ * s3r_set_tuning(knob, negative value) restores the default.  Errors:
+ * S3R_E_ARG for an unknown knob or a value out of range.
+ */
+enum {
+  S3R_TUNE_OFFSET_FUSE_MAX = 0,
+  S3R_TUNE_SCAN_FUSE_MAX = 1,
+  S3R_TUNE_BIN_MAX_TILES = 2,
+  S3R_TUNE_RASTER_WAVES = 3,
+  S3R_TUNE_COUNT = 4
+};
+int s3r_set_tuning(int32_t knob, int32_t value);
+int s3r_get_tuning(int32_t knob, int32_t* value);
 
 /*
  * Opt-in per-kernel timing (tracing): when enabled, every kernel the library

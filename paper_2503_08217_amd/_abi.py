@@ -20,7 +20,12 @@ S3R_TEMPORAL, S3R_LOD, S3R_PLAIN, S3R_LOD_STOCHASTIC, S3R_GRAD_SPARSE = 1, 2, 4,
 S3R_SORT_TILES = 32
 S3R_VIS_UPDATE, S3R_VIS_FOLD, S3R_VIS_RESET = 0, 1, 2
 S3R_WS_PROJECT, S3R_WS_SORT, S3R_WS_BACKWARD = 0, 1, 2
-CNT_SURV, CNT_OVF_SURV, CNT_DUP, CNT_OVF_DUP, CNT_SPIN = 0, 1, 2, 3, 4
+S3R_TUNE_OFFSET_FUSE_MAX, S3R_TUNE_SCAN_FUSE_MAX, S3R_TUNE_BIN_MAX_TILES = 0, 1, 2
+S3R_TUNE_RASTER_WAVES = 3
+TUNE_KNOBS = {"offset_fuse_max": S3R_TUNE_OFFSET_FUSE_MAX, "scan_fuse_max": S3R_TUNE_SCAN_FUSE_MAX,
+              "bin_max_tiles": S3R_TUNE_BIN_MAX_TILES, "raster_waves": S3R_TUNE_RASTER_WAVES}
+CNT_SURV, CNT_OVF_SURV, CNT_DUP, CNT_OVF_DUP, CNT_SPIN, CNT_PAIRS = 0, 1, 2, 3, 4, 7
+BSTAT = 8  # ints per (256-Gaussian block, view) entry of S3RProjected.bstat
 
 P = C.c_void_p
 
@@ -52,12 +57,11 @@ class S3RProjected(C.Structure):
     _fields_ = [("cam", P), ("cen", P), ("t_norm", P), ("mask", P), ("rec_gid", P),
                 ("rec_view", P), ("rec_geo", P), ("rec_conic", P), ("rec_rgb", P),
                 ("rec_rect", P), ("counters", P), ("stats", P), ("rec_npairs", P), ("surv", P),
-                ("bstat", P)]
+                ("bstat", P), ("rec_pair", P)]
 
 
 class S3RBins(C.Structure):
-    _fields_ = [("tile_count", P), ("tile_start", P), ("vals", P), ("tile_order", P),
-                ("rec_pair", P)]
+    _fields_ = [("tile_count", P), ("tile_start", P), ("vals", P), ("tile_order", P)]
 
 
 class S3RImage(C.Structure):
@@ -78,6 +82,8 @@ class S3RSizes(C.Structure):
 
 SIGNATURES = {
     "s3r_abi_version": ([], C.c_int),
+    "s3r_set_tuning": ([C.c_int32, C.c_int32], C.c_int),
+    "s3r_get_tuning": ([C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "s3r_status_string": ([C.c_int], C.c_char_p),
     "s3r_workspace_size": ([C.POINTER(S3RSizes), C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
     "s3r_project_cull": ([C.POINTER(S3RScene), C.POINTER(S3RViews), C.POINTER(S3RParams),
@@ -155,3 +161,27 @@ def check(rc: int, what: str):
     if rc != S3R_OK:
         msg = load().s3r_status_string(rc).decode()
         raise S3RError(f"{what} failed with status {rc}: {msg}")
+
+
+def set_tuning(**knobs):
+    """Set launch-shape knobs by name (TUNE_KNOBS; a negative value restores
+    the default).  Returns the previous values."""
+    lib = load()
+    old = {}
+    for name, value in knobs.items():
+        k = TUNE_KNOBS[name]
+        cur = C.c_int32(0)
+        check(lib.s3r_get_tuning(k, C.byref(cur)), "s3r_get_tuning")
+        old[name] = cur.value
+        check(lib.s3r_set_tuning(k, int(value)), f"s3r_set_tuning({name}={value})")
+    return old
+
+
+def get_tuning():
+    lib = load()
+    out = {}
+    for name, k in TUNE_KNOBS.items():
+        cur = C.c_int32(0)
+        check(lib.s3r_get_tuning(k, C.byref(cur)), "s3r_get_tuning")
+        out[name] = cur.value
+    return out

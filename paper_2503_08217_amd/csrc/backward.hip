@@ -429,7 +429,7 @@ __device__ __forceinline__ void project_bwd_owner(const ProjBwdArgs& a, int r0, 
     int64_t r = r0;
     bool has = active && v == v0;
     if (active && v > v0 && mask_bit(a.surv + (size_t)v * a.mask_words, i)) {
-      const int first = a.bstat[((size_t)vb * a.nv + v) * 4 + 3];
+      const int first = a.bstat[((size_t)vb * a.nv + v) * kBstat + 3];
       int before = 0;
       for (int w = 0; w <= wave; ++w) {
         const uint32_t* sb = a.surv + (size_t)v * a.mask_words + 2 * ((size_t)vb * kProjWaves + w);

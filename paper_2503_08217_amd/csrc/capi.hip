@@ -1,5 +1,6 @@
 // extern "C" entry points: argument validation, workspace carving, launches.
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 
 #include "internal.hpp"
@@ -11,6 +12,17 @@ using namespace s3r;
 // for the life of the process; every call on a device reuses it.
 constexpr size_t kScratchBytes = size_t(4) << 20;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace s3r {
+namespace {
+// defaults, and the largest value, of the launch-shape knobs
+constexpr int kTuneDefault[S3R_TUNE_COUNT] = {1024, 1024, 12288, 1};
+constexpr int kTuneMax[S3R_TUNE_COUNT] = {1024, 1024, 12288, 16};
+std::atomic<int> g_tune[S3R_TUNE_COUNT] = {{kTuneDefault[0]}, {kTuneDefault[1]},
+                                           {kTuneDefault[2]}, {kTuneDefault[3]}};
+}  // namespace
+int tune(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }
+}  // namespace s3r
 
 namespace {
 
@@ -52,6 +64,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 struct WsProject {
   int32_t* chunk_sum;
+  long long* chunk_sum_p;
   int32_t* chunk_stat;
 };
 struct WsSort {
@@ -63,6 +76,8 @@ struct WsSort {
   int32_t* sums;
   int32_t* misc;
   int32_t* order_cnt;
+  int32_t* bin_count;   // [total_tiles] pairs per tile (binning path)
+  int32_t* bin_cursor;  // [total_tiles] next free slot of each tile's list
 };
 struct WsBwd {
   float4* g2d;
@@ -76,6 +91,8 @@ size_t ws_project(const S3RSizes& z, WsProject* w, char* base) {
   size_t off = 0;
   if (w) w->chunk_sum = reinterpret_cast<int32_t*>(base + off);
   off += align_up((size_t)nchunk * 4 + 16);
+  if (w) w->chunk_sum_p = reinterpret_cast<long long*>(base + off);
+  off += align_up((size_t)nchunk * 8 + 16);
   if (w) w->chunk_stat = reinterpret_cast<int32_t*>(base + off);
   off += align_up((size_t)nchunk * z.n_views * 12 + 16);
   return off;
@@ -101,6 +118,10 @@ size_t ws_sort(const S3RSizes& z, WsSort* w, char* base) {
   off += align_up(64);
   if (w) w->order_cnt = reinterpret_cast<int32_t*>(base + off);
   off += align_up(order_count_words(z.total_tiles) * 4);
+  if (w) w->bin_count = reinterpret_cast<int32_t*>(base + off);
+  off += align_up((size_t)z.total_tiles * 4 + 4);
+  if (w) w->bin_cursor = reinterpret_cast<int32_t*>(base + off);
+  off += align_up((size_t)z.total_tiles * 4 + 4);
   return off;
 }
 
@@ -229,6 +250,7 @@ int check_project_args(const S3RScene* scene, const S3RViews* views, const S3RPa
   S3R_REQUIRE(out->rec_npairs);
   S3R_REQUIRE(out->surv);
   S3R_REQUIRE(out->bstat);
+  S3R_REQUIRE(out->rec_pair);
   return S3R_OK;
 }
 
@@ -276,7 +298,9 @@ int project_cull_launch(const S3RScene* scene, const S3RViews* views, const S3RP
   a.counters = out->counters;
   a.surv = out->surv;
   a.bstat = out->bstat;
+  a.rec_pair = out->rec_pair;
   a.chunk_sum = w.chunk_sum;
+  a.chunk_sum_p = w.chunk_sum_p;
   a.chunk_stat = w.chunk_stat;
   a.nblk = nblk;
   a.kp = kparams(*params);
@@ -289,6 +313,21 @@ int project_cull_launch(const S3RScene* scene, const S3RViews* views, const S3RP
 extern "C" {
 
 int s3r_abi_version(void) { return S3R_ABI_VERSION; }
+
+int s3r_set_tuning(int32_t knob, int32_t value) {
+  if (knob < 0 || knob >= S3R_TUNE_COUNT) return S3R_E_ARG;
+  if (value < 0) value = kTuneDefault[knob];
+  if (value > kTuneMax[knob] || (knob == S3R_TUNE_RASTER_WAVES && value < 1)) return S3R_E_ARG;
+  g_tune[knob].store(value, std::memory_order_relaxed);
+  return S3R_OK;
+}
+
+int s3r_get_tuning(int32_t knob, int32_t* value) {
+  if (knob < 0 || knob >= S3R_TUNE_COUNT) return S3R_E_ARG;
+  if (!value) return S3R_E_NULL;
+  *value = tune(knob);
+  return S3R_OK;
+}
 
 const char* s3r_status_string(int code) {
   switch (code) {
@@ -362,7 +401,7 @@ int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* vi
   S3R_REQUIRE(bins->tile_start);
   S3R_REQUIRE(bins->tile_order);
   S3R_REQUIRE(bins->vals);
-  S3R_REQUIRE(bins->rec_pair);
+  S3R_REQUIRE(proj->rec_pair);
   const S3RSizes z = sizes_of(nullptr, views, params);
   if (!ws || ws_bytes < ws_sort(z, nullptr, nullptr)) return S3R_E_WORKSPACE;
   if (!aligned16(ws)) return S3R_E_ALIGN;
@@ -384,7 +423,9 @@ int s3r_sort(const S3RScene* scene, const S3RProjected* proj, const S3RViews* vi
   a.tile_count = bins->tile_count;
   a.tile_start = bins->tile_start;
   a.tile_order = bins->tile_order;
-  a.pair_off = bins->rec_pair;
+  a.pair_off = proj->rec_pair;
+  a.bin_count = w.bin_count;
+  a.bin_cursor = w.bin_cursor;
   a.keys = w.keys;
   a.keys_alt = w.keys_alt;
   a.vals0 = w.vals;
@@ -496,7 +537,7 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   S3R_REQUIRE(bins->tile_start);
   S3R_REQUIRE(bins->tile_order);
   S3R_REQUIRE(bins->vals);
-  S3R_REQUIRE(bins->rec_pair);
+  S3R_REQUIRE(proj->rec_pair);
   S3R_REQUIRE(g->scale);
   S3R_REQUIRE(g->opacity);
   S3R_REQUIRE(g->sh);
@@ -557,7 +598,7 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   b.d_color = d_color;
   b.nv = views->n_views;
   b.total_tiles = views->total_tiles;
-  b.rec_pair = bins->rec_pair;
+  b.rec_pair = proj->rec_pair;
   b.rec_rect = reinterpret_cast<const int4*>(proj->rec_rect);
   b.part = w.part;
   b.tile_cut = w.tile_cut;

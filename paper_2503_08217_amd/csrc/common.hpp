@@ -82,6 +82,22 @@ __device__ __forceinline__ float wave_sum4(float x, float y, float z, float w) {
   return s;
 }
 
+// inclusive prefix sum over the 64 lanes (DPP: row shifts, then row
+// broadcasts across rows; no LDS)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_add_i32(int x) {
+  return x + __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xf, false);
+}
+__device__ __forceinline__ int wave_inclusive_scan(int x) {
+  x = dpp_add_i32<0x111, 0xf>(x);  // row_shr:1
+  x = dpp_add_i32<0x112, 0xf>(x);  // row_shr:2
+  x = dpp_add_i32<0x114, 0xf>(x);  // row_shr:4
+  x = dpp_add_i32<0x118, 0xf>(x);  // row_shr:8
+  x = dpp_add_i32<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = dpp_add_i32<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);

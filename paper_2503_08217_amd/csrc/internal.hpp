@@ -9,10 +9,12 @@ namespace s3r {
 // kernels timed by the opt-in profiler (names in profile.hip)
 enum KernelId {
   K_COMPOSE, K_PLAIN_TRANSFORM, K_PROJECT, K_STATS, K_RECORDS, K_SCAN, K_EMIT, K_RADIX,
-  K_TILE_RANGES, K_TILE_ORDER, K_TILE_SORT, K_TILE_SORT_CHUNKS, K_TILE_SORT_MERGE,
+  K_TILE_RANGES, K_TILE_ORDER, K_TILE_SORT, K_TILE_SORT_CHUNKS, K_TILE_SORT_MERGE, K_TILE_BIN,
   K_RASTER_FWD, K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PAIR_REDUCE, K_PROJECT_BWD,
   K_POSE_BWD, K_POSE6, K_PLAIN_TRANSFORM_BWD, K_VISIBILITY, K_ZERO, K_COUNT
 };
+// current value of launch-shape knob S3R_TUNE_* (capi.hip)
+int tune(int knob);
 void prof_begin(int id, hipStream_t st);
 void prof_end(int id, hipStream_t st);
 #define S3R_LAUNCH(ID, ...)        \
@@ -59,11 +61,14 @@ struct ProjArgs {
   int4* rec_rect;
   int32_t* rec_npairs;
   int32_t* counters;
-  // per (block, view): N_t, N_f, N_r, first record (workspace)
+  int32_t* rec_pair;  // first (tile, record) pair of each record, emission order
+  // per (block, view), kBstat ints: N_t, N_f, N_r, first record, pairs,
+  // first pair
   int32_t* bstat;
-  // workspace: per chunk of (block, view) entries, the record count sum
-  // (then its offset) and per-view partial stats
+  // workspace: per chunk of (block, view) entries, the record and pair count
+  // sums (then their offsets) and per-view partial stats
   int32_t* chunk_sum;
+  long long* chunk_sum_p;
   int32_t* chunk_stat;
   uint64_t* flags;
   int nblk;
@@ -149,7 +154,7 @@ struct ProjBwdArgs {
   const int32_t* rec_view;
   const int32_t* counters;
   const uint32_t* surv;   // [V][mask_words] survivor bits
-  const int32_t* bstat;   // [nblk][V][4] per-block counts and first record
+  const int32_t* bstat;   // [nblk][V][kBstat] per-block counts and first record
   int64_t mask_words;
   const float4* g2d;
   // gradients (written)
@@ -178,6 +183,7 @@ hipError_t launch_plain_transform(const float* mean, const float* quat, const in
 // Gaussian) and the per-(block, view) survivor counts give each block's
 // first record
 constexpr int kProjBlock = 256;
+constexpr int kBstat = 8;  // ints per (256-Gaussian block, view) entry of S3RProjected.bstat
 constexpr int kProjWaves = kProjBlock / kWave;
 int project_blocks(int64_t n);
 int offset_chunks(int64_t nblk, int nv);
@@ -206,7 +212,7 @@ struct SortArgs {
   int32_t* tile_start;
   int32_t* tile_order;
   // workspace
-  int32_t* pair_off;   // [cap_surv] first pair of each record (output)
+  const int32_t* pair_off;  // [cap_surv] first pair of each record (s3r_project_cull)
   uint64_t* keys;      // [cap_dup]
   uint64_t* keys_alt;  // [cap_dup]
   uint32_t* vals0;     // [cap_dup]: emitted values
@@ -216,6 +222,8 @@ struct SortArgs {
   int32_t* scan_sums;
   int32_t* misc;       // [0] total pairs, [1] histogram total, [2] histogram length
   int32_t* order_cnt;  // [order_count_words] per (bucket, chunk) tile counts
+  int32_t* bin_count;  // [total_tiles] pairs per tile (binning path)
+  int32_t* bin_cursor; // [total_tiles] next free slot of each list (binning path)
   int64_t cap_dup, cap_surv;
 };
 int sort_passes(int total_tiles, bool by_tile);

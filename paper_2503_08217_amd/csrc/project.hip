@@ -8,14 +8,14 @@
 //                    over the batch's views (a Gaussian's 44 bytes of geometry
 //                    are read once per batch); decisions become M_t bits and
 //                    survivor bits through wave ballots, plus per-(block,
-//                    view) counts
-//   k_off_*          an exclusive scan of the counts (chunk sums, one small
-//                    top scan, chunk rescans) gives the first record of every
-//                    (block, view)
+//                    view) counts of records and of (tile, record) pairs
+//   k_off_*          exclusive scans of the counts (chunk sums, one small
+//                    top scan, chunk rescans) give the first record and the
+//                    first pair of every (block, view)
 //   k_records        one wave per Gaussian block: its survivors (only,
 //                    packed densely over the lanes) re-project, query their
 //                    colour and write their record at base + rank within the
-//                    block
+//                    block, with the record's first pair in emission order
 // Records come out ordered by Gaussian block, then view, then Gaussian.
 #include "internal.hpp"
 
@@ -172,7 +172,7 @@ __device__ __forceinline__ void view_geometry(const ProjArgs& a, int v, const Lo
 // Phase A: decisions of every (view, Gaussian) of the block.  Writes the M_t
 // bits, the survivor bits and the block's per-view counts (N_t, N_f, N_r).
 __global__ __launch_bounds__(kProjBlock) void k_cull(ProjArgs a) {
-  __shared__ int s_cnt[kMaxViews][kProjWaves][3];
+  __shared__ int s_cnt[kMaxViews][kProjWaves][4];
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const int lane = tid % kWave;
@@ -203,6 +203,7 @@ __global__ __launch_bounds__(kProjBlock) void k_cull(ProjArgs a) {
   for (int v = 0; v < a.nv; ++v) {
     const bool pass_t = (pass_bits >> v) & 1ull;
     bool vis = false, surv = false;
+    int npairs = 0;  // tiles of the footprint rectangle of a survivor
     if (pass_t) {
       Loaded e;
       float P[12], fx, fy, cx, cy;
@@ -217,11 +218,13 @@ __global__ __launch_bounds__(kProjBlock) void k_cull(ProjArgs a) {
                           o, i, v);
         vis = o.visible;
         surv = vis && o.keep;
+        npairs = surv ? (o.x1 - o.x0) * (o.y1 - o.y0) : 0;
       }
     }
     const uint64_t bt = ballot(pass_t);
     const uint64_t bf = ballot(vis);
     const uint64_t bs = ballot(surv);
+    const int wp = bs != 0ull ? (int)wave_sum_u32((uint32_t)npairs) : 0;
     if (lane == 0) {
       const int gw = vb * kProjWaves + wave;
       if ((int64_t)gw * kWave < a.n) {
@@ -235,100 +238,152 @@ __global__ __launch_bounds__(kProjBlock) void k_cull(ProjArgs a) {
       s_cnt[v][wave][0] = __popcll(bt);
       s_cnt[v][wave][1] = __popcll(bf);
       s_cnt[v][wave][2] = __popcll(bs);
+      s_cnt[v][wave][3] = wp;
     }
   }
   __syncthreads();
   for (int v = tid; v < a.nv; v += kProjBlock) {
-    int nt = 0, nf = 0, nr = 0;
+    int nt = 0, nf = 0, nr = 0, np = 0;
     for (int w = 0; w < kProjWaves; ++w) {
       nt += s_cnt[v][w][0];
       nf += s_cnt[v][w][1];
       nr += s_cnt[v][w][2];
+      np += s_cnt[v][w][3];
     }
-    int32_t* bs = a.bstat + ((size_t)vb * a.nv + v) * 4;
-    bs[0] = nt; bs[1] = nf; bs[2] = nr;
+    int32_t* bs = a.bstat + ((size_t)vb * a.nv + v) * kBstat;
+    bs[0] = nt; bs[1] = nf; bs[2] = nr; bs[4] = np;
   }
 }
 
-// Exclusive scan of the per-(block, view) survivor counts in (block, view)
-// order -> first record of each (block, view); totals -> counters and stats.
-// Over chunks of kOffChunk entries: chunk sums (and per-view partial stats),
-// then each chunk rescanned with its offset, the sum of the chunk sums before
-// it -- added up by the chunk itself when there are at most kOffFuseMax
-// chunks, else scanned by one workgroup in between.  No contended atomics.
+// Exclusive scans of the per-(block, view) record and pair counts in (block,
+// view) order -> first record and first pair of each (block, view); totals
+// -> counters and stats.  Over chunks of kOffChunk entries: chunk sums (and
+// per-view partial stats), then each chunk rescanned with its offsets, the
+// sums of the chunk sums before it -- added up by the chunk itself when there
+// are at most kOffFuseMax chunks, else scanned by one workgroup in between.
+// Pair sums are 64-bit (a batch may hold more pairs than any capacity).  No
+// contended atomics.
 constexpr int kOffChunk = 1024;
 constexpr int kOffThreads = 256;
 constexpr int kOffPer = kOffChunk / kOffThreads;
 
-__device__ __forceinline__ int block_exclusive_scan(int x, int* s_w, int& total) {
+__device__ __forceinline__ long long shfl_up64(long long v, int o) {
+  const int lo = __shfl_up((int)(uint32_t)(uint64_t)v, o, kWave);
+  const int hi = __shfl_up((int)(uint32_t)((uint64_t)v >> 32), o, kWave);
+  return (long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// exclusive scan of (x, y) over the workgroup in thread order; totals out
+__device__ __forceinline__ void block_exclusive_scan2(int x, long long y, int* s_w,
+                                                      long long* s_w64, int& ex, long long& ey,
+                                                      int& total, long long& total64) {
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-  int incl = x;
+  int ix = x;
+  long long iy = y;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
-    const int t = __shfl_up(incl, o, kWave);
-    if (lane >= o) incl += t;
+    const int tx = __shfl_up(ix, o, kWave);
+    const long long ty = shfl_up64(iy, o);
+    if (lane >= o) {
+      ix += tx;
+      iy += ty;
+    }
   }
-  if (lane == kWave - 1) s_w[wave] = incl;
+  if (lane == kWave - 1) {
+    s_w[wave] = ix;
+    s_w64[wave] = iy;
+  }
   __syncthreads();
-  int base = 0;
+  int bx = 0;
+  long long by = 0;
   total = 0;
+  total64 = 0;
   for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
-    if (w < wave) base += s_w[w];
+    if (w < wave) {
+      bx += s_w[w];
+      by += s_w64[w];
+    }
     total += s_w[w];
+    total64 += s_w64[w];
   }
   __syncthreads();
-  return base + incl - x;
+  ex = bx + ix - x;
+  ey = by + iy - y;
 }
 
 __global__ __launch_bounds__(kOffThreads) void k_off_reduce(const int32_t* __restrict__ bstat,
                                                            int64_t total, int nv,
                                                            int32_t* __restrict__ csum,
+                                                           long long* __restrict__ csum_p,
                                                            int32_t* __restrict__ cstat) {
   __shared__ int s_w[kOffThreads / kWave];
+  __shared__ long long s_w64[kOffThreads / kWave];
   __shared__ int s_stat[kMaxViews][3];
   const int tid = threadIdx.x;
   const int64_t c = blockIdx.x;
   for (int q = tid; q < nv * 3; q += kOffThreads) s_stat[q / 3][q % 3] = 0;
   __syncthreads();
   int sum = 0;
+  long long psum = 0;
   for (int m = 0; m < kOffPer; ++m) {
     const int64_t e = c * kOffChunk + (int64_t)m * kOffThreads + tid;
     if (e < total) {
-      const int4 bs = reinterpret_cast<const int4*>(bstat)[e];
+      const int4 bs = reinterpret_cast<const int4*>(bstat)[e * (kBstat / 4)];
       const int v = (int)(e % nv);
       sum += bs.z;
+      psum += bstat[e * kBstat + 4];
       if (bs.x) atomicAdd(&s_stat[v][0], bs.x);
       if (bs.y) atomicAdd(&s_stat[v][1], bs.y);
       if (bs.z) atomicAdd(&s_stat[v][2], bs.z);
     }
   }
-  int tot;
-  (void)block_exclusive_scan(sum, s_w, tot);
-  if (tid == 0) csum[c] = tot;
+  int ex, tot;
+  long long ey, tot64;
+  block_exclusive_scan2(sum, psum, s_w, s_w64, ex, ey, tot, tot64);
+  if (tid == 0) {
+    csum[c] = tot;
+    csum_p[c] = tot64;
+  }
   for (int q = tid; q < nv * 3; q += kOffThreads) cstat[(c * nv + q / 3) * 3 + q % 3] = s_stat[q / 3][q % 3];
 }
 
-__global__ __launch_bounds__(1024) void k_off_top(int32_t* __restrict__ csum, int nchunk, int nv,
-                                                  const int32_t* __restrict__ cstat,
+// survivor and pair totals -> counters (records beyond cap_surv dropped; the
+// pairs are settled by k_records, which knows the last kept record's pairs)
+__device__ __forceinline__ void store_totals(int32_t* counters, long long surv, long long pairs,
+                                             int64_t cap_surv) {
+  counters[S3R_CNT_SURV] = (int32_t)min(surv, (long long)cap_surv);
+  counters[S3R_CNT_OVF_SURV] = (int32_t)max(0ll, surv - (long long)cap_surv);
+  counters[S3R_CNT_PAIRS] = (int32_t)min(pairs, (long long)INT32_MAX);
+}
+
+__global__ __launch_bounds__(1024) void k_off_top(int32_t* __restrict__ csum,
+                                                  long long* __restrict__ csum_p, int nchunk,
+                                                  int nv, const int32_t* __restrict__ cstat,
                                                   int32_t* __restrict__ counters,
                                                   int32_t* __restrict__ stats, int64_t cap_surv) {
   __shared__ int s_w[1024 / kWave];
+  __shared__ long long s_w64[1024 / kWave];
   const int tid = threadIdx.x;
   const int per = (nchunk + 1023) / 1024;
   const int c0 = min(nchunk, tid * per), c1 = min(nchunk, c0 + per);
   int sum = 0;
-  for (int c = c0; c < c1; ++c) sum += csum[c];
-  int tot;
-  int run = block_exclusive_scan(sum, s_w, tot);
+  long long psum = 0;
+  for (int c = c0; c < c1; ++c) {
+    sum += csum[c];
+    psum += csum_p[c];
+  }
+  int run, tot;
+  long long run64, tot64;
+  block_exclusive_scan2(sum, psum, s_w, s_w64, run, run64, tot, tot64);
   for (int c = c0; c < c1; ++c) {
     const int x = csum[c];
+    const long long y = csum_p[c];
     csum[c] = run;
+    csum_p[c] = run64;
     run += x;
+    run64 += y;
   }
-  if (tid == 0) {
-    counters[S3R_CNT_SURV] = (int32_t)min((int64_t)tot, cap_surv);
-    counters[S3R_CNT_OVF_SURV] = (int32_t)max((int64_t)0, (int64_t)tot - cap_surv);
-  }
+  if (tid == 0) store_totals(counters, tot, tot64, cap_surv);
   for (int q = tid; q < nv * 3; q += 1024) {
     int acc = 0;
     for (int c = 0; c < nchunk; ++c) acc += cstat[((int64_t)c * nv + q / 3) * 3 + q % 3];
@@ -338,59 +393,77 @@ __global__ __launch_bounds__(1024) void k_off_top(int32_t* __restrict__ csum, in
 
 // kPrefix (at most kOffFuseMax chunks): in place of k_off_top, each chunk
 // adds up the chunk sums before it, the chunks share out the per-view
-// statistics, and the last chunk stores the survivor counters
+// statistics, and the last chunk stores the totals
 constexpr int kOffFuseMax = 1024;
 
 template <bool kPrefix>
 __global__ __launch_bounds__(kOffThreads) void k_off_down(int32_t* __restrict__ bstat,
                                                          int64_t total,
                                                          const int32_t* __restrict__ csum,
+                                                         const long long* __restrict__ csum_p,
                                                          int64_t cap_surv, int nchunk, int nv,
                                                          const int32_t* __restrict__ cstat,
                                                          int32_t* __restrict__ counters,
                                                          int32_t* __restrict__ stats) {
   __shared__ int s_w[kOffThreads / kWave];
+  __shared__ long long s_w64[kOffThreads / kWave];
   const int tid = threadIdx.x;
   const int64_t c = blockIdx.x;
   int before;
+  long long before_p;
   if (kPrefix) {
     int p = 0;
-    for (int q = tid; q < (int)c; q += kOffThreads) p += csum[q];
-    (void)block_exclusive_scan(p, s_w, before);
+    long long pp = 0;
+    for (int q = tid; q < (int)c; q += kOffThreads) {
+      p += csum[q];
+      pp += csum_p[q];
+    }
+    int ex;
+    long long ey;
+    block_exclusive_scan2(p, pp, s_w, s_w64, ex, ey, before, before_p);
     // statistic q of the views (3 per view) is summed over the chunks by
     // chunk q mod nchunk
     for (int q = (int)c; q < nv * 3; q += nchunk) {
       int acc = 0;
       for (int k = tid; k < nchunk; k += kOffThreads)
         acc += cstat[((int64_t)k * nv + q / 3) * 3 + q % 3];
-      int all;
-      (void)block_exclusive_scan(acc, s_w, all);
+      int all, ex2;
+      long long ey2, all64;
+      block_exclusive_scan2(acc, 0ll, s_w, s_w64, ex2, ey2, all, all64);
       if (tid == 0) stats[(q / 3) * 4 + (q % 3)] = all;
     }
   } else {
     before = csum[c];
+    before_p = csum_p[c];
   }
   // thread t takes the kOffPer consecutive entries c*kOffChunk + t*kOffPer + m
-  int cnt[kOffPer];
+  int cnt[kOffPer], pc[kOffPer];
   int sum = 0;
+  long long psum = 0;
 #pragma unroll
   for (int m = 0; m < kOffPer; ++m) {
     const int64_t e = c * kOffChunk + (int64_t)tid * kOffPer + m;
-    cnt[m] = e < total ? bstat[e * 4 + 2] : 0;
+    cnt[m] = e < total ? bstat[e * kBstat + 2] : 0;
+    pc[m] = e < total ? bstat[e * kBstat + 4] : 0;
     sum += cnt[m];
+    psum += pc[m];
   }
-  int tot;
-  int64_t run = (int64_t)before + block_exclusive_scan(sum, s_w, tot);
-  if (kPrefix && c == (int64_t)gridDim.x - 1 && tid == 0) {
-    const int64_t all = (int64_t)before + tot;
-    counters[S3R_CNT_SURV] = (int32_t)min(all, cap_surv);
-    counters[S3R_CNT_OVF_SURV] = (int32_t)max((int64_t)0, all - cap_surv);
-  }
+  int ex, tot;
+  long long ey, tot64;
+  block_exclusive_scan2(sum, psum, s_w, s_w64, ex, ey, tot, tot64);
+  int64_t run = (int64_t)before + ex;
+  long long run_p = before_p + ey;
+  if (kPrefix && c == (int64_t)gridDim.x - 1 && tid == 0)
+    store_totals(counters, (long long)before + tot, before_p + tot64, cap_surv);
 #pragma unroll
   for (int m = 0; m < kOffPer; ++m) {
     const int64_t e = c * kOffChunk + (int64_t)tid * kOffPer + m;
-    if (e < total) bstat[e * 4 + 3] = (int32_t)min(run, cap_surv);
+    if (e < total) {
+      bstat[e * kBstat + 3] = (int32_t)min(run, cap_surv);
+      bstat[e * kBstat + 5] = (int32_t)min(run_p, (long long)INT32_MAX);
+    }
     run += cnt[m];
+    run_p += pc[m];
   }
 }
 
@@ -425,9 +498,12 @@ __global__ __launch_bounds__(kRecThreads)
 __attribute__((amdgpu_waves_per_eu(4))) void k_records(ProjArgs a) {
   __shared__ uint64_t s_w[kMaxViews][kProjWaves];
   __shared__ int s_pre[kMaxViews + 1];
+  __shared__ int s_carry[kMaxViews];  // pairs of the view's items already placed
+  __shared__ int s_base[kMaxViews];   // carry minus the scan at the view's first lane
   const int tid = threadIdx.x;
   const int vb = blockIdx.x;
   const bool plain = (a.kp.flags & S3R_PLAIN) != 0;
+  for (int v = tid; v < a.nv; v += kRecThreads) s_carry[v] = 0;
   for (int q = tid; q < a.nv * kProjWaves; q += kRecThreads) {
     const int v = q / kProjWaves, w = q % kProjWaves;
     const int gw = vb * kProjWaves + w;
@@ -450,27 +526,61 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_records(ProjArgs a) {
   __syncthreads();
   const int total = s_pre[a.nv];
   const int B = (a.sh_deg + 1) * (a.sh_deg + 1);
-  for (int item = tid; item < total; item += kRecThreads) {
-    int v = 0;
-    while (s_pre[v + 1] <= item) ++v;
-    int k = item - s_pre[v];
-    const int64_t slot = (int64_t)a.bstat[((size_t)vb * a.nv + v) * 4 + 3] + k;
-    int w = 0;
-    while (k >= __popcll(s_w[v][w])) {
-      k -= __popcll(s_w[v][w]);
-      ++w;
+  const int n_keep = a.counters[S3R_CNT_SURV];  // records kept (min(survivors, cap_surv))
+  const int lane = tid;
+  // the loop bound is uniform over the wave (it holds shuffles)
+  for (int it0 = 0; it0 < total; it0 += kRecThreads) {
+    const int item = it0 + lane;
+    const bool live = item < total;
+    int v = 0, k = 0, i = 0;
+    int64_t slot = INT64_MAX;
+    if (live) {
+      while (s_pre[v + 1] <= item) ++v;
+      k = item - s_pre[v];
+      slot = (int64_t)a.bstat[((size_t)vb * a.nv + v) * kBstat + 3] + k;
+      int w = 0, kk = k;
+      while (kk >= __popcll(s_w[v][w])) {
+        kk -= __popcll(s_w[v][w]);
+        ++w;
+      }
+      i = vb * kProjBlock + w * kWave + select_bit(s_w[v][w], kk);
     }
-    const int i = vb * kProjBlock + w * kWave + select_bit(s_w[v][w], k);
-    if (slot >= a.kp.cap_surv) continue;
     Loaded g;
-    load_gaussian(a, i, true, plain, g);
+    load_gaussian(a, i, live, plain, g);
     Loaded e;
     float P[12], fx, fy, cx, cy;
     int W, H;
-    view_geometry(a, v, g, plain, i, e, P, fx, fy, cx, cy, W, H);
     Proj o;
-    project_canonical(P, e.mx, e.my, e.mz, e.R, e.s0, e.s1, e.s2, fx, fy, cx, cy, W, H, a.kp, o,
-                      i, v);
+    int npairs = 0;
+    if (live) {
+      view_geometry(a, v, g, plain, i, e, P, fx, fy, cx, cy, W, H);
+      project_canonical(P, e.mx, e.my, e.mz, e.R, e.s0, e.s1, e.s2, fx, fy, cx, cy, W, H, a.kp,
+                        o, i, v);
+      npairs = (o.x1 - o.x0) * (o.y1 - o.y0);
+    }
+    // first pair of each item: its (block, view)'s first pair plus the pairs
+    // of the view's items before it -- a scan over the wave in item order,
+    // rebased at the first lane of each view's run and carried across
+    // iterations in LDS
+    const int incl = wave_inclusive_scan(npairs);
+    const int excl = incl - npairs;
+    const bool run_start = live && (lane == 0 || item == s_pre[v]);
+    const bool run_end = live && (lane == kWave - 1 || item + 1 == s_pre[v + 1]);
+    if (run_start) s_base[v] = s_carry[v] - excl;
+    __syncthreads();
+    const int first_pair = live ? a.bstat[((size_t)vb * a.nv + v) * kBstat + 5] + s_base[v] + excl
+                                : 0;
+    if (run_end) s_carry[v] = s_base[v] + incl;
+    __syncthreads();
+    if (!live || slot >= a.kp.cap_surv) continue;
+    // the last kept record settles the pair counters: pairs beyond it, or
+    // beyond cap_dup, are dropped
+    if (slot == n_keep - 1) {
+      const int64_t all = a.counters[S3R_CNT_PAIRS];
+      const int64_t kept = min((int64_t)first_pair + npairs, a.kp.cap_dup);
+      a.counters[S3R_CNT_DUP] = (int32_t)kept;
+      a.counters[S3R_CNT_OVF_DUP] = (int32_t)max((int64_t)0, all - kept);
+    }
     // the geometric part of the record is stored before the colour is
     // evaluated, so its registers are free for the SH coefficients
     a.rec_gid[slot] = i;
@@ -478,7 +588,8 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_records(ProjArgs a) {
     a.rec_geo[slot] = make_float4(o.u, o.v, a.opac[i], o.pz);
     a.rec_conic[slot] = make_float4(o.c / o.det, (-o.b) / o.det, o.a / o.det, 0.f);
     a.rec_rect[slot] = make_int4(o.x0, o.y0, o.x1, o.y1);
-    a.rec_npairs[slot] = (o.x1 - o.x0) * (o.y1 - o.y0);
+    a.rec_npairs[slot] = npairs;
+    a.rec_pair[slot] = first_pair;
 
     // viewing direction in the instance-local frame
     float dx, dy, dz;
@@ -551,16 +662,18 @@ hipError_t launch_project(const ProjArgs& a, int32_t* stats, hipStream_t st) {
   const int nchunk = offset_chunks(a.nblk, a.nv);
   if (nchunk > 0)
     S3R_LAUNCH(K_STATS, k_off_reduce, dim3(nchunk), dim3(kOffThreads), 0, st, a.bstat, total, a.nv,
-               a.chunk_sum, a.chunk_stat);
-  if (nchunk > 0 && nchunk <= kOffFuseMax) {
+               a.chunk_sum, a.chunk_sum_p, a.chunk_stat);
+  if (nchunk > 0 && nchunk <= min(kOffFuseMax, tune(S3R_TUNE_OFFSET_FUSE_MAX))) {
     // counters and statistics start at zero (k_compose), so no chunks, no launch
     S3R_LAUNCH(K_STATS, k_off_down<true>, dim3(nchunk), dim3(kOffThreads), 0, st, a.bstat, total,
-               a.chunk_sum, a.kp.cap_surv, nchunk, a.nv, a.chunk_stat, a.counters, stats);
+               a.chunk_sum, a.chunk_sum_p, a.kp.cap_surv, nchunk, a.nv, a.chunk_stat, a.counters,
+               stats);
   } else if (nchunk > 0) {
-    S3R_LAUNCH(K_STATS, k_off_top, dim3(1), dim3(1024), 0, st, a.chunk_sum, nchunk, a.nv,
-               a.chunk_stat, a.counters, stats, a.kp.cap_surv);
+    S3R_LAUNCH(K_STATS, k_off_top, dim3(1), dim3(1024), 0, st, a.chunk_sum, a.chunk_sum_p, nchunk,
+               a.nv, a.chunk_stat, a.counters, stats, a.kp.cap_surv);
     S3R_LAUNCH(K_STATS, k_off_down<false>, dim3(nchunk), dim3(kOffThreads), 0, st, a.bstat, total,
-               a.chunk_sum, a.kp.cap_surv, nchunk, a.nv, a.chunk_stat, a.counters, stats);
+               a.chunk_sum, a.chunk_sum_p, a.kp.cap_surv, nchunk, a.nv, a.chunk_stat, a.counters,
+               stats);
   }
   if (a.nblk > 0) S3R_LAUNCH(K_RECORDS, k_records, dim3(a.nblk), dim3(kRecThreads), 0, st, a);
   return hipGetLastError();

@@ -19,16 +19,18 @@
 
 namespace s3r {
 
-template <int TS>
-__global__ __launch_bounds__(kWave)
+template <int TS, int WPG>
+__global__ __launch_bounds__(kWave * WPG)
 __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a) {
   constexpr int NW = RasterShape<TS>::NW;
-  // id = kXcds (NW q + w) + x  ->  tile rank kXcds q + x, sub-tile w
+  constexpr int G = NW / WPG;  // workgroups per tile
+  // id = kXcds (G q + g) + x  ->  tile rank kXcds q + x, sub-tiles g WPG ..
+  // g WPG + WPG - 1 (one per wave)
   const int xcd = (int)(blockIdx.x % kXcds), k = (int)(blockIdx.x / kXcds);
-  const int rank = (k / NW) * kXcds + xcd;
+  const int rank = (k / G) * kXcds + xcd;
   if (rank >= a.total_tiles) return;  // padding of the last group of tiles
-  const int lane = threadIdx.x;
-  const int tid = (k % NW) * kWave + lane;  // pixel slot in the tile
+  const int lane = threadIdx.x % kWave;
+  const int tid = ((k % G) * WPG + (int)(threadIdx.x / kWave)) * kWave + lane;  // pixel slot
   const int t = a.tile_order[rank];
   const int v = find_view(a.tile_offset, a.nv, t);
   const int lt = t - a.tile_offset[v];
@@ -146,23 +148,40 @@ hipError_t launch_raster_mask(const int32_t* rec_taken, const int32_t* rec_gid,
   return hipGetLastError();
 }
 
+template <int TS, int WPG>
+static void launch_fwd_shape(const RasterArgs& a, unsigned groups, hipStream_t st) {
+  constexpr int NW = RasterShape<TS>::NW;
+  const dim3 grid(groups * kXcds * (unsigned)(NW / WPG));
+  S3R_LAUNCH(K_RASTER_FWD, (k_raster_fwd<TS, WPG>), grid, dim3(kWave * WPG), 0, st, a);
+}
+
+// waves per workgroup: the largest power of two up to the knob and the tile's
+// sub-tile count
+template <int TS>
+static void launch_fwd_tile(const RasterArgs& a, unsigned groups, hipStream_t st) {
+  constexpr int NW = RasterShape<TS>::NW;
+  const int want = min(tune(S3R_TUNE_RASTER_WAVES), NW);
+  if constexpr (NW >= 16) {
+    if (want >= 16) return launch_fwd_shape<TS, 16>(a, groups, st);
+    if (want >= 8) return launch_fwd_shape<TS, 8>(a, groups, st);
+  }
+  if constexpr (NW >= 4) {
+    if (want >= 4) return launch_fwd_shape<TS, 4>(a, groups, st);
+    if (want >= 2) return launch_fwd_shape<TS, 2>(a, groups, st);
+  }
+  launch_fwd_shape<TS, 1>(a, groups, st);
+}
+
 hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st) {
   if (a.total_tiles <= 0) return hipSuccess;
-  // one wave64 workgroup per 8x8 sub-tile, tiles padded to a multiple of kXcds
+  // tiles padded to a multiple of kXcds; the sub-tiles of a tile take
+  // workgroup ids congruent modulo kXcds (one L2)
   const unsigned groups = ((unsigned)a.total_tiles + kXcds - 1) / kXcds;
-  const dim3 grid(groups * kXcds * (unsigned)(a.kp.tile * a.kp.tile / kWave));
   switch (a.kp.tile) {
-    case 8:
-      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<8>, grid, dim3(kWave), 0, st, a);
-      break;
-    case 16:
-      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<16>, grid, dim3(kWave), 0, st, a);
-      break;
-    case 32:
-      S3R_LAUNCH(K_RASTER_FWD, k_raster_fwd<32>, grid, dim3(kWave), 0, st, a);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case 8: launch_fwd_tile<8>(a, groups, st); break;
+    case 16: launch_fwd_tile<16>(a, groups, st); break;
+    case 32: launch_fwd_tile<32>(a, groups, st); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -1,27 +1,33 @@
 // Per-tile contributor lists in the blending order of Eq. (2).
 //
-// A list entry is a (tile, record) pair; its key is (global tile << 32 |
-// depth bits) and its value the record index.  Pairs are emitted in record
-// order (records of a view are in Gaussian order), so ordering every tile's
-// list by (depth bits, emission position) gives the order the oracle defines
-// -- (depth, Gaussian index) -- bit for bit.
+// A list entry is a (tile, record) pair.  s3r_project_cull gives every
+// record its first pair in emission order (a record emits the tiles of its
+// rectangle row by row, records in record order, and records of a view are
+// in Gaussian order); ordering every tile's list by (depth bits, record)
+// gives the order the oracle defines -- (depth, Gaussian index) -- bit for
+// bit.
 //
-//   1. exclusive scan of the pairs per record (reduce-then-scan; up to 1024
-//      blocks, each block of the second pass adds up the block sums before it)
-//   2. k_emit_pairs: every thread computes a run of consecutive pairs
-//      (records covering thousands of tiles are spread over many threads),
-//      stored coalesced through LDS
-//   3. least-significant-digit radix passes, 8 bits each: block histograms ->
+// With S3R_SORT_TILES and at most kBinMaxTiles tiles (a batch of one 1080p
+// view at 16 px has 8160):
+//   1. k_bin_count / k_bin_scan / k_bin_place: pairs counted per tile in LDS
+//      histograms, list starts and the launch order from one scan, pairs
+//      written into their lists as keys (depth bits << 32 | record)
+//   2. k_tile_sort_*: each list sorted on that key with bitonic networks
+//      (registers, LDS between waves; long lists in chunks merged by rank;
+//      lists too long for LDS in place in global memory)
+// Otherwise:
+//   1. k_emit_pairs: keys (global tile << 32 | depth bits) in record order,
+//      every thread a run of consecutive pairs, stored coalesced through LDS
+//   2. least-significant-digit radix passes, 8 bits each: block histograms ->
 //      scan of the digit-major histogram matrix (sized by the pair count on
 //      the device, not by the capacity) -> stable scatter, where each wave
 //      ranks its keys by matching digits with eight ballots.  The passes
 //      cover all key bits, or with S3R_SORT_TILES only the tile bits (a stable
-//      partition that leaves every list in emission order).
-//   4. tile ranges from where the tile changes between neighbouring keys; the
+//      partition that leaves every list in emission order)
+//   3. tile ranges from where the tile changes between neighbouring keys; the
 //      tiles' launch order (descending list length)
-//   5. with S3R_SORT_TILES, k_tile_sort_*: each list sorted by (depth bits,
-//      position) with bitonic networks in LDS (long lists in chunks merged by
-//      rank; lists too long for LDS in place in global memory)
+//   4. with S3R_SORT_TILES, k_tile_sort_*: each list sorted by (depth bits,
+//      position in the list)
 // No kernel waits on another workgroup and none uses a contended atomic.
 #include "internal.hpp"
 
@@ -149,7 +155,7 @@ static hipError_t scan_i32(const int32_t* in, const int32_t* n_dev, int64_t n_ca
                            int32_t* sums, int32_t* total, hipStream_t st) {
   const int nb = scan_blocks(n_cap) > 0 ? scan_blocks(n_cap) : 1;
   S3R_LAUNCH(K_SCAN, k_scan_reduce, dim3(nb), dim3(kST), 0, st, in, n_dev, n_cap, sums);
-  if (nb <= kScanFuseMax) {
+  if (nb <= min(kScanFuseMax, tune(S3R_TUNE_SCAN_FUSE_MAX))) {
     S3R_LAUNCH(K_SCAN, k_scan_down<true>, dim3(nb), dim3(kST), 0, st, in, n_dev, n_cap, sums, out,
                total);
   } else {
@@ -176,13 +182,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(SortArgs a) {
   __shared__ uint64_t s_key[kEmitThreads * kEmitPad];
   __shared__ uint32_t s_val[kEmitThreads * kEmitPad];
   const int nrec = a.counters[S3R_CNT_SURV];
-  const int64_t total = a.misc[0];
-  const int64_t ndup = min(total, a.cap_dup);
+  const int64_t ndup = min((int64_t)a.counters[S3R_CNT_DUP], a.cap_dup);
   const int tid = threadIdx.x;
-  if (blockIdx.x == 0 && tid == 0) {
-    a.counters[S3R_CNT_DUP] = (int32_t)ndup;
-    a.counters[S3R_CNT_OVF_DUP] = (int32_t)(total - ndup);
-  }
   // the loop bounds are uniform over the workgroup (it holds barriers)
   for (int64_t P = (int64_t)blockIdx.x * kEmitBlock; P < ndup;
        P += (int64_t)gridDim.x * kEmitBlock) {
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(SortArgs a) {
         else hi = mid - 1;
       }
       int r = lo;
-      int64_t next = (r + 1 < nrec) ? (int64_t)a.pair_off[r + 1] : total;
+      int64_t next = (r + 1 < nrec) ? (int64_t)a.pair_off[r + 1] : ndup;
       int4 rc = a.rec_rect[r];
       int v = a.rec_view[r];
       uint32_t db = __float_as_uint(a.rec_geo[r].w);
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(SortArgs a) {
       for (int64_t p = p0; p < p1; ++p) {
         while (p >= next) {
           ++r;
-          next = (r + 1 < nrec) ? (int64_t)a.pair_off[r + 1] : total;
+          next = (r + 1 < nrec) ? (int64_t)a.pair_off[r + 1] : ndup;
           rc = a.rec_rect[r];
           v = a.rec_view[r];
           db = __float_as_uint(a.rec_geo[r].w);
@@ -483,6 +484,255 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_place(const int32_t* __
 }
 
 // ---------------------------------------------------------------------------
+// tile binning (S3R_SORT_TILES while a tile histogram fits in LDS)
+// ---------------------------------------------------------------------------
+// Each workgroup takes kBinBlock consecutive pairs (in emission order) and
+// counts them per tile in an LDS histogram; k_bin_count adds the non-zero
+// bins to the global counts, k_bin_scan turns the counts into list starts
+// (and the launch order), and k_bin_place claims, per non-zero bin, a block of
+// slots of the tile's list with one atomic on its cursor and writes each pair
+// there as the key (depth bits << 32 | record).  The order inside a list is
+// left arbitrary: the per-list sort orders it by that key, whose record part
+// is the Gaussian order within a view, so the lists come out exactly as a
+// stable sort would leave them.  Same-address atomics are one per tile and
+// workgroup, never one per pair.
+constexpr int kBinThreads = 256;
+constexpr int kBinRun = 16;  // consecutive pairs per thread
+constexpr int kBinBlock = kBinThreads * kBinRun;
+constexpr int kBinMaxTiles = 12288;  // a 48 KB histogram: two workgroups per CU
+constexpr int kBinClaim = 8;         // slot claims in flight per thread
+
+// The records holding the pairs [P, Pe) of this workgroup (each record has at
+// least one pair, so at most Pe - P of them): their first pairs are staged in
+// s_pair[0 .. nw) and s_pair[nw] is the first pair after them.  The two
+// record searches run cooperatively, kBinThreads probes per round (about
+// three rounds of parallel loads instead of a chain of dependent ones per
+// thread).  Returns the first record; *nw_out gets nw.
+__device__ __forceinline__ int record_window(const int32_t* __restrict__ pair_off, int nrec,
+                                             int64_t P, int64_t Pe, int* s_pair, int* s_red,
+                                             int* nw_out) {
+  const int tid = threadIdx.x, wave = tid / kWave;
+  constexpr int NW = kBinThreads / kWave;
+  int lo0 = 0, hi0 = nrec - 1, lo1 = 0, hi1 = nrec - 1;  // last record with first pair <= P, <= Pe - 1
+  while (hi0 > lo0 || hi1 > lo1) {  // uniform over the workgroup
+    const int st0 = (hi0 - lo0 + kBinThreads) / kBinThreads;
+    const int st1 = (hi1 - lo1 + kBinThreads) / kBinThreads;
+    const int i0 = lo0 + tid * st0, i1 = lo1 + tid * st1;
+    const bool ok0 = i0 <= hi0 && pair_off[i0] <= P;
+    const bool ok1 = i1 <= hi1 && pair_off[i1] <= Pe - 1;
+    // first pairs are non-decreasing: the probes that pass form a prefix
+    const uint64_t b0 = ballot(ok0), b1 = ballot(ok1);
+    if ((tid % kWave) == 0) {
+      s_red[wave] = __popcll(b0);
+      s_red[NW + wave] = __popcll(b1);
+    }
+    __syncthreads();
+    int c0 = 0, c1 = 0;
+    for (int w = 0; w < NW; ++w) {
+      c0 += s_red[w];
+      c1 += s_red[NW + w];
+    }
+    __syncthreads();
+    lo0 += (c0 - 1) * st0;
+    hi0 = min(hi0, lo0 + st0 - 1);
+    lo1 += (c1 - 1) * st1;
+    hi1 = min(hi1, lo1 + st1 - 1);
+  }
+  const int nw = lo1 - lo0 + 1;
+  for (int i = tid; i <= nw; i += kBinThreads)
+    s_pair[i] = (lo0 + i < nrec) ? pair_off[lo0 + i] : INT32_MAX;
+  __syncthreads();
+  *nw_out = nw;
+  return lo0;
+}
+
+// the pairs [p0, p1) of this thread (inside the workgroup's window):
+// f(global tile, record, depth bits)
+template <class F>
+__device__ __forceinline__ void walk_pairs(const SortArgs& a, const int* s_pair, int r0, int nw,
+                                           int64_t p0, int64_t p1, F&& f) {
+  int lo = 0, hi = nw - 1;  // last window record whose first pair is at or before p0
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_pair[mid] <= p0) lo = mid;
+    else hi = mid - 1;
+  }
+  int i = lo;
+  int64_t first = s_pair[i], next = s_pair[i + 1];
+  int r = r0 + i;
+  int4 rc = a.rec_rect[r];
+  int v = a.rec_view[r];
+  uint32_t db = __float_as_uint(a.rec_geo[r].w);
+  int gx = (a.wh[2 * v] + a.tile - 1) / a.tile;
+  int tb = a.tile_offset[v];
+  for (int64_t p = p0; p < p1; ++p) {
+    while (p >= next) {
+      ++i;
+      first = next;
+      next = s_pair[i + 1];
+      r = r0 + i;
+      rc = a.rec_rect[r];
+      v = a.rec_view[r];
+      db = __float_as_uint(a.rec_geo[r].w);
+      gx = (a.wh[2 * v] + a.tile - 1) / a.tile;
+      tb = a.tile_offset[v];
+    }
+    const int j = (int)(p - first);
+    const int w = rc.z - rc.x;
+    f(tb + (rc.y + j / w) * gx + rc.x + j % w, r, db);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bin_zero(int32_t* __restrict__ c, int n) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) c[t] = 0;
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_bin_count(SortArgs a) {
+  __shared__ int s_h[kBinMaxTiles];
+  __shared__ int s_pair[kBinBlock + 2];
+  __shared__ int s_red[2 * kBinThreads / kWave];
+  const int nrec = a.counters[S3R_CNT_SURV];
+  const int64_t ndup = min((int64_t)a.counters[S3R_CNT_DUP], a.cap_dup);
+  const int64_t P = (int64_t)blockIdx.x * kBinBlock;
+  if (P >= ndup || nrec <= 0) return;  // uniform over the workgroup
+  const int tid = threadIdx.x;
+  for (int t = tid; t < a.total_tiles; t += kBinThreads) s_h[t] = 0;
+  const int64_t Pe = min(ndup, P + kBinBlock);
+  int nw;
+  const int r0 = record_window(a.pair_off, nrec, P, Pe, s_pair, s_red, &nw);
+  const int64_t p0 = P + (int64_t)tid * kBinRun;
+  const int64_t p1 = min(Pe, p0 + kBinRun);
+  if (p0 < p1)
+    walk_pairs(a, s_pair, r0, nw, p0, p1, [&](int t, int, uint32_t) { atomicAdd(&s_h[t], 1); });
+  __syncthreads();
+  for (int t = tid; t < a.total_tiles; t += kBinThreads)
+    if (s_h[t] != 0) atomicAdd(&a.bin_count[t], s_h[t]);
+}
+
+// One workgroup: list starts (exclusive scan of the counts), list lengths,
+// the slot cursors, each view's pair count, and the rasterizers' launch
+// order -- tiles by descending binary logarithm of the list length (empty
+// lists last), tile order within a bucket -- with the bucket starts the
+// per-list sorts read (order_cnt[b * nchunk], nchunk tile chunks of
+// kOrderChunk).  Global arrays are read and written tile-consecutively
+// through LDS; each thread scans a contiguous run of tiles.
+constexpr int kBinScanThreads = 1024;
+__global__ __launch_bounds__(kBinScanThreads) void k_bin_scan(SortArgs a, int nchunk) {
+  __shared__ int s_c[kOrderBuckets * kBinScanThreads];
+  __shared__ int s_start[kBinMaxTiles + 1];
+  __shared__ int s_w[kBinScanThreads / kWave];
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int T = a.total_tiles;
+  const int per = (T + kBinScanThreads - 1) / kBinScanThreads;
+  const int t0 = min(T, tid * per), t1 = min(T, t0 + per);
+  auto scan = [&](int x, int& total) {
+    const int incl = wave_inclusive_scan(x);
+    if (lane == kWave - 1) s_w[wave] = incl;
+    __syncthreads();
+    int base = 0;
+    total = 0;
+    for (int w = 0; w < kBinScanThreads / kWave; ++w) {
+      if (w < wave) base += s_w[w];
+      total += s_w[w];
+    }
+    __syncthreads();
+    return base + incl - x;
+  };
+  for (int t = tid; t < T; t += kBinScanThreads) {
+    const int c = a.bin_count[t];
+    s_start[t] = c;
+    a.tile_count[t] = c;
+  }
+  for (int b = 0; b < kOrderBuckets; ++b) s_c[b * kBinScanThreads + tid] = 0;
+  __syncthreads();
+  int sum = 0;
+  for (int t = t0; t < t1; ++t) sum += s_start[t];
+  int total;
+  int run = scan(sum, total);
+  for (int t = t0; t < t1; ++t) {
+    const int c = s_start[t];
+    s_start[t] = run;
+    run += c;
+    const int b = c <= 0 ? kOrderBuckets - 1 : 15 - min(15, 31 - __builtin_clz((unsigned)c));
+    s_c[b * kBinScanThreads + tid] += 1;
+  }
+  if (tid == 0) s_start[T] = total;
+  __syncthreads();
+  for (int t = tid; t <= T; t += kBinScanThreads) {
+    const int st = s_start[t];
+    a.tile_start[t] = st;
+    if (t < T) a.bin_cursor[t] = st;
+  }
+  // (bucket, thread) offsets: thread i scans the kOrderBuckets consecutive
+  // entries i * kOrderBuckets .. of the bucket-major linear order
+  int bsum = 0;
+  for (int k = 0; k < kOrderBuckets; ++k) bsum += s_c[tid * kOrderBuckets + k];
+  int btot;
+  int brun = scan(bsum, btot);
+  for (int k = 0; k < kOrderBuckets; ++k) {
+    const int x = s_c[tid * kOrderBuckets + k];
+    s_c[tid * kOrderBuckets + k] = brun;
+    brun += x;
+  }
+  __syncthreads();
+  if (tid < kOrderBuckets) a.order_cnt[tid * nchunk] = s_c[tid * kBinScanThreads];
+  if (tid < a.nv) a.stats[tid * 4 + 3] = s_start[a.tile_offset[tid + 1]] - s_start[a.tile_offset[tid]];
+  __syncthreads();
+  for (int t = t0; t < t1; ++t) {
+    const int c = s_start[t + 1] - s_start[t];
+    const int b = c <= 0 ? kOrderBuckets - 1 : 15 - min(15, 31 - __builtin_clz((unsigned)c));
+    a.tile_order[s_c[b * kBinScanThreads + tid]++] = t;
+  }
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_bin_place(SortArgs a) {
+  __shared__ int s_h[kBinMaxTiles];
+  __shared__ int s_pair[kBinBlock + 2];
+  __shared__ int s_red[2 * kBinThreads / kWave];
+  const int nrec = a.counters[S3R_CNT_SURV];
+  const int64_t ndup = min((int64_t)a.counters[S3R_CNT_DUP], a.cap_dup);
+  const int64_t P = (int64_t)blockIdx.x * kBinBlock;
+  if (P >= ndup || nrec <= 0) return;  // uniform over the workgroup
+  const int tid = threadIdx.x;
+  const int T = a.total_tiles;
+  for (int t = tid; t < T; t += kBinThreads) s_h[t] = 0;
+  const int64_t Pe = min(ndup, P + kBinBlock);
+  int nw;
+  const int r0 = record_window(a.pair_off, nrec, P, Pe, s_pair, s_red, &nw);
+  const int64_t p0 = P + (int64_t)tid * kBinRun;
+  const int64_t p1 = min(Pe, p0 + kBinRun);
+  if (p0 < p1)
+    walk_pairs(a, s_pair, r0, nw, p0, p1, [&](int t, int, uint32_t) { atomicAdd(&s_h[t], 1); });
+  __syncthreads();
+  // this workgroup's block of slots in every list it touches; kBinClaim
+  // claims are in flight before their results are used
+  for (int tb = 0; tb < T; tb += kBinThreads * kBinClaim) {
+    int c[kBinClaim], base[kBinClaim];
+#pragma unroll
+    for (int u = 0; u < kBinClaim; ++u) {
+      const int t = tb + u * kBinThreads + tid;
+      c[u] = t < T ? s_h[t] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBinClaim; ++u) {
+      const int t = tb + u * kBinThreads + tid;
+      base[u] = c[u] != 0 ? atomicAdd(&a.bin_cursor[t], c[u]) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBinClaim; ++u) {
+      const int t = tb + u * kBinThreads + tid;
+      if (c[u] != 0) s_h[t] = base[u];
+    }
+  }
+  __syncthreads();
+  if (p0 < p1)
+    walk_pairs(a, s_pair, r0, nw, p0, p1, [&](int t, int r, uint32_t db) {
+      const int slot = atomicAdd(&s_h[t], 1);
+      a.keys[slot] = ((uint64_t)db << 32) | (uint32_t)r;
+    });
+}
+
+// ---------------------------------------------------------------------------
 // per-tile depth order
 // ---------------------------------------------------------------------------
 // A list of n entries is sorted on the composite key (depth bits << 32 |
@@ -590,34 +840,43 @@ __device__ __forceinline__ void list_of(const int32_t* start, const int32_t* ord
   n = (int)(min((int64_t)start[t + 1], cap) - s0);
 }
 
-// keys [at + base, at + base + 64 E) of this wave's lanes as composite keys
-// (positions from pos0), the largest key past len
+// keys [at + base, at + base + 64 E) of this wave's lanes, the largest key
+// past len.  Binned lists (direct) hold their sort keys (depth bits << 32 |
+// record) already; partitioned ones hold (tile << 32 | depth bits) and become
+// composite keys (depth bits << 32 | position, positions from pos0).
 template <int E>
 __device__ __forceinline__ void load_keys(uint64_t (&x)[E], const uint64_t* __restrict__ keys,
-                                          int64_t at, int base, int len, uint32_t pos0, int lane) {
-  uint32_t d[E];
+                                          int64_t at, int base, int len, uint32_t pos0, int lane,
+                                          bool direct) {
+  uint64_t d[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int p = base + lane * E + e;
-    d[e] = p < len ? (uint32_t)keys[at + p] : 0u;
+    d[e] = p < len ? keys[at + p] : ~0ull;
   }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int p = base + lane * E + e;
-    x[e] = p < len ? (((uint64_t)d[e] << 32) | (pos0 + (uint32_t)p)) : ~0ull;
+    x[e] = (p >= len || direct) ? d[e] : (((uint64_t)(uint32_t)d[e] << 32) | (pos0 + (uint32_t)p));
   }
+}
+
+// the list entry (record index) of a sorted key
+__device__ __forceinline__ uint32_t entry_of(uint64_t x, const uint32_t* __restrict__ vin,
+                                             int64_t s0, bool direct) {
+  return direct ? (uint32_t)x : vin[s0 + (uint32_t)x];
 }
 
 // vout[s0 + p] = vin[s0 + position of sorted key p] for this lane's keys
 template <int E>
 __device__ __forceinline__ void gather_keys(const uint64_t (&x)[E], const uint32_t* __restrict__ vin,
                                             uint32_t* __restrict__ vout, int64_t s0, int base,
-                                            int n, int lane) {
+                                            int n, int lane, bool direct) {
   uint32_t r[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int p = base + lane * E + e;
-    r[e] = p < n ? vin[s0 + (uint32_t)x[e]] : 0u;
+    r[e] = p < n ? entry_of(x[e], vin, s0, direct) : 0u;
   }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -630,11 +889,11 @@ template <int E>
 __device__ __forceinline__ void sort_tiny(const uint64_t* __restrict__ keys,
                                           const uint32_t* __restrict__ vin,
                                           uint32_t* __restrict__ vout, int64_t s0, int n,
-                                          int lane) {
+                                          int lane, bool direct) {
   uint64_t x[E];
-  load_keys<E>(x, keys, s0, 0, n, 0u, lane);
+  load_keys<E>(x, keys, s0, 0, n, 0u, lane, direct);
   NetSort<E, kWave * E>::run(x, lane);
-  gather_keys<E>(x, vin, vout, s0, 0, n, lane);
+  gather_keys<E>(x, vin, vout, s0, 0, n, lane, direct);
 }
 
 // tiny lists, one wave each
@@ -643,22 +902,22 @@ __global__ __launch_bounds__(kWave) void k_tile_sort_tiny(const uint64_t* __rest
                                                           uint32_t* __restrict__ vout,
                                                           const int32_t* __restrict__ start,
                                                           const int32_t* __restrict__ order,
-                                                          int64_t cap) {
+                                                          int64_t cap, bool direct) {
   int64_t s0;
   int n;
   list_of(start, order, blockIdx.x, cap, s0, n);
   const int lane = threadIdx.x;
   if (n >= kTsTiny || n <= 0) return;
   if (n == 1) {
-    if (lane == 0) vout[s0] = vin[s0];
+    if (lane == 0) vout[s0] = direct ? (uint32_t)keys[s0] : vin[s0];
   } else if (n <= kWave) {
-    sort_tiny<1>(keys, vin, vout, s0, n, lane);
+    sort_tiny<1>(keys, vin, vout, s0, n, lane, direct);
   } else if (n <= 2 * kWave) {
-    sort_tiny<2>(keys, vin, vout, s0, n, lane);
+    sort_tiny<2>(keys, vin, vout, s0, n, lane, direct);
   } else if (n <= 4 * kWave) {
-    sort_tiny<4>(keys, vin, vout, s0, n, lane);
+    sort_tiny<4>(keys, vin, vout, s0, n, lane, direct);
   } else {
-    sort_tiny<8>(keys, vin, vout, s0, n, lane);
+    sort_tiny<8>(keys, vin, vout, s0, n, lane, direct);
   }
 }
 
@@ -683,7 +942,7 @@ __global__ __launch_bounds__(256) void k_tile_sort_chunks(uint64_t* __restrict__
                                                           const int32_t* __restrict__ start,
                                                           const int32_t* __restrict__ order,
                                                           const int32_t* __restrict__ ocnt,
-                                                          int nchunk, int64_t cap) {
+                                                          int nchunk, int64_t cap, bool direct) {
   __shared__ uint64_t s[kTsChunk];
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int base = wave * kTsWaveKeys;
@@ -707,7 +966,7 @@ __global__ __launch_bounds__(256) void k_tile_sort_chunks(uint64_t* __restrict__
     if (c0 >= n) continue;
     const int len = min(kTsChunk, n - c0);
     uint64_t x[kTsE];
-    load_keys<kTsE>(x, keys, s0 + c0, base, len, (uint32_t)c0, lane);
+    load_keys<kTsE>(x, keys, s0 + c0, base, len, (uint32_t)c0, lane, direct);
     NetSort<kTsE, kTsWaveKeys>::run(x, lane);
     const int mtop = next_pow2(len);  // merges above this size leave the keys in place
     for (int k = 2 * kTsWaveKeys; k <= mtop; k <<= 1) {
@@ -727,7 +986,7 @@ __global__ __launch_bounds__(256) void k_tile_sort_chunks(uint64_t* __restrict__
       NetMerge<kTsE, 4 * kTsChunk, kTsWaveKeys / 2>::run(x, lane);
     }
     if (n < kTsChunk) {
-      gather_keys<kTsE>(x, vin, vout, s0, base, n, lane);
+      gather_keys<kTsE>(x, vin, vout, s0, base, n, lane, direct);
     } else {
 #pragma unroll
       for (int e = 0; e < kTsE; ++e) {
@@ -741,10 +1000,11 @@ __global__ __launch_bounds__(256) void k_tile_sort_chunks(uint64_t* __restrict__
 // lists of kTsLarge entries or more: the same network on the keys in global
 // memory (rewritten in place as composite keys), by one workgroup
 __device__ void sort_list_global(uint64_t* __restrict__ keys, const uint32_t* __restrict__ vin,
-                                 uint32_t* __restrict__ vout, int64_t s0, int n) {
+                                 uint32_t* __restrict__ vout, int64_t s0, int n, bool direct) {
   uint64_t* g = keys + s0;
-  for (int q = threadIdx.x; q < n; q += blockDim.x)
-    g[q] = ((uint64_t)(uint32_t)g[q] << 32) | (uint32_t)q;
+  if (!direct)
+    for (int q = threadIdx.x; q < n; q += blockDim.x)
+      g[q] = ((uint64_t)(uint32_t)g[q] << 32) | (uint32_t)q;
   __syncthreads();
   const int m = next_pow2(n);
   for (int k = 2; k <= m; k <<= 1) {
@@ -762,7 +1022,7 @@ __device__ void sort_list_global(uint64_t* __restrict__ keys, const uint32_t* __
       __syncthreads();
     }
   }
-  for (int q = threadIdx.x; q < n; q += blockDim.x) vout[s0 + q] = vin[s0 + (uint32_t)g[q]];
+  for (int q = threadIdx.x; q < n; q += blockDim.x) vout[s0 + q] = entry_of(g[q], vin, s0, direct);
   __syncthreads();
 }
 
@@ -781,7 +1041,7 @@ __global__ __launch_bounds__(1024) void k_tile_sort_merge(uint64_t* __restrict__
                                                           const int32_t* __restrict__ start,
                                                           const int32_t* __restrict__ order,
                                                           const int32_t* __restrict__ ocnt,
-                                                          int nchunk, int64_t cap) {
+                                                          int nchunk, int64_t cap, bool direct) {
   constexpr int NTH = 1024, EL = kTsLarge / NTH, E = kTsMergeSlice / NTH;
   constexpr int SLICES = kTsLarge / kTsMergeSlice;
   __shared__ uint64_t s[kTsLarge];
@@ -793,7 +1053,7 @@ __global__ __launch_bounds__(1024) void k_tile_sort_merge(uint64_t* __restrict__
     int n;
     if (item < lh) {
       list_of(start, order, (int)item, cap, s0, n);
-      sort_list_global(keys, vin, vout, s0, n);
+      sort_list_global(keys, vin, vout, s0, n, direct);
       continue;
     }
     const int i = lh + (int)((item - lh) / SLICES);
@@ -844,7 +1104,7 @@ __global__ __launch_bounds__(1024) void k_tile_sort_merge(uint64_t* __restrict__
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int q = q0 + threadIdx.x + e * NTH;
-      r[e] = q < qe ? vin[s0 + (uint32_t)x[e]] : 0u;
+      r[e] = q < qe ? entry_of(x[e], vin, s0, direct) : 0u;
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -869,48 +1129,63 @@ size_t order_count_words(int total_tiles) {
 }
 
 hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
-  // 1. pairs per record -> first pair of each record
-  hipError_t e = scan_i32(a.rec_npairs, a.counters + S3R_CNT_SURV, a.cap_surv, a.pair_off,
-                          a.scan_sums, a.misc, st);
-  if (e != hipSuccess) return e;
-  // radix passes over the tile bits only (then a depth sort per list) or over
-  // all key bits; the values of a full sort end in the caller's array
-  const int passes = sort_passes(a.total_tiles, a.by_tile);
-  const int shift0 = a.by_tile ? 32 : 0;
-  const int nblk = scan_blocks(a.cap_dup) > 0 ? scan_blocks(a.cap_dup) : 1;
-  uint64_t* kb[2] = {a.keys, a.keys_alt};
-  uint32_t* vb[2] = {a.vals0, a.vals1};
-  if (!a.by_tile) vb[passes & 1] = a.vals_out;
-  // 2. emit (tile, depth) keys in record order
-  {
-    SortArgs ea = a;
-    ea.vals0 = vb[0];
-    const int64_t want = (a.cap_dup + kEmitBlock - 1) / kEmitBlock;
-    const int grid = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
-    S3R_LAUNCH(K_EMIT, k_emit_pairs, dim3(grid), dim3(kEmitThreads), 0, st, ea);
-  }
-  // 3. radix passes
-  for (int p = 0; p < passes; ++p) {
-    const int shift = shift0 + 8 * p;
-    const int src = p & 1, dst = src ^ 1;
-    S3R_LAUNCH(K_RADIX, k_radix_hist, dim3(nblk), dim3(kRT), 0, st, kb[src],
-               a.counters + S3R_CNT_DUP, shift, a.hist, a.misc + 2);
-    e = scan_i32(a.hist, a.misc + 2, (int64_t)256 * nblk, a.hist, a.scan_sums, a.misc + 1, st);
-    if (e != hipSuccess) return e;
-    S3R_LAUNCH(K_RADIX, k_radix_scatter, dim3(nblk), dim3(kRT), 0, st, kb[src], vb[src], kb[dst],
-               vb[dst], a.counters + S3R_CNT_DUP, shift, a.hist);
-  }
-  uint64_t* parted = kb[passes & 1];
-  const uint32_t* pvals = vb[passes & 1];
-  // 4. tile ranges and the launch order
-  {
-    const int64_t want = (a.cap_dup + 1 + 255) / 256;
-    const int grid = (int)(want < 1024 ? want : 1024);
-    S3R_LAUNCH(K_TILE_RANGES, k_tile_ranges, dim3(grid), dim3(256), 0, st, parted,
-               a.counters + S3R_CNT_DUP, a.total_tiles, a.tile_start);
-  }
-  {
-    const int nchunk = (a.total_tiles + kOrderChunk - 1) / kOrderChunk;
+  const int nchunk = (a.total_tiles + kOrderChunk - 1) / kOrderChunk;
+  // pairs in emission order come from s3r_project_cull (a.pair_off, the pair
+  // count in counters[S3R_CNT_DUP]); launch grids are sized by the capacity
+  // and workgroups past the pair count return at once
+  const int64_t bin_grid = (a.cap_dup + kBinBlock - 1) / kBinBlock;
+  const bool binned =
+      a.by_tile && a.total_tiles <= min(kBinMaxTiles, tune(S3R_TUNE_BIN_MAX_TILES));
+  const uint64_t* parted = a.keys;
+  const uint32_t* pvals = a.vals0;
+  if (binned) {
+    // 1. pairs per tile, 2. list starts and launch order, 3. pairs into
+    // their lists as (depth bits << 32 | record) keys
+    S3R_LAUNCH(K_TILE_BIN, k_bin_zero, dim3((a.total_tiles + 255) / 256), dim3(256), 0, st,
+               a.bin_count, a.total_tiles);
+    S3R_LAUNCH(K_TILE_BIN, k_bin_count, dim3((unsigned)(bin_grid > 0 ? bin_grid : 1)),
+               dim3(kBinThreads), 0, st, a);
+    S3R_LAUNCH(K_TILE_BIN, k_bin_scan, dim3(1), dim3(kBinScanThreads), 0, st, a, nchunk);
+    S3R_LAUNCH(K_TILE_BIN, k_bin_place, dim3((unsigned)(bin_grid > 0 ? bin_grid : 1)),
+               dim3(kBinThreads), 0, st, a);
+  } else {
+    // radix passes over the tile bits only (then a depth sort per list) or
+    // over all key bits; the values of a full sort end in the caller's array
+    const int passes = sort_passes(a.total_tiles, a.by_tile);
+    const int shift0 = a.by_tile ? 32 : 0;
+    const int nblk = scan_blocks(a.cap_dup) > 0 ? scan_blocks(a.cap_dup) : 1;
+    uint64_t* kb[2] = {a.keys, a.keys_alt};
+    uint32_t* vb[2] = {a.vals0, a.vals1};
+    if (!a.by_tile) vb[passes & 1] = a.vals_out;
+    // 1. emit (tile, depth) keys in record order
+    {
+      SortArgs ea = a;
+      ea.vals0 = vb[0];
+      const int64_t want = (a.cap_dup + kEmitBlock - 1) / kEmitBlock;
+      const int grid = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+      S3R_LAUNCH(K_EMIT, k_emit_pairs, dim3(grid), dim3(kEmitThreads), 0, st, ea);
+    }
+    // 2. radix passes
+    for (int p = 0; p < passes; ++p) {
+      const int shift = shift0 + 8 * p;
+      const int src = p & 1, dst = src ^ 1;
+      S3R_LAUNCH(K_RADIX, k_radix_hist, dim3(nblk), dim3(kRT), 0, st, kb[src],
+                 a.counters + S3R_CNT_DUP, shift, a.hist, a.misc + 2);
+      hipError_t e = scan_i32(a.hist, a.misc + 2, (int64_t)256 * nblk, a.hist, a.scan_sums,
+                              a.misc + 1, st);
+      if (e != hipSuccess) return e;
+      S3R_LAUNCH(K_RADIX, k_radix_scatter, dim3(nblk), dim3(kRT), 0, st, kb[src], vb[src],
+                 kb[dst], vb[dst], a.counters + S3R_CNT_DUP, shift, a.hist);
+    }
+    parted = kb[passes & 1];
+    pvals = vb[passes & 1];
+    // 3. tile ranges and the launch order
+    {
+      const int64_t want = (a.cap_dup + 1 + 255) / 256;
+      const int grid = (int)(want < 1024 ? want : 1024);
+      S3R_LAUNCH(K_TILE_RANGES, k_tile_ranges, dim3(grid), dim3(256), 0, st, parted,
+                 a.counters + S3R_CNT_DUP, a.total_tiles, a.tile_start);
+    }
     if (nchunk > 0)
       S3R_LAUNCH(K_TILE_ORDER, k_order_count, dim3(nchunk), dim3(kOrderThreads), 0, st,
                  a.tile_start, a.total_tiles, nchunk, a.order_cnt, a.tile_count);
@@ -920,17 +1195,17 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
       S3R_LAUNCH(K_TILE_ORDER, k_order_place, dim3(nchunk), dim3(kOrderThreads), 0, st,
                  a.tile_start, a.total_tiles, nchunk, a.order_cnt, a.tile_order);
   }
-  // 5. depth order inside every list, written to the caller's value array
+  // 4. depth order inside every list, written to the caller's value array
   if (a.by_tile) {
-    const int nchunk = (a.total_tiles + kOrderChunk - 1) / kOrderChunk;
+    uint64_t* keys = const_cast<uint64_t*>(parted);
     S3R_LAUNCH(K_TILE_SORT_CHUNKS, k_tile_sort_chunks, dim3(kTsChunkBlocks), dim3(256), 0, st,
-               parted, pvals, a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk,
-               a.cap_dup);
+               keys, pvals, a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk,
+               a.cap_dup, binned);
     S3R_LAUNCH(K_TILE_SORT_MERGE, k_tile_sort_merge, dim3(kTsMergeBlocks), dim3(1024), 0, st,
-               parted, pvals, a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk,
-               a.cap_dup);
-    S3R_LAUNCH(K_TILE_SORT, k_tile_sort_tiny, dim3(a.total_tiles), dim3(kWave), 0, st, parted,
-               pvals, a.vals_out, a.tile_start, a.tile_order, a.cap_dup);
+               keys, pvals, a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk,
+               a.cap_dup, binned);
+    S3R_LAUNCH(K_TILE_SORT, k_tile_sort_tiny, dim3(a.total_tiles), dim3(kWave), 0, st, keys,
+               pvals, a.vals_out, a.tile_start, a.tile_order, a.cap_dup, binned);
   }
   return hipGetLastError();
 }

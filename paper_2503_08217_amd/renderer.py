@@ -150,7 +150,7 @@ class Renderer:
         self.stats = torch.zeros(V, 4, device=d, dtype=i32)
         self.rec_npairs = torch.zeros(cs, device=d, dtype=i32)
         self.surv = torch.zeros(V, self.mask_words, device=d, dtype=i32)
-        self.bstat = torch.zeros((n + 255) // 256 * V * 4 + 4, device=d, dtype=i32)
+        self.bstat = torch.zeros((n + 255) // 256 * V * A.BSTAT + 4, device=d, dtype=i32)
         self.tile_count = torch.zeros(self.total_tiles, device=d, dtype=i32)
         self.tile_start = torch.zeros(self.total_tiles + 1, device=d, dtype=i32)
         self.tile_order = torch.zeros(max(1, self.total_tiles), device=d, dtype=i32)
@@ -211,9 +211,9 @@ class Renderer:
             _ptr(self.cam), _ptr(self.cen), _ptr(self.t_norm), _ptr(self.mask), _ptr(self.rec_gid),
             _ptr(self.rec_view), _ptr(self.rec_geo), _ptr(self.rec_conic), _ptr(self.rec_rgb),
             _ptr(self.rec_rect), _ptr(self.counters), _ptr(self.stats), _ptr(self.rec_npairs),
-            _ptr(self.surv), _ptr(self.bstat))
+            _ptr(self.surv), _ptr(self.bstat), _ptr(self.rec_pair))
         self.c_bins = A.S3RBins(_ptr(self.tile_count), _ptr(self.tile_start), _ptr(self.vals),
-                                _ptr(self.tile_order), _ptr(self.rec_pair))
+                                _ptr(self.tile_order))
         self.c_img = A.S3RImage(_ptr(self.color), _ptr(self.T_final), _ptr(self.last),
                                 _ptr(self.m_raster), _ptr(self.rec_taken), self.n, None)
         self.c_img_census = A.S3RImage(_ptr(self.color), _ptr(self.T_final), _ptr(self.last),

@@ -35,7 +35,7 @@ def test_every_header_symbol_is_exported(lib):
 
 
 def test_version_and_status(lib):
-    assert lib.s3r_abi_version() == 1
+    assert lib.s3r_abi_version() == 2
     assert lib.s3r_status_string(0) == b"ok"
     assert b"aligned" in lib.s3r_status_string(-2)
 
@@ -44,8 +44,8 @@ def test_struct_sizes_match_c_layout():
     assert C.sizeof(A.S3RParams) == 96
     assert C.sizeof(A.S3RScene) == 11 * 8 + 8 + 16
     assert C.sizeof(A.S3RViews) == 7 * 8 + 16
-    assert C.sizeof(A.S3RProjected) == 15 * 8
-    assert C.sizeof(A.S3RBins) == 5 * 8
+    assert C.sizeof(A.S3RProjected) == 16 * 8
+    assert C.sizeof(A.S3RBins) == 4 * 8
     assert C.sizeof(A.S3RGrads) == 11 * 8
     assert C.sizeof(A.S3RImage) == 7 * 8
     assert C.sizeof(A.S3RSizes) == 40
@@ -82,7 +82,7 @@ def test_host_validation_codes(lib):
     ptr = C.c_void_p(al)
     scene = A.S3RScene(*([ptr] * 9), C.c_void_p(0), C.c_void_p(0), 4, 0, 1, 1, 0)
     views = A.S3RViews(*([ptr] * 6), C.c_void_p(0), 1, 1, 64)
-    proj = A.S3RProjected(*([ptr] * 15))
+    proj = A.S3RProjected(*([ptr] * 16))
     p = _params()
     ws = C.c_void_p(al)
     # NULL scene
@@ -130,7 +130,7 @@ def test_noalloc_rejects_problem_beyond_its_scratch(lib):
     al = base + (16 - base % 16) % 16
     ptr = C.c_void_p(al)
     views = A.S3RViews(*([ptr] * 6), C.c_void_p(0), 64, 1, 64)
-    proj = A.S3RProjected(*([ptr] * 15))
+    proj = A.S3RProjected(*([ptr] * 16))
     p = _params()
     big = A.S3RScene(*([ptr] * 9), C.c_void_p(0), C.c_void_p(0), 60_000_000, 0, 1, 1, 0)
     z = A.S3RSizes(60_000_000, 64, 1, 16, 64, 1, 0)
@@ -145,3 +145,21 @@ def test_noalloc_rejects_problem_beyond_its_scratch(lib):
     p_bad = _params(tile=12)
     assert lib.s3r_project_cull_noalloc(C.byref(big), C.byref(views), C.byref(p_bad),
                                         C.byref(proj), None) == A.S3R_E_SIZE
+
+
+def test_tuning_knobs(lib):
+    """Launch-shape knobs: defaults, range checks, restore with a negative
+    value (host-side state only)."""
+    v = C.c_int32(-1)
+    assert lib.s3r_get_tuning(A.S3R_TUNE_BIN_MAX_TILES, C.byref(v)) == 0 and v.value == 12288
+    assert lib.s3r_get_tuning(A.S3R_TUNE_RASTER_WAVES, C.byref(v)) == 0 and v.value == 1
+    assert lib.s3r_set_tuning(99, 1) == A.S3R_E_ARG
+    assert lib.s3r_get_tuning(99, C.byref(v)) == A.S3R_E_ARG
+    assert lib.s3r_set_tuning(A.S3R_TUNE_BIN_MAX_TILES, 12289) == A.S3R_E_ARG
+    assert lib.s3r_set_tuning(A.S3R_TUNE_RASTER_WAVES, 0) == A.S3R_E_ARG
+    old = A.set_tuning(offset_fuse_max=0, bin_max_tiles=0, raster_waves=4)
+    assert old == {"offset_fuse_max": 1024, "bin_max_tiles": 12288, "raster_waves": 1}
+    assert A.get_tuning()["raster_waves"] == 4
+    A.set_tuning(offset_fuse_max=-1, bin_max_tiles=-1, raster_waves=-1)
+    assert A.get_tuning() == {"offset_fuse_max": 1024, "scan_fuse_max": 1024,
+                              "bin_max_tiles": 12288, "raster_waves": 1}

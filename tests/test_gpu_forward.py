@@ -220,25 +220,44 @@ def test_rendering_visibility_parity(which):
         assert took.sum() > 0
 
 
-def test_scan_paths_agree():
-    """The pair-offset scan takes two launches up to 1024 blocks of 4096
-    records and three beyond; a record capacity of 4.4M (1075 blocks) gives
-    the same first pairs, lists and image as the default capacity."""
-    cfg = scenes.make_config(1)
-    banner("scan paths")
+@pytest.mark.parametrize("which", ["config1", "config2"])
+def test_launch_paths_agree(which):
+    """Every launch path gives the same records, first pairs, lists, launch
+    order and image bit for bit: the record/pair offset scan in two launches
+    or three (with the top scan), the radix histogram scans likewise, tile
+    binning or the radix tile partition, the full radix sort, and forward
+    workgroups of one wave or of a whole tile's sub-tiles."""
+    from paper_2503_08217_amd import _abi as A
+    if which == "config1":
+        c = scenes.make_config(1)
+        views, p = c.views, c.params
+    else:
+        c = scenes.make_config(2, scale_n=0.1)
+        views, p = c.views.subset([3, 27, 44]), c.params
+    variants = [dict(), dict(offset_fuse_max=0, scan_fuse_max=0), dict(bin_max_tiles=0),
+                dict(raster_waves=16), dict(sort="global", scan_fuse_max=0)]
     out = []
-    for cap in (None, 4_400_000):
-        r = make_renderer(cfg.scene, cfg.views, cfg.params, cap_surv=cap, cap_dup=1_000_000)
-        r.forward()
-        c = r.read_counters()
-        n, nd = c["n_surv"], int(r.counters.cpu().numpy()[2])
-        out.append((r.rec_pair[:n].cpu().numpy().copy(), r.tile_start.cpu().numpy().copy(),
-                    r.vals.cpu().numpy()[:nd].copy(),
-                    np.stack([image_np(r, v) for v in range(r.V)])))
-    first = out[0][0]
-    assert first[0] == 0 and np.all(np.diff(first) >= 0) and first[-1] < out[0][2].shape[0]
-    for a, b in zip(out[0], out[1]):
-        np.testing.assert_array_equal(a, b)
+    try:
+        for var in variants:
+            knobs = {k: v for k, v in var.items() if k != "sort"}
+            A.set_tuning(**knobs)
+            banner(f"launch paths {which} {var}")
+            r = make_renderer(c.scene, views, dict(p, sort=var.get("sort", "tiles")))
+            r.forward()
+            cnt = r.read_counters()
+            n, nd = cnt["n_surv"], cnt["n_dup"]
+            out.append((r.rec_gid[:n].cpu().numpy().copy(), r.rec_pair[:n].cpu().numpy().copy(),
+                        r.tile_start.cpu().numpy().copy(), r.vals.cpu().numpy()[:nd].copy(),
+                        r.tile_order.cpu().numpy().copy(), r.stats.cpu().numpy().copy(),
+                        r.color.cpu().numpy().copy()))
+            A.set_tuning(**{k: -1 for k in knobs})
+    finally:
+        A.set_tuning(**{k: -1 for k in A.TUNE_KNOBS})
+    first = out[0][1]
+    assert first[0] == 0 and np.all(np.diff(first) > 0)
+    for o in out[1:]:
+        for a_, b_ in zip(out[0], o):
+            np.testing.assert_array_equal(a_, b_)
 
 
 def test_work_census():

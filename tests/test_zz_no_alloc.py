@@ -14,14 +14,16 @@ pytestmark = [pytest.mark.gpu, needs_gpu]
 
 torch = pytest.importorskip("torch")
 
+from paper_2503_08217_amd import _abi as A  # noqa: E402
+
 
 def poison(r):
     """Outputs of project_cull start from garbage so that an entry the call
     does not write shows up."""
     for t in (r.cam, r.cen, r.t_norm, r.rec_geo, r.rec_conic, r.rec_rgb):
         t.fill_(float("nan"))
-    for t in (r.mask, r.surv, r.rec_gid, r.rec_view, r.rec_rect, r.rec_npairs, r.counters,
-              r.stats, r.bstat):
+    for t in (r.mask, r.surv, r.rec_gid, r.rec_view, r.rec_rect, r.rec_npairs, r.rec_pair,
+              r.counters, r.stats, r.bstat):
         t.fill_(-7)
 
 
@@ -32,8 +34,9 @@ def outputs(r):
     o = {k: getattr(r, k).cpu().numpy().copy() for k in ("cam", "cen", "t_norm", "mask", "surv",
                                                          "stats")}
     o["counters"] = r.counters[:4].cpu().numpy().copy()
-    o["bstat"] = r.bstat[: nblk * r.V * 4].cpu().numpy().copy()
-    for k in ("rec_gid", "rec_view", "rec_geo", "rec_conic", "rec_rgb", "rec_rect", "rec_npairs"):
+    o["bstat"] = r.bstat[: nblk * r.V * A.BSTAT].cpu().numpy().copy()
+    for k in ("rec_gid", "rec_view", "rec_geo", "rec_conic", "rec_rgb", "rec_rect", "rec_npairs",
+              "rec_pair"):
         o[k] = getattr(r, k)[:n].cpu().numpy().copy()
     return o
 

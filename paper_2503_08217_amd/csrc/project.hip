@@ -528,40 +528,58 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_records(ProjArgs a) {
   const int B = (a.sh_deg + 1) * (a.sh_deg + 1);
   const int n_keep = a.counters[S3R_CNT_SURV];  // records kept (min(survivors, cap_surv))
   const int lane = tid;
-  // the loop bound is uniform over the wave (it holds shuffles)
-  for (int it0 = 0; it0 < total; it0 += kRecThreads) {
-    const int item = it0 + lane;
-    const bool live = item < total;
-    int v = 0, k = 0, i = 0;
-    int64_t slot = INT64_MAX;
-    if (live) {
-      while (s_pre[v + 1] <= item) ++v;
-      k = item - s_pre[v];
-      slot = (int64_t)a.bstat[((size_t)vb * a.nv + v) * kBstat + 3] + k;
-      int w = 0, kk = k;
-      while (kk >= __popcll(s_w[v][w])) {
-        kk -= __popcll(s_w[v][w]);
-        ++w;
-      }
-      i = vb * kProjBlock + w * kWave + select_bit(s_w[v][w], kk);
+  // survivor `item` of the block (survivors in (view, Gaussian) order):
+  // its view, its record slot and its Gaussian
+  auto locate = [&](int item, int& v, int64_t& slot, int& i) {
+    v = 0;
+    while (s_pre[v + 1] <= item) ++v;
+    const int k = item - s_pre[v];
+    slot = (int64_t)a.bstat[((size_t)vb * a.nv + v) * kBstat + 3] + k;
+    int w = 0, kk = k;
+    while (kk >= __popcll(s_w[v][w])) {
+      kk -= __popcll(s_w[v][w]);
+      ++w;
     }
+    i = vb * kProjBlock + w * kWave + select_bit(s_w[v][w], kk);
+  };
+  // pass 1: projection and the geometric part of the records (and each
+  // record's pair count)
+  for (int item = lane; item < total; item += kRecThreads) {
+    int v, i;
+    int64_t slot;
+    locate(item, v, slot, i);
+    if (slot >= a.kp.cap_surv) continue;
     Loaded g;
-    load_gaussian(a, i, live, plain, g);
+    load_gaussian(a, i, true, plain, g);
     Loaded e;
     float P[12], fx, fy, cx, cy;
     int W, H;
+    view_geometry(a, v, g, plain, i, e, P, fx, fy, cx, cy, W, H);
     Proj o;
-    int npairs = 0;
-    if (live) {
-      view_geometry(a, v, g, plain, i, e, P, fx, fy, cx, cy, W, H);
-      project_canonical(P, e.mx, e.my, e.mz, e.R, e.s0, e.s1, e.s2, fx, fy, cx, cy, W, H, a.kp,
-                        o, i, v);
-      npairs = (o.x1 - o.x0) * (o.y1 - o.y0);
-    }
+    project_canonical(P, e.mx, e.my, e.mz, e.R, e.s0, e.s1, e.s2, fx, fy, cx, cy, W, H, a.kp, o,
+                      i, v);
+    a.rec_gid[slot] = i;
+    a.rec_view[slot] = v;
+    a.rec_geo[slot] = make_float4(o.u, o.v, a.opac[i], o.pz);
+    a.rec_conic[slot] = make_float4(o.c / o.det, (-o.b) / o.det, o.a / o.det, 0.f);
+    a.rec_rect[slot] = make_int4(o.x0, o.y0, o.x1, o.y1);
+    a.rec_npairs[slot] = (o.x1 - o.x0) * (o.y1 - o.y0);
+  }
+  // pass 2 (each item on the lane that wrote it): first pairs and colours.
+  // The loop bound is uniform over the wave (it holds a wave scan).
+  for (int it0 = 0; it0 < total; it0 += kRecThreads) {
+    const int item = it0 + lane;
+    const bool live = item < total;
+    int v = 0, i = 0;
+    int64_t slot = INT64_MAX;
+    if (live) locate(item, v, slot, i);
+    const bool kept = live && slot < a.kp.cap_surv;
+    const int npairs = kept ? a.rec_npairs[slot] : 0;
     // first pair of each item: its (block, view)'s first pair plus the pairs
     // of the view's items before it -- a scan over the wave in item order,
     // rebased at the first lane of each view's run and carried across
-    // iterations in LDS
+    // iterations in LDS (records past cap_surv are a suffix: their zeros
+    // change no kept record's first pair)
     const int incl = wave_inclusive_scan(npairs);
     const int excl = incl - npairs;
     const bool run_start = live && (lane == 0 || item == s_pre[v]);
@@ -572,37 +590,33 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_records(ProjArgs a) {
                                 : 0;
     if (run_end) s_carry[v] = s_base[v] + incl;
     __syncthreads();
-    if (!live || slot >= a.kp.cap_surv) continue;
+    if (!kept) continue;
     // the last kept record settles the pair counters: pairs beyond it, or
     // beyond cap_dup, are dropped
     if (slot == n_keep - 1) {
       const int64_t all = a.counters[S3R_CNT_PAIRS];
-      const int64_t kept = min((int64_t)first_pair + npairs, a.kp.cap_dup);
-      a.counters[S3R_CNT_DUP] = (int32_t)kept;
-      a.counters[S3R_CNT_OVF_DUP] = (int32_t)max((int64_t)0, all - kept);
+      const int64_t kept_pairs = min((int64_t)first_pair + npairs, a.kp.cap_dup);
+      a.counters[S3R_CNT_DUP] = (int32_t)kept_pairs;
+      a.counters[S3R_CNT_OVF_DUP] = (int32_t)max((int64_t)0, all - kept_pairs);
     }
-    // the geometric part of the record is stored before the colour is
-    // evaluated, so its registers are free for the SH coefficients
-    a.rec_gid[slot] = i;
-    a.rec_view[slot] = v;
-    a.rec_geo[slot] = make_float4(o.u, o.v, a.opac[i], o.pz);
-    a.rec_conic[slot] = make_float4(o.c / o.det, (-o.b) / o.det, o.a / o.det, 0.f);
-    a.rec_rect[slot] = make_int4(o.x0, o.y0, o.x1, o.y1);
-    a.rec_npairs[slot] = npairs;
     a.rec_pair[slot] = first_pair;
 
     // viewing direction in the instance-local frame
+    const int kslot = clampi(a.inst[i], 0, a.n_slots - 1);
     float dx, dy, dz;
     if (plain) {
+      const float* mw = a.mean_w + ((size_t)a.plain_slot[v] * a.n + i) * 3;
       const float4 cw = reinterpret_cast<const float4*>(a.cen)[(size_t)v * a.n_slots];
-      const float wx = e.mx - cw.x, wy = e.my - cw.y, wz = e.mz - cw.z;
-      const float* G = a.pose + ((size_t)clampi(a.tstep[v], 0, a.n_ts - 1) * a.n_slots + g.k) * 12;
+      const float wx = mw[0] - cw.x, wy = mw[1] - cw.y, wz = mw[2] - cw.z;
+      const float* G = a.pose + ((size_t)clampi(a.tstep[v], 0, a.n_ts - 1) * a.n_slots + kslot) * 12;
       dx = (G[0] * wx + G[4] * wy) + G[8] * wz;
       dy = (G[1] * wx + G[5] * wy) + G[9] * wz;
       dz = (G[2] * wx + G[6] * wy) + G[10] * wz;
     } else {
-      const float4 ce = reinterpret_cast<const float4*>(a.cen)[(size_t)v * a.n_slots + g.k];
-      dx = g.mx - ce.x; dy = g.my - ce.y; dz = g.mz - ce.z;
+      const float4 ce = reinterpret_cast<const float4*>(a.cen)[(size_t)v * a.n_slots + kslot];
+      dx = a.mean[3 * i] - ce.x;
+      dy = a.mean[3 * i + 1] - ce.y;
+      dz = a.mean[3 * i + 2] - ce.z;
     }
     const float nrm = sqrtf((dx * dx + dy * dy) + dz * dz);
     dx = dx / nrm; dy = dy / nrm; dz = dz / nrm;

@@ -87,13 +87,21 @@ enum {
   S3R_GRAD_SPARSE = 16, /* s3r_raster_bwd clears only the gradient rows it
                        wrote on the previous call (S3RGrads.rows) instead of
                        the whole arrays; streamlined route only            */
-  S3R_SORT_TILES = 32  /* s3r_sort partitions the pairs by tile (radix passes
-                       over the tile bits only) and orders each list by depth
-                       in LDS: fastest when lists are short (a few thousand
-                       entries, as with the LOD cull); lists of 16384 entries
-                       or more take a slow one-workgroup path.  Without the
-                       flag a radix sort over all key bits orders every list,
-                       whatever its length.  Both give the same order.      */
+  S3R_SORT_TILES = 32, /* s3r_sort bins the pairs by tile (or partitions them
+                       by radix passes over the tile bits) and orders each
+                       list by depth in registers / LDS: fastest when lists
+                       are short (a few thousand entries, as with the LOD
+                       cull); lists of 16384 entries or more take a slow
+                       one-workgroup path.  Without the flag a radix sort over
+                       all key bits orders every list, whatever its length.
+                       Both give the same order.                            */
+  S3R_DETERMINISTIC_GRADS = 64 /* s3r_raster_bwd sums every gradient in a fixed
+                       order (per-wave window copies added in wave order,
+                       per-record slot sums in emission order with no
+                       atomics, camera gradients in 2^-32 fixed point), so two
+                       calls on the same inputs give bitwise equal gradients;
+                       slower.  Streamlined route only (with S3R_PLAIN:
+                       S3R_E_ARG).                                          */
 };
 
 /* modes of s3r_update_visibility */

@@ -18,6 +18,7 @@ S3R_E_NULL, S3R_E_ALIGN, S3R_E_SIZE, S3R_E_WORKSPACE, S3R_E_HIP, S3R_E_ARG = -1,
 S3R_E_SCRATCH = -7
 S3R_TEMPORAL, S3R_LOD, S3R_PLAIN, S3R_LOD_STOCHASTIC, S3R_GRAD_SPARSE = 1, 2, 4, 8, 16
 S3R_SORT_TILES = 32
+S3R_DETERMINISTIC_GRADS = 64
 S3R_VIS_UPDATE, S3R_VIS_FOLD, S3R_VIS_RESET = 0, 1, 2
 S3R_WS_PROJECT, S3R_WS_SORT, S3R_WS_BACKWARD = 0, 1, 2
 S3R_TUNE_OFFSET_FUSE_MAX, S3R_TUNE_SCAN_FUSE_MAX, S3R_TUNE_BIN_MAX_TILES = 0, 1, 2

@@ -39,15 +39,28 @@ __device__ __forceinline__ int64_t pair_slot(const int32_t* __restrict__ rec_pai
   return (int64_t)rec_pair[r] + (int64_t)(ty - rc.y) * (rc.z - rc.x) + (tx - rc.x);
 }
 
-template <int TS>
+// window of list entries whose sums a tile keeps in LDS; the deterministic
+// variant keeps one copy per wave (summed in wave order at the flush), in at
+// most 36 KB
+template <int TS, bool DET>
+struct BwdWindow {
+  static constexpr int NW = RasterShape<TS>::NW;
+  static constexpr int WIN_DET = 512 / NW < 64 ? 64 : 512 / NW;
+  static constexpr int WIN = DET && WIN_DET < RasterShape<TS>::WIN ? WIN_DET : RasterShape<TS>::WIN;
+  static constexpr int COPIES = DET ? NW : 1;
+};
+
+template <int TS, bool DET>
 // (64 VGPRs: eight waves per SIMD)
 __global__ __launch_bounds__(RasterShape<TS>::NT)
 __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
   constexpr int NT = RasterShape<TS>::NT, NW = RasterShape<TS>::NW;
-  constexpr int WIN = RasterShape<TS>::WIN;
-  // per list entry of the window [w0, w0 + WIN), summed over the tile's waves:
-  // moments m_x, m_y, m_xx, m_xy, m_yy, then d opacity and d rgb
-  __shared__ float s_g[WIN][9];
+  constexpr int WIN = BwdWindow<TS, DET>::WIN;
+  constexpr int COPIES = BwdWindow<TS, DET>::COPIES;
+  // per list entry of the window [w0, w0 + WIN), summed over the tile's waves
+  // (atomically, or per wave when DET): moments m_x, m_y, m_xx, m_xy, m_yy,
+  // then d opacity and d rgb
+  __shared__ float s_g[COPIES][WIN][9];
   __shared__ int s_max[NW];
   const int tid = threadIdx.x;
   const int lane = tid % kWave, wave = tid / kWave;
@@ -88,7 +101,7 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
   for (int o = 32; o > 0; o >>= 1) mw = max(mw, __shfl_xor(mw, o, kWave));
   mw = __builtin_amdgcn_readfirstlane(mw);
   if (lane == 0) s_max[wave] = mw;
-  for (int k = tid; k < WIN * 9; k += NT) (&s_g[0][0])[k] = 0.f;
+  for (int k = tid; k < COPIES * WIN * 9; k += NT) (&s_g[0][0][0])[k] = 0.f;
   __syncthreads();
   int nrep = 0;
   for (int w = 0; w < NW; ++w) nrep = max(nrep, s_max[w]);
@@ -171,12 +184,20 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
         const float s2 = wave_sum4(m_yy, g_o, wgt * dCr, wgt * dCg);
         const float sb = wave_sum_dpp(wgt * dCb);
         if ((lane & 15) == 15) {
-          float* G = s_g[(int)(b0 - w0) + j];
           const int row = lane >> 4;
           const int q = ((row & 1) << 1) | (row >> 1);
-          atomicAdd(G + q, s1);
-          atomicAdd(G + 4 + q, s2);
-          if (row == 3) atomicAdd(G + 8, sb);
+          if (DET) {
+            // this wave's own copy: one writer per entry and component
+            float* G = s_g[wave][(int)(b0 - w0) + j];
+            G[q] = s1;
+            G[4 + q] = s2;
+            if (row == 3) G[8] = sb;
+          } else {
+            float* G = s_g[0][(int)(b0 - w0) + j];
+            atomicAdd(G + q, s1);
+            atomicAdd(G + 4 + q, s2);
+            if (row == 3) atomicAdd(G + 8, sb);
+          }
         }
       }
     }
@@ -185,15 +206,20 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
     // into the pair's own slot (zeros where nothing blended): no two tiles
     // share a slot, so no atomics reach global memory here
     for (int k = tid; k < (int)(w_end - w0); k += NT) {
-      float* G = s_g[k];
       float gv[9];
       bool any = false;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        gv[q] = G[q];
-        any |= (gv[q] != 0.f);
-        G[q] = 0.f;
+      for (int q = 0; q < 9; ++q) gv[q] = 0.f;
+      for (int c = 0; c < COPIES; ++c) {  // wave order
+        float* G = s_g[c][k];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          gv[q] += G[q];
+          G[q] = 0.f;
+        }
       }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) any |= (gv[q] != 0.f);
       const uint32_t r = a.vals[w0 + k];
       float4 o0 = zero4, o1 = zero4, o2 = zero4;
       if (any) {
@@ -324,6 +350,152 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_reduce(BwdArgs a) {
   }
 }
 
+// S3R_DETERMINISTIC_GRADS: the same sums, with the pairs of every record
+// added in emission order and no atomics -- inside a run by its thread,
+// across the runs of a workgroup by the thread where the record begins (its
+// owner), across workgroups by k_pair_reduce_carry from the partial sums
+// each workgroup leaves for the record running into it (carry-in) and for the
+// record it began that runs on past it (carry-out).
+__global__ __launch_bounds__(kPairThreads) void k_pair_reduce_det(BwdArgs a) {
+  __shared__ float s_head[kPairThreads][9];  // a run's first segment, of a record begun before it
+  __shared__ int s_head_rec[kPairThreads];
+  __shared__ float s_tail[kPairThreads][9];  // a run's last segment, of a record that runs on
+  __shared__ int s_tail_rec[kPairThreads];
+  const int nrec = a.counters[S3R_CNT_SURV];
+  const int64_t ndup = min((int64_t)a.counters[S3R_CNT_DUP], a.kp.cap_dup);
+  const int64_t P0 = (int64_t)blockIdx.x * kPairThreads * kPairRun;
+  if (P0 >= ndup || nrec <= 0) return;  // uniform over the workgroup
+  const int64_t Pend = min(ndup, P0 + (int64_t)kPairThreads * kPairRun);
+  const int tid = threadIdx.x;
+  s_head_rec[tid] = -1;
+  s_tail_rec[tid] = -1;
+  const int64_t p0 = P0 + (int64_t)tid * kPairRun;
+  const int64_t p1 = min(ndup, p0 + kPairRun);
+  if (p0 < p1) {
+    int lo = 0, hi = nrec - 1;  // last record whose first pair is at or before p0
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.rec_pair[mid] <= p0) lo = mid;
+      else hi = mid - 1;
+    }
+    int r = lo - 1;
+    int64_t first = 0, next = a.rec_pair[lo];
+    int4 rc = make_int4(0, 0, 1, 1);
+    int tx = 0, ty = 0, gx = 1, tbase = 0;
+    uint32_t db = 0u;
+    float acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = 0.f;
+    for (int64_t p = p0; p < p1; ++p) {
+      if (p >= next) {
+        do {
+          ++r;
+          first = next;
+          next = (r + 1 < nrec) ? (int64_t)a.rec_pair[r + 1] : INT64_MAX;
+        } while (p >= next);
+        rc = a.rec_rect[r];
+        const int v = a.rec_view[r];
+        db = __float_as_uint(a.rec_geo[r].w);
+        gx = (a.wh[2 * v] + a.kp.tile - 1) / a.kp.tile;
+        tbase = a.tile_offset[v];
+        const int j = (int)(p - first), w = rc.z - rc.x;
+        tx = rc.x + j % w;
+        ty = rc.y + j / w;
+      }
+      const int2 cut = a.tile_cut[tbase + ty * gx + tx];
+      const uint32_t dc = (uint32_t)cut.y;
+      if (cut.x < 0 || db < dc || (db == dc && r < cut.x)) {
+        const float4 x0 = a.part[3 * p], x1 = a.part[3 * p + 1], x2 = a.part[3 * p + 2];
+        acc[0] += x0.x; acc[1] += x0.y; acc[2] += x0.z; acc[3] += x0.w;
+        acc[4] += x1.x; acc[5] += x1.y; acc[6] += x1.z; acc[7] += x1.w;
+        acc[8] += x2.x;
+      }
+      if (++tx == rc.z) {
+        tx = rc.x;
+        ++ty;
+      }
+      if (p + 1 < p1 && p + 1 < next) continue;
+      // the segment of record r in this run ends at p
+      const bool before = first < p0, on = min(next, ndup) > p1;
+      if (!before && !on) {
+        a.g2d[3 * (size_t)r] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        a.g2d[3 * (size_t)r + 1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+        a.g2d[3 * (size_t)r + 2] = make_float4(acc[8], 0.f, 0.f, 0.f);
+      } else if (before) {
+        s_head_rec[tid] = r;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) s_head[tid][q] = acc[q];
+      } else {
+        s_tail_rec[tid] = r;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) s_tail[tid][q] = acc[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) acc[q] = 0.f;
+    }
+  }
+  __syncthreads();
+  const int64_t wg = blockIdx.x;
+  if (tid == 0) a.carry_rec[2 * wg + 1] = -1;
+  // owners: a record begun in this run, summed over the runs that follow
+  const int r = s_tail_rec[tid];
+  if (r >= 0) {
+    float sum[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sum[q] = s_tail[tid][q];
+    for (int u = tid + 1; u < kPairThreads && s_head_rec[u] == r; ++u)
+#pragma unroll
+      for (int q = 0; q < 9; ++q) sum[q] += s_head[u][q];
+    const int64_t end = min(r + 1 < nrec ? (int64_t)a.rec_pair[r + 1] : INT64_MAX, ndup);
+    if (end <= Pend) {
+      a.g2d[3 * (size_t)r] = make_float4(sum[0], sum[1], sum[2], sum[3]);
+      a.g2d[3 * (size_t)r + 1] = make_float4(sum[4], sum[5], sum[6], sum[7]);
+      a.g2d[3 * (size_t)r + 2] = make_float4(sum[8], 0.f, 0.f, 0.f);
+    } else {
+      a.carry_rec[2 * wg + 1] = r;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) a.carry_g[(2 * wg + 1) * 9 + q] = sum[q];
+    }
+  }
+  // carry-in: the record running into this workgroup, summed over its runs here
+  if (tid == 0) {
+    const int r0 = s_head_rec[0];
+    a.carry_rec[2 * wg] = r0;
+    if (r0 >= 0) {
+      float sum[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) sum[q] = 0.f;
+      for (int u = 0; u < kPairThreads && s_head_rec[u] == r0; ++u)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) sum[q] += s_head[u][q];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) a.carry_g[2 * wg * 9 + q] = sum[q];
+    }
+  }
+}
+
+// one thread per workgroup of k_pair_reduce_det: the record it began and
+// handed on is completed with the carry-ins of the workgroups that follow,
+// in order
+__global__ __launch_bounds__(256) void k_pair_reduce_carry(BwdArgs a, int64_t nb) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ndup = min((int64_t)a.counters[S3R_CNT_DUP], a.kp.cap_dup);
+  const int64_t per = (int64_t)kPairThreads * kPairRun;
+  const int64_t active = min(nb, (ndup + per - 1) / per);
+  if (w >= active || a.counters[S3R_CNT_SURV] <= 0) return;
+  const int r = a.carry_rec[2 * w + 1];
+  if (r < 0) return;
+  float sum[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) sum[q] = a.carry_g[(2 * w + 1) * 9 + q];
+  for (int64_t u = w + 1; u < active && a.carry_rec[2 * u] == r; ++u)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sum[q] += a.carry_g[2 * u * 9 + q];
+  a.g2d[3 * (size_t)r] = make_float4(sum[0], sum[1], sum[2], sum[3]);
+  a.g2d[3 * (size_t)r + 1] = make_float4(sum[4], sum[5], sum[6], sum[7]);
+  a.g2d[3 * (size_t)r + 2] = make_float4(sum[8], 0.f, 0.f, 0.f);
+}
+
 // ---------------------------------------------------------------------------
 // projection / colour backward
 // ---------------------------------------------------------------------------
@@ -345,9 +517,15 @@ __device__ __forceinline__ void quat_rot_bwd(float4 q, const float dR[9], float 
   dq[3] = (dz - z * dot) / n;
 }
 
+// 2^32: the unit of the fixed-point camera-gradient sums of the deterministic
+// mode (integer additions commute, so their order cannot change the result)
+constexpr double kFixedScale = 4294967296.0;
+
 // Sum 12 values over the lanes of a wave that share a key (key < 0: none)
-// and add them to dst + key * 12.
-__device__ __forceinline__ void wave_segmented_add(int key, const float val[12], float* dst) {
+// and add them to dst + key * 12 -- or, with fx, to the fixed-point sums
+// fx + key * 12 (deterministic whatever order the waves add in).
+__device__ __forceinline__ void wave_segmented_add(int key, const float val[12], float* dst,
+                                                   unsigned long long* fx = nullptr) {
   const int lane = lane_id();
   uint64_t todo = ballot(key >= 0);
   while (todo) {
@@ -358,7 +536,13 @@ __device__ __forceinline__ void wave_segmented_add(int key, const float val[12],
 #pragma unroll
     for (int q = 0; q < 12; ++q) {
       const float s = wave_sum(mine ? val[q] : 0.f);
-      if (lane == leader) atomicAdd(dst + (size_t)lk * 12 + q, s);
+      if (lane == leader) {
+        if (fx)
+          atomicAdd(fx + (size_t)lk * 12 + q,
+                    (unsigned long long)(long long)__double2ll_rn((double)s * kFixedScale));
+        else
+          atomicAdd(dst + (size_t)lk * 12 + q, s);
+      }
     }
     todo &= ~grp;
   }
@@ -704,7 +888,7 @@ __device__ __forceinline__ void project_bwd_owner(const ProjBwdArgs& a, int r0, 
         }
       }
     }
-    wave_segmented_add(cam_key, dcam, plain ? a.d_pose : a.d_cam);
+    wave_segmented_add(cam_key, dcam, plain ? a.d_pose : a.d_cam, plain ? nullptr : a.d_cam_fx);
   }
 
   if (first) return;  // not an owner: nothing to write
@@ -749,6 +933,41 @@ __global__ void k_pose_bwd(const float* __restrict__ W, const int32_t* __restric
                       w[2 * 4 + r] * dP[2 * 4 + c];
       if (g != 0.f) atomicAdd(dG + r * 4 + c, g);
     }
+}
+
+// deterministic mode: one thread per (timestep, slot) sums the fixed-point
+// camera gradients of the batch's views at that timestep, in view order, and
+// writes dL/dG_{tau,k} = sum_v W_R^T dL/dP_{v,k} (slot 0 skipped)
+__global__ void k_pose_bwd_det(const float* __restrict__ W, const int32_t* __restrict__ tstep,
+                               const unsigned long long* __restrict__ d_cam_fx, int nv, int S,
+                               int T, float* __restrict__ d_pose) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= T * S) return;
+  const int tau = idx / S, k = idx % S;
+  if (k == 0) return;
+  float g[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) g[q] = 0.f;
+  bool any = false;
+  for (int v = 0; v < nv; ++v) {
+    if (clampi(tstep[v], 0, T - 1) != tau) continue;
+    any = true;
+    const float* w = W + v * 12;
+    float dP[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q)
+      dP[q] = (float)((double)(long long)d_cam_fx[((size_t)v * S + k) * 12 + q] / kFixedScale);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        g[r * 4 + c] += w[0 * 4 + r] * dP[0 * 4 + c] + w[1 * 4 + r] * dP[1 * 4 + c] +
+                        w[2 * 4 + r] * dP[2 * 4 + c];
+  }
+  if (!any) return;
+  float* dG = d_pose + ((size_t)tau * S + k) * 12;
+#pragma unroll
+  for (int q = 0; q < 12; ++q) dG[q] = g[q];
 }
 
 // 6-DoF form of the pose gradient: M = G~^T D, rho = M[0:3,3],
@@ -871,18 +1090,20 @@ hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st) {
   S3R_LAUNCH(K_ZERO_G2D, k_zero_g2d, dim3(1024), dim3(256), 0, st, a.g2d, a.counters, a.zero_a,
              a.n_zero_a, a.zero_b, a.n_zero_b);
   if (a.total_tiles <= 0) return hipGetLastError();
+  const bool det = (a.kp.flags & S3R_DETERMINISTIC_GRADS) != 0;
+  const dim3 grid(a.total_tiles);
   switch (a.kp.tile) {
     case 8:
-      S3R_LAUNCH(K_RASTER_BWD, k_raster_bwd<8>, dim3(a.total_tiles), dim3(RasterShape<8>::NT), 0,
-                 st, a);
+      if (det) S3R_LAUNCH(K_RASTER_BWD, (k_raster_bwd<8, true>), grid, dim3(64), 0, st, a);
+      else S3R_LAUNCH(K_RASTER_BWD, (k_raster_bwd<8, false>), grid, dim3(64), 0, st, a);
       break;
     case 16:
-      S3R_LAUNCH(K_RASTER_BWD, k_raster_bwd<16>, dim3(a.total_tiles), dim3(RasterShape<16>::NT),
-                 0, st, a);
+      if (det) S3R_LAUNCH(K_RASTER_BWD, (k_raster_bwd<16, true>), grid, dim3(256), 0, st, a);
+      else S3R_LAUNCH(K_RASTER_BWD, (k_raster_bwd<16, false>), grid, dim3(256), 0, st, a);
       break;
     case 32:
-      S3R_LAUNCH(K_RASTER_BWD, k_raster_bwd<32>, dim3(a.total_tiles), dim3(RasterShape<32>::NT),
-                 0, st, a);
+      if (det) S3R_LAUNCH(K_RASTER_BWD, (k_raster_bwd<32, true>), grid, dim3(1024), 0, st, a);
+      else S3R_LAUNCH(K_RASTER_BWD, (k_raster_bwd<32, false>), grid, dim3(1024), 0, st, a);
       break;
     default:
       return hipErrorInvalidValue;
@@ -890,8 +1111,14 @@ hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st) {
   {
     const int64_t per = (int64_t)kPairThreads * kPairRun;
     const int64_t nb = (a.kp.cap_dup + per - 1) / per;
-    S3R_LAUNCH(K_PAIR_REDUCE, k_pair_reduce, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kPairThreads),
-               0, st, a);
+    const dim3 g((unsigned)(nb > 0 ? nb : 1));
+    if (det) {
+      S3R_LAUNCH(K_PAIR_REDUCE, k_pair_reduce_det, g, dim3(kPairThreads), 0, st, a);
+      S3R_LAUNCH(K_PAIR_REDUCE, k_pair_reduce_carry, dim3((unsigned)((nb + 255) / 256 > 0 ? (nb + 255) / 256 : 1)),
+                 dim3(256), 0, st, a, nb);
+    } else {
+      S3R_LAUNCH(K_PAIR_REDUCE, k_pair_reduce, g, dim3(kPairThreads), 0, st, a);
+    }
   }
   return hipGetLastError();
 }
@@ -975,6 +1202,20 @@ hipError_t launch_project_bwd(const ProjBwdArgs& a, hipStream_t st) {
   const int64_t want = (a.kp.cap_surv + 255) / 256;
   const int grid = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
   S3R_LAUNCH(K_PROJECT_BWD, k_project_bwd, dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_bwd_det(const float* W, const int32_t* tstep, const float* pose,
+                               const unsigned long long* d_cam_fx, int nv, int S, int T,
+                               float* d_pose, float* d_pose6, hipStream_t st) {
+  const int ts = T * S;
+  if (ts > 0) {
+    S3R_LAUNCH(K_POSE_BWD, k_pose_bwd_det, dim3((ts + 127) / 128), dim3(128), 0, st, W, tstep,
+               d_cam_fx, nv, S, T, d_pose);
+    if (d_pose6 != nullptr)
+      S3R_LAUNCH(K_POSE6, k_pose6, dim3((ts + 127) / 128), dim3(128), 0, st, pose, d_pose, ts, S,
+                 d_pose6);
+  }
   return hipGetLastError();
 }
 

@@ -84,6 +84,9 @@ struct WsBwd {
   float4* part;
   int2* tile_cut;
   float* d_cam;
+  unsigned long long* d_cam_fx;
+  int32_t* carry_rec;
+  float* carry_g;
 };
 
 size_t ws_project(const S3RSizes& z, WsProject* w, char* base) {
@@ -135,6 +138,14 @@ size_t ws_bwd(const S3RSizes& z, WsBwd* w, char* base) {
   off += align_up((size_t)z.total_tiles * 8 + 8);
   if (w) w->d_cam = reinterpret_cast<float*>(base + off);
   off += align_up((size_t)z.n_views * z.n_slots * 48 + 16);
+  if (w) w->d_cam_fx = reinterpret_cast<unsigned long long*>(base + off);
+  off += align_up((size_t)z.n_views * z.n_slots * 96 + 16);
+  // one carry-in and one carry-out per workgroup of the per-record sum
+  const size_t nwg = (size_t)(z.cap_dup + 2047) / 2048 + 1;
+  if (w) w->carry_rec = reinterpret_cast<int32_t*>(base + off);
+  off += align_up(2 * nwg * 4);
+  if (w) w->carry_g = reinterpret_cast<float*>(base + off);
+  off += align_up(2 * nwg * 9 * 4);
   return off;
 }
 
@@ -550,6 +561,8 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
     S3R_REQUIRE(g->quat);
   }
   if (g->pose6 && !aligned16(g->pose6)) return S3R_E_ALIGN;
+  const bool det = (params->flags & S3R_DETERMINISTIC_GRADS) != 0;
+  if (det && plain) return S3R_E_ARG;
   const bool sparse = (params->flags & S3R_GRAD_SPARSE) != 0 && !plain;
   if (sparse) {
     S3R_REQUIRE(g->rows);
@@ -602,8 +615,12 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   b.rec_rect = reinterpret_cast<const int4*>(proj->rec_rect);
   b.part = w.part;
   b.tile_cut = w.tile_cut;
-  b.zero_a = w.d_cam;
-  b.n_zero_a = (int64_t)views->n_views * scene->n_slots * 12;
+  // (the fixed-point sums of the deterministic mode are cleared as floats:
+  // two per 64-bit sum)
+  b.zero_a = det ? reinterpret_cast<float*>(w.d_cam_fx) : w.d_cam;
+  b.n_zero_a = (int64_t)views->n_views * scene->n_slots * 12 * (det ? 2 : 1);
+  b.carry_rec = w.carry_rec;
+  b.carry_g = w.carry_g;
   b.zero_b = g->pose;
   b.n_zero_b = (int64_t)scene->n_timesteps * scene->n_slots * 12;
   b.g2d = w.g2d;
@@ -646,12 +663,16 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   p.d_mean_w = g->mean_w;
   p.d_rot_w = g->rot_w;
   p.d_cam = w.d_cam;
+  p.d_cam_fx = det ? w.d_cam_fx : nullptr;
   p.d_pose = g->pose;
   p.kp = kp;
   p.rows = sparse ? g->rows : nullptr;
   p.n_rows = sparse ? g->n_rows : nullptr;
   S3R_HIP(launch_project_bwd(p, st));
-  if (!plain)
+  if (det)
+    S3R_HIP(launch_pose_bwd_det(views->W, views->tstep, scene->pose, w.d_cam_fx, views->n_views,
+                                scene->n_slots, scene->n_timesteps, g->pose, g->pose6, st));
+  else if (!plain)
     S3R_HIP(launch_pose_bwd(views->W, views->tstep, scene->pose, w.d_cam, views->n_views,
                             scene->n_slots, scene->n_timesteps, g->pose, g->pose6, st));
   return S3R_OK;

@@ -129,6 +129,10 @@ struct BwdArgs {
   // depth bits), or record -1 when it replayed the whole list (workspace)
   int2* tile_cut;
   float4* g2d;
+  // S3R_DETERMINISTIC_GRADS: per workgroup of the per-record sum, the record
+  // running in (2 w) and the one handed on (2 w + 1) with their partial sums
+  int32_t* carry_rec;
+  float* carry_g;
   KParams kp;
 };
 
@@ -168,6 +172,7 @@ struct ProjBwdArgs {
   int32_t* rows;   // sparse gradient mode: [cap_surv] owner Gaussian or -1
   int32_t* n_rows;  // (null in the dense mode)
   float* d_cam;    // [V][S][12] workspace
+  unsigned long long* d_cam_fx;  // [V][S][12] S3R_DETERMINISTIC_GRADS: fixed point, 2^-32 units
   float* d_pose;   // [T][S][12] (plain route: colour-direction part)
   KParams kp;
 };
@@ -247,6 +252,9 @@ hipError_t launch_clear_rows(const int32_t* rows, const int32_t* n_rows, int64_t
                              float* mean, float* scale, float* quat, float* opac, float* sh,
                              int64_t cap, hipStream_t st);
 
+hipError_t launch_pose_bwd_det(const float* W, const int32_t* tstep, const float* pose,
+                               const unsigned long long* d_cam_fx, int nv, int S, int T,
+                               float* d_pose, float* d_pose6, hipStream_t st);
 hipError_t launch_pose_bwd(const float* W, const int32_t* tstep, const float* pose,
                            const float* d_cam, int nv, int S, int T, float* d_pose,
                            float* d_pose6, hipStream_t st);

@@ -237,6 +237,8 @@ class Renderer:
             flags |= A.S3R_LOD_STOCHASTIC
         if p.get("grad_sparse", False):
             flags |= A.S3R_GRAD_SPARSE
+        if p.get("deterministic", False):
+            flags |= A.S3R_DETERMINISTIC_GRADS
         # sort mode: "tiles" (tile partition + per-list depth sort) is fastest
         # while lists stay short; "auto" takes it when every list seen by the
         # last capacity fit held fewer than TILE_SORT_MAX entries

@@ -200,3 +200,32 @@ def test_grads_records_spanning_reduce_workgroups():
     g = gpu_region_grads(r, parts)
     ref = oracle_region_grads(scene, views, p, parts)
     compare(g, ref, KEYS, tag="spanning records")
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_deterministic_gradients_bitwise(tile):
+    """S3R_DETERMINISTIC_GRADS: repeated backward calls (and a repeated
+    forward + backward) give bitwise equal gradients of every tensor, which
+    also match the oracle -- on a scene whose large Gaussians cover thousands
+    of tiles, so per-record sums cross runs and workgroups of the slot sum,
+    and a tile's waves all add into the same window entries."""
+    scene, views = scenes.micro_scene(21, n=200, width=960, height=540, n_inst=1, sh_degree=1)
+    scene.scale[:6] = 1.2
+    p = dict(scenes.default_params(tile=tile), deterministic=True)
+    banner(f"deterministic gradients tile={tile}")
+    r = make_renderer(scene, views, p)
+    rng = np.random.default_rng(9)
+    parts = []
+    for v in range(views.n_views):
+        for _ in range(24):
+            tx, ty = int(rng.integers(0, 960 // 8)), int(rng.integers(0, 540 // 8))
+            reg = (8 * tx, 8 * ty, 8 * tx + 8, 8 * ty + 8)
+            parts.append((v, reg, rng.uniform(-1.0, 1.0, (3, 8, 8)) / 64.0))
+    runs = [gpu_region_grads(r, parts) for _ in range(2)]
+    r.forward()
+    runs.append(gpu_region_grads(r, parts))
+    for k in KEYS:
+        for o in runs[1:]:
+            np.testing.assert_array_equal(o[k], runs[0][k], err_msg=f"{k} not reproducible")
+    ref = oracle_region_grads(scene, views, p, parts)
+    compare(runs[0], ref, KEYS, tag=f"deterministic tile {tile}")

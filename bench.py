@@ -38,13 +38,18 @@ FP32_PEAK_TFLOPS = 157.3
 METRIC = "fwd+bwd views/s at 1080p, 2M Gaussians: streamlined vs plain, same GPU"
 
 # algorithmic work per unit (see the design notes): FP32 operations of Eq. (2)
-# and its derivative, counted on the work census of the forward
-FLOP_EVAL = 15.0         # exponent of one evaluated (pixel, entry) pair: offsets,
-                         # quadratic form, o exp(power), clamp, two tests (+1 exp)
-FLOP_FWD_BLEND = 8.0     # blending a contributing pair: T (1 - alpha), 3 colour FMAs
-FLOP_BWD_BLEND = 25.0    # its backward: T recovery (+1 rcp), dL/dalpha, dL/dpower,
-                         # five conic moments, opacity and colour gradients
-FLOP_LAST_PAIR = 60.0    # the coarser model: every list entry up to the pixel's last
+# and its derivative per evaluated (pixel, entry) pair -- an entry whose
+# cutoff box meets the pixel's sub-tile, while the pixel still blends -- as
+# counted by the forward's work census
+FLOP_FWD_PAIR = 22.0     # blending: offsets, quadratic form, o exp(power), clamp,
+                         # tests, transmittance and colour update (+1 exp)
+FLOP_BWD_PAIR = 60.0     # the backward replay of a pair (+1 exp, +1 rcp)
+# the same work itemised: 15 FLOP per evaluated pair (the exponent), and per
+# blended pair 8 (forward) or 25 (backward: T recovery, dL/dalpha, dL/dpower,
+# five conic moments, opacity and colour gradients)
+FLOP_EVAL = 15.0
+FLOP_FWD_BLEND = 8.0
+FLOP_BWD_BLEND = 25.0
 REC_BYTES = 72           # record written per survivor (gid, view, geo, conic, rgb, rect)
 GEOM_BYTES = 44          # mean, scale, quat, instance id of a Gaussian that passes
 
@@ -213,22 +218,32 @@ def kernel_roofline(name, total_ms, launches, units, steps, sh_degree, n):
     sh_bytes = 12 * (sh_degree + 1) ** 2
     sec = total_ms * 1e-3
     if name in ("raster_bwd", "raster_fwd"):
-        blend = FLOP_BWD_BLEND if name == "raster_bwd" else FLOP_FWD_BLEND
-        work = sum(FLOP_EVAL * u["pairs_eval"] + blend * u["pairs_blend"] for u in per)
-        coarse = sum(u["pairs_last"] for u in per) * FLOP_LAST_PAIR
-        extra = {"pairs_per_launch": {
-                     "list_entries_to_last": sum(u["pairs_last"] for u in per) / steps,
-                     "evaluated": sum(u["pairs_eval"] for u in per) / steps,
-                     "blended": sum(u["pairs_blend"] for u in per) / steps},
+        fwd = name == "raster_fwd"
+        per_pair = FLOP_FWD_PAIR if fwd else FLOP_BWD_PAIR
+        blend = FLOP_FWD_BLEND if fwd else FLOP_BWD_BLEND
+        ev = sum(u["pairs_eval"] for u in per)
+        bl = sum(u["pairs_blend"] for u in per)
+        last = sum(u["pairs_last"] for u in per)
+        work = ev * per_pair
+
+        def model(flop, what):
+            return {"achieved": flop / sec / 1e12, "frac": flop / sec / 1e12 / FP32_PEAK_TFLOPS,
+                    "work": what}
+        extra = {"pairs_per_launch": {"list_entries_to_last": last / steps, "evaluated": ev / steps,
+                                      "blended": bl / steps},
                  "flop_per_launch": work / steps,
-                 "coarse_model": {"achieved": coarse / sec / 1e12,
-                                  "frac": coarse / sec / 1e12 / FP32_PEAK_TFLOPS,
-                                  "work": f"{FLOP_LAST_PAIR:.0f} FLOP per list entry up to each "
-                                          "pixel's last contributor (counts entries the cutoff "
-                                          "box skips: an upper bound)"}}
+                 "other_models": {
+                     "per_blended_pair": model(bl * per_pair, f"{per_pair:.0f} FLOP per blended pair"),
+                     "itemised": model(FLOP_EVAL * ev + blend * bl,
+                                       f"{FLOP_EVAL:.0f} FLOP per evaluated + {blend:.0f} per "
+                                       "blended pair"),
+                     "per_list_entry": model(last * per_pair,
+                                             f"{per_pair:.0f} FLOP per list entry up to each "
+                                             "pixel's last contributor (counts entries the "
+                                             "cutoff box skips: an upper bound)")}}
         return "alu", work / sec / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s", \
-            (f"{FLOP_EVAL:.0f} FLOP + 1 exp per evaluated (pixel, entry) pair, {blend:.0f} FLOP "
-             "per blended pair (work census of the forward)"), extra
+            (f"{per_pair:.0f} FLOP + 1 exp per evaluated (pixel, entry) pair (work census of "
+             "the forward)"), extra
     if name == "project":
         b = sum(8 * n + GEOM_BYTES * u["N_t"] + n / 8 + (4 + sh_bytes + REC_BYTES) * u["N_r"]
                 for u in per)
@@ -485,11 +500,15 @@ def lifecycle(cfg, torch, epochs=6, reset_every=3):
     return out
 
 
-def batched_graph(cfg, torch, replays, tiles, sorts=("tiles", "global")):
+def batched_graph(cfg, torch, replays, tiles, sorts=("tiles", "global"), waves=(1, 4)):
     """Batched multi-view step (all timed views of the workload in one batch)
-    captured in a HIP graph; tile size and sort mode picked by timing each
-    candidate (tiles x sorts)."""
+    captured in a HIP graph.  With more than one candidate, the tile size,
+    sort mode and forward waves per workgroup come from the library's
+    autotuner (eager steps timed per candidate, same image required); the
+    chosen shape is then captured and replayed `replays` times."""
     from paper_2503_08217_amd import S3R_VIS_FOLD, S3R_VIS_UPDATE
+    from paper_2503_08217_amd import _abi
+    from paper_2503_08217_amd.autotune import autotune
     from paper_2503_08217_amd.renderer import Renderer
     import scenes
     views = cfg.views.subset(cfg.timed_views)
@@ -511,70 +530,74 @@ def batched_graph(cfg, torch, replays, tiles, sorts=("tiles", "global")):
     vis_s, vis_e = warm.vis_s.clone(), warm.vis_e.clone()
     del warm, hs
     torch.cuda.empty_cache()
-    best = None
-    tune = []
-    for tile, sort in [(t, m) for t in tiles for m in sorts]:
-        params = dict(cfg.params, tile=tile, grad_sparse=True, sort=sort)
-        r = Renderer(cfg.scene, views, params, cap_surv=max(1024, cfg.scene.n // 2),
-                     cap_dup=max(4096, 2 * cfg.scene.n))
-        r.vis_s.copy_(vis_s)
-        r.vis_e.copy_(vis_e)
-        c = r.fit_capacity()
-        g = r.capture_step(target, update_visibility=True)
-        times = []
-        for i in range(replays):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            g.replay()
-            e1.record()
-            times.append((e0, e1))
-        torch.cuda.synchronize()
-        ms = np.asarray([a.elapsed_time(b) for a, b in times])
-        st = r.stats.cpu().numpy()
-        # a few eager steps with every kernel timed: per-kernel breakdown and
-        # the project/cull/sort share of HBM peak for this batch
-        from paper_2503_08217_amd import _abi
-        lib = _abi.load()
-        _abi.check(lib.s3r_profile_reset(), "profile reset")
-        _abi.check(lib.s3r_profile_only(-1), "profile only")
-        _abi.check(lib.s3r_profile_enable(1), "profile enable")
-        prof_steps = 3
-        for _ in range(prof_steps):
-            r.step(target)
-        torch.cuda.synchronize()
-        table = _abi.profile_table()
-        _abi.check(lib.s3r_profile_enable(0), "profile disable")
-        units = [dict(N_t=int(x[0]), N_f=int(x[1]), N_r=int(x[2]), N_dup=int(x[3])) for x in st]
-        pcs_ms = sum(table[k][0] for k in PCS_KERNELS if k in table) / prof_steps
-        pcs_b = pcs_batch_bytes(units, cfg.scene.sh_degree, cfg.scene.n)
-        res = {"tile": tile, "sort": sort, "p50_ms": float(np.percentile(ms, 50)),
-               "p99_ms": float(np.percentile(ms, 99)), "mean_ms": float(ms.mean()),
-               "views_per_s": views.n_views / (ms.mean() * 1e-3),
-               "temporal_pass_fraction": float(st[:, 0].mean() / cfg.scene.n),
-               "frustum_visible_fraction": float(st[:, 1].mean() / cfg.scene.n),
-               "records": c["n_surv"], "pairs": c["n_dup"],
-               "gaussians_per_s": cfg.scene.n * views.n_views / (ms.mean() * 1e-3),
-               "project_cull_sort_hbm": {"achieved": pcs_b / (pcs_ms * 1e-3) / 1e9,
-                                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                         "frac": pcs_b / (pcs_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                         "ms_per_step": pcs_ms, "bytes": pcs_b},
-               "kernels_us_per_step": {k: 1000 * v[0] / prof_steps for k, v in table.items()}}
-        log(f"batched {cfg.name} tile {tile} sort {sort}: p50 {res['p50_ms']:.2f} ms, p99 "
-            f"{res['p99_ms']:.2f} ms, {res['views_per_s']:.1f} views/s, N_t/N "
-            f"{res['temporal_pass_fraction']:.3f}, N_f/N {res['frustum_visible_fraction']:.3f}, "
-            f"project/cull/sort "
-            f"{res['project_cull_sort_hbm']['ms_per_step']:.3f} ms at "
-            f"{100 * res['project_cull_sort_hbm']['frac']:.1f}% of HBM peak")
-        for k, v in sorted(res["kernels_us_per_step"].items(), key=lambda kv: -kv[1])[:12]:
-            log(f"   {k:22s} {v:9.1f} us/step")
-        tune.append(res)
-        if best is None or res["mean_ms"] < best["mean_ms"]:
-            best = res
-        del g, r
-        torch.cuda.empty_cache()
+    caps = dict(cap_surv=max(1024, cfg.scene.n // 2), cap_dup=max(4096, 2 * cfg.scene.n))
+    base = dict(cfg.params, grad_sparse=True)
+    tune = None
+    if len(tiles) * len(sorts) * len(waves) > 1:
+        tune = autotune(cfg.scene, views, base, target, tiles=tiles, sorts=sorts,
+                        raster_waves=waves, reps=5, vis=(vis_s, vis_e), log=log, **caps)
+        choice = tune["best"]
+    else:
+        choice = dict(tile=tiles[0], sort=sorts[0], raster_waves=waves[0], binning=True)
+        _abi.set_tuning(raster_waves=waves[0])
+    params = dict(base, tile=choice["tile"], sort=choice["sort"])
+    r = Renderer(cfg.scene, views, params, **caps)
+    r.vis_s.copy_(vis_s)
+    r.vis_e.copy_(vis_e)
+    c = r.fit_capacity()
+    g = r.capture_step(target, update_visibility=True)
+    times = []
+    for i in range(replays):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        times.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = np.asarray([a.elapsed_time(b) for a, b in times])
+    st = r.stats.cpu().numpy()
+    # a few eager steps with every kernel timed: per-kernel breakdown and
+    # the project/cull/sort share of HBM peak for this batch
+    lib = _abi.load()
+    _abi.check(lib.s3r_profile_reset(), "profile reset")
+    _abi.check(lib.s3r_profile_only(-1), "profile only")
+    _abi.check(lib.s3r_profile_enable(1), "profile enable")
+    prof_steps = 3
+    for _ in range(prof_steps):
+        r.step(target)
+    torch.cuda.synchronize()
+    table = _abi.profile_table()
+    _abi.check(lib.s3r_profile_enable(0), "profile disable")
+    units = [dict(N_t=int(x[0]), N_f=int(x[1]), N_r=int(x[2]), N_dup=int(x[3])) for x in st]
+    pcs_ms = sum(table[k][0] for k in PCS_KERNELS if k in table) / prof_steps
+    pcs_b = pcs_batch_bytes(units, cfg.scene.sh_degree, cfg.scene.n)
+    res = {"tile": choice["tile"], "sort": choice["sort"], "raster_waves": choice["raster_waves"],
+           "binning": choice["binning"], "p50_ms": float(np.percentile(ms, 50)),
+           "p99_ms": float(np.percentile(ms, 99)), "mean_ms": float(ms.mean()),
+           "views_per_s": views.n_views / (ms.mean() * 1e-3),
+           "temporal_pass_fraction": float(st[:, 0].mean() / cfg.scene.n),
+           "frustum_visible_fraction": float(st[:, 1].mean() / cfg.scene.n),
+           "records": c["n_surv"], "pairs": c["n_dup"],
+           "gaussians_per_s": cfg.scene.n * views.n_views / (ms.mean() * 1e-3),
+           "project_cull_sort_hbm": {"achieved": pcs_b / (pcs_ms * 1e-3) / 1e9,
+                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": pcs_b / (pcs_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                     "ms_per_step": pcs_ms, "bytes": pcs_b},
+           "kernels_us_per_step": {k: 1000 * v[0] / prof_steps for k, v in table.items()}}
+    log(f"batched {cfg.name} tile {choice['tile']} sort {choice['sort']} waves "
+        f"{choice['raster_waves']}: p50 {res['p50_ms']:.2f} ms, p99 {res['p99_ms']:.2f} ms, "
+        f"{res['views_per_s']:.1f} views/s, N_t/N {res['temporal_pass_fraction']:.3f}, N_f/N "
+        f"{res['frustum_visible_fraction']:.3f}, project/cull/sort "
+        f"{res['project_cull_sort_hbm']['ms_per_step']:.3f} ms at "
+        f"{100 * res['project_cull_sort_hbm']['frac']:.1f}% of HBM peak")
+    for k, v in sorted(res["kernels_us_per_step"].items(), key=lambda kv: -kv[1])[:12]:
+        log(f"   {k:22s} {v:9.1f} us/step")
+    del g, r
+    torch.cuda.empty_cache()
+    _abi.set_tuning(**{k: -1 for k in _abi.TUNE_KNOBS})
     return {"workload": cfg.name, "views_per_batch": views.n_views, "replays": replays,
-            "best": best, "autotune": tune}
+            "best": res, "autotune": tune["table"] if tune else None}
 
 
 def main():
@@ -734,7 +757,7 @@ def main():
             t0 = time.perf_counter()
             bc = scenes.make_config(cid)
             log(f"config {cid} ({bc.name}) generated in {time.perf_counter() - t0:.1f}s")
-            res = batched_graph(bc, torch, a.batched_replays, (tile,), ("tiles",))
+            res = batched_graph(bc, torch, a.batched_replays, (tile,), ("tiles",), (1,))
             out["batched"][bc.name] = res["best"]
             del bc
             torch.cuda.empty_cache()

@@ -388,6 +388,21 @@ class Renderer:
         torch.cuda.synchronize()
         return graph
 
+    @classmethod
+    def autotuned(cls, scene, views, params, target, *, vis=None, **kw):
+        """A renderer of `views` with the tile size, sort mode and launch
+        shapes that ran one training step fastest (autotune.autotune; every
+        candidate must render the same image).  Returns (renderer, result)."""
+        from .autotune import autotune
+        res = autotune(scene, views, params, target, vis=vis, **kw)
+        r = cls(scene, views, res["best"]["params"], device=kw.get("device", "cuda"),
+                cap_surv=kw.get("cap_surv"), cap_dup=kw.get("cap_dup"))
+        if vis is not None:
+            r.vis_s.copy_(vis[0])
+            r.vis_e.copy_(vis[1])
+        r.fit_capacity()
+        return r, res
+
     # ---------------------------------------------------------------- helpers
     def parameters(self):
         """The scene parameters as the renderer's own device tensors, in the

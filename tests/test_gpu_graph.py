@@ -46,3 +46,33 @@ def test_graph_replay_matches_eager():
             np.testing.assert_allclose(out[k] / scale, ref[k] / scale, atol=1e-5, err_msg=k)
         np.testing.assert_array_equal(out["life_s"], ref["life_s"])
         np.testing.assert_array_equal(out["life_e"], ref["life_e"])
+
+
+def test_autotuner_picks_a_shape_that_renders_the_same_image():
+    """The library-side autotuner times every (tile, sort, forward waves per
+    workgroup, binning) candidate on a step of an uneven batch, requires each
+    to render the same image bit for bit, and leaves the knobs at the
+    fastest; the renderer it returns renders that image too."""
+    from paper_2503_08217_amd import _abi as A
+    from paper_2503_08217_amd.renderer import Renderer
+    c = scenes.make_config(4, scale_n=0.01)
+    idx = [i for i in range(c.views.n_views) if c.views.tstep[i] == 21]
+    views = c.views.subset(idx)
+    tg = scenes.targets(4, views)
+    target = torch.as_tensor(np.concatenate([t.ravel() for t in tg])).cuda()
+    banner("autotune")
+    try:
+        r, res = Renderer.autotuned(c.scene, views, c.params, target, tiles=(8, 16, 32),
+                                    raster_waves=(1, 16), reps=2)
+        table, best = res["table"], res["best"]
+        assert len(table) == 3 * (2 * 2 + 2)
+        assert best["ms"] == min(row["ms"] for row in table)
+        knobs = A.get_tuning()
+        assert knobs["raster_waves"] == best["raster_waves"]
+        assert knobs["bin_max_tiles"] == (12288 if best["binning"] else 0)
+        r.forward()
+        ref = make_renderer(c.scene, views, c.params)
+        ref.forward()
+        np.testing.assert_array_equal(r.color.cpu().numpy(), ref.color.cpu().numpy())
+    finally:
+        A.set_tuning(**{k: -1 for k in A.TUNE_KNOBS})

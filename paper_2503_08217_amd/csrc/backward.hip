@@ -253,100 +253,165 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
 // Sum of the per-pair gradients of each record (pairs are contiguous per
 // record in emission order).  A pair counts only if its tile's backward
 // replayed it, i.e. if it precedes the tile's cut in the list order (depth
-// bits, then record index: the order of the stable sort).  A thread adds a run
-// of kPairRun pairs; a record wholly inside one run is stored directly, a
-// record crossing runs is summed in an LDS slot of the workgroup (the slot of
-// the run holding its first pair in this workgroup, or the carry-in slot for a
-// record begun in an earlier workgroup) and added to global memory with one
-// atomic per component and workgroup.  g2d must be zero beforehand for
-// records that cross runs.
+// bits, then record index: the order of the stable sort).  A workgroup takes
+// kPairSlabs slabs of kPairThreads consecutive pairs, one pair per lane: the
+// records of the workgroup's pairs are staged in LDS (record_window), each
+// lane finds its own there, and loads its pair's partial (coalesced over the
+// lanes) only if the pair was replayed.  Lanes of one record are adjacent: a segmented
+// scan over the wave leaves each record's sum in its last lane, which stores
+// it when the record lies wholly in the wave and otherwise adds it to an LDS
+// slot (the slot of the wave-chunk where the record begins, or the carry-in
+// slot for a record begun before the workgroup; only the last record begun in
+// a chunk can run past it, so slots are not shared).  The slots are stored at
+// the end, or added atomically for the (at most two) records that cross the
+// workgroup's bounds; g2d must be zero beforehand for those.
 constexpr int kPairThreads = 256;
-constexpr int kPairRun = 8;
+constexpr int kPairRun = 8;    // pairs per thread of the deterministic sum
+constexpr int kPairSlabs = 4;  // slabs per workgroup of the atomic sum
+constexpr int kPairViews = 64; // views whose tile offsets and widths are staged in LDS
+constexpr int kPairGrid = 2048; // workgroups of the atomic sum at most
+
+// one step of a segmented inclusive scan: lanes add the DPP source lane's
+// values when it holds the same key (keys ascend over the lanes, so the
+// source's partial sum lies wholly in the lane's own segment); a lane whose
+// source is outside its row, or whose row the mask leaves out, reads key -2
+template <int CTRL, int ROW_MASK, int N>
+__device__ __forceinline__ void seg_scan_step(int key, float (&v)[N]) {
+  const int ks = __builtin_amdgcn_update_dpp(-2, key, CTRL, ROW_MASK, 0xf, false);
+  const bool take = ks == key;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    const float x = __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), CTRL, ROW_MASK, 0xf, false));
+    if (take) v[q] += x;
+  }
+}
+
+// inclusive sums over the runs of equal keys of a wave (keys >= -1, ascending)
+template <int N>
+__device__ __forceinline__ void wave_segmented_scan(int key, float (&v)[N]) {
+  seg_scan_step<0x111, 0xf>(key, v);  // row_shr:1
+  seg_scan_step<0x112, 0xf>(key, v);  // row_shr:2
+  seg_scan_step<0x114, 0xf>(key, v);  // row_shr:4
+  seg_scan_step<0x118, 0xf>(key, v);  // row_shr:8
+  seg_scan_step<0x142, 0xa>(key, v);  // row_bcast:15 into rows 1 and 3
+  seg_scan_step<0x143, 0xc>(key, v);  // row_bcast:31 into rows 2 and 3
+}
 
 __global__ __launch_bounds__(kPairThreads) void k_pair_reduce(BwdArgs a) {
-  constexpr int NS = kPairThreads + 1;  // slot kPairThreads: carry-in
-  __shared__ float s_acc[NS][9];
-  __shared__ int s_rec[NS];
+  constexpr int S = kPairSlabs, NP = kPairThreads * S, NC = NP / kWave + 1;
+  __shared__ int s_pair[NP + 2];
+  __shared__ int s_red[2 * kPairThreads / kWave];
+  __shared__ float s_acc[NC][9];
+  __shared__ int s_rec[NC];
+  __shared__ int2 s_view[kPairViews];  // (first tile, tiles per row)
   const int nrec = a.counters[S3R_CNT_SURV];
   const int64_t ndup = a.counters[S3R_CNT_DUP];
-  const int64_t P0 = (int64_t)blockIdx.x * kPairThreads * kPairRun;
-  if (P0 >= ndup || nrec <= 0) return;  // uniform over the workgroup
-  const int tid = threadIdx.x;
-  for (int k = tid; k < NS * 9; k += kPairThreads) (&s_acc[0][0])[k] = 0.f;
-  for (int k = tid; k < NS; k += kPairThreads) s_rec[k] = -1;
-  __syncthreads();
-  const int64_t p0 = P0 + (int64_t)tid * kPairRun;
-  const int64_t p1 = min(ndup, p0 + kPairRun);
-  if (p0 < p1) {
-    // last record whose first pair is at or before p0
-    int lo = 0, hi = nrec - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (a.rec_pair[mid] <= p0) lo = mid;
-      else hi = mid - 1;
-    }
-    int r = lo - 1;
-    int64_t first = 0, next = a.rec_pair[lo];
-    int4 rc = make_int4(0, 0, 1, 1);
-    int tx = 0, ty = 0, gx = 1, tbase = 0;
-    uint32_t db = 0u;
-    float acc[9];
+  if (nrec <= 0) return;  // uniform over the grid
+  const int tid = threadIdx.x, lane = lane_id();
+  const bool vlds = a.nv <= kPairViews;
+  if (vlds && tid < a.nv)
+    s_view[tid] = make_int2(a.tile_offset[tid], (a.wh[2 * tid] + a.kp.tile - 1) / a.kp.tile);
+  // the grid is capped (the pair count is known only on the device): a
+  // workgroup takes every gridDim.x-th group of slabs
+  for (int64_t P0 = (int64_t)blockIdx.x * NP; P0 < ndup; P0 += (int64_t)gridDim.x * NP) {
+    const int64_t Pe = min(ndup, P0 + (int64_t)NP);
+    const int64_t wb0 = P0 + (int64_t)(tid - lane);  // the wave's first pair in slab 0
+    float g[S][9];
+    bool live[S];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) acc[q] = 0.f;
-    for (int64_t p = p0; p < p1; ++p) {
-      if (p >= next) {
-        // the record holding pair p (records without pairs are skipped)
-        do {
-          ++r;
-          first = next;
-          next = (r + 1 < nrec) ? (int64_t)a.rec_pair[r + 1] : INT64_MAX;
-        } while (p >= next);
-        rc = a.rec_rect[r];
-        const int v = a.rec_view[r];
-        db = __float_as_uint(a.rec_geo[r].w);
-        gx = (a.wh[2 * v] + a.kp.tile - 1) / a.kp.tile;
-        tbase = a.tile_offset[v];
-        const int j = (int)(p - first), w = rc.z - rc.x;
-        tx = rc.x + j % w;
-        ty = rc.y + j / w;
+    for (int k = 0; k < S; ++k) {
+      live[k] = wb0 + (int64_t)k * kPairThreads + lane < Pe;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) g[k][q] = 0.f;
+    }
+    for (int k = tid; k < NC * 9; k += kPairThreads) (&s_acc[0][0])[k] = 0.f;
+    for (int k = tid; k < NC; k += kPairThreads) s_rec[k] = -1;
+    int nw;  // (record_window ends with a barrier: the LDS above is visible after it)
+    const int r0 = record_window<kPairThreads>(a.rec_pair, nrec, P0, Pe, s_pair, s_red, &nw);
+    // last window record whose first pair is at or before p (s_pair[0] <= P0)
+    int idx[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) idx[k] = 0;
+    int step = 1;
+    while (2 * step < nw) step *= 2;
+    for (; step > 0; step >>= 1) {  // uniform over the workgroup
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        const int64_t p = wb0 + (int64_t)k * kPairThreads + lane;
+        const int t = idx[k] + step;
+        if (t < nw && s_pair[t] <= p) idx[k] = t;
       }
-      const int2 cut = a.tile_cut[tbase + ty * gx + tx];
+    }
+    int4 rc[S];
+    int rv[S];
+    uint32_t db[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      if (!live[k]) continue;
+      const int r = r0 + idx[k];
+      rc[k] = a.rec_rect[r];
+      rv[k] = a.rec_view[r];
+      db[k] = __float_as_uint(a.rec_geo[r].w);
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      if (!live[k]) continue;
+      const int64_t p = wb0 + (int64_t)k * kPairThreads + lane;
+      const int v = rv[k];
+      const int2 vw = vlds ? s_view[v]
+                           : make_int2(a.tile_offset[v], (a.wh[2 * v] + a.kp.tile - 1) / a.kp.tile);
+      const int j = (int)(p - s_pair[idx[k]]), w = rc[k].z - rc[k].x;
+      const int tx = rc[k].x + j % w, ty = rc[k].y + j / w;
+      const int2 cut = a.tile_cut[vw.x + ty * vw.y + tx];
       const uint32_t dc = (uint32_t)cut.y;
-      if (cut.x < 0 || db < dc || (db == dc && r < cut.x)) {
+      const int r = r0 + idx[k];
+      if (cut.x < 0 || db[k] < dc || (db[k] == dc && r < cut.x)) {  // replayed: load its partial
         const float4 x0 = a.part[3 * p], x1 = a.part[3 * p + 1], x2 = a.part[3 * p + 2];
-        acc[0] += x0.x; acc[1] += x0.y; acc[2] += x0.z; acc[3] += x0.w;
-        acc[4] += x1.x; acc[5] += x1.y; acc[6] += x1.z; acc[7] += x1.w;
-        acc[8] += x2.x;
+        g[k][0] = x0.x; g[k][1] = x0.y; g[k][2] = x0.z; g[k][3] = x0.w;
+        g[k][4] = x1.x; g[k][5] = x1.y; g[k][6] = x1.z; g[k][7] = x1.w;
+        g[k][8] = x2.x;
       }
-      if (++tx == rc.z) {
-        tx = rc.x;
-        ++ty;
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const int64_t wb = wb0 + (int64_t)k * kPairThreads;
+      if (wb >= Pe) break;  // uniform over the wave
+      const int key = live[k] ? idx[k] : -1;
+      wave_segmented_scan(key, g[k]);  // each record's sum in its last lane of the wave
+      const int kn = __shfl_down(key, 1, kWave);
+      if (live[k] && (lane == kWave - 1 || kn != key)) {
+        const int64_t f = s_pair[key], e = s_pair[key + 1];
+        if (f >= wb && e <= wb + kWave) {
+          const int r = r0 + key;
+          a.g2d[3 * (size_t)r] = make_float4(g[k][0], g[k][1], g[k][2], g[k][3]);
+          a.g2d[3 * (size_t)r + 1] = make_float4(g[k][4], g[k][5], g[k][6], g[k][7]);
+          a.g2d[3 * (size_t)r + 2] = make_float4(g[k][8], 0.f, 0.f, 0.f);
+        } else {
+          const int slot = f < P0 ? 0 : 1 + (int)((f - P0) / kWave);
+          s_rec[slot] = key;
+#pragma unroll
+          for (int q = 0; q < 9; ++q) atomicAdd(&s_acc[slot][q], g[k][q]);
+        }
       }
-      if (p + 1 < p1 && p + 1 < next) continue;
-      // the segment of record r in this run ends at p
-      if (first >= p0 && next <= p1) {
-        a.g2d[3 * (size_t)r] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-        a.g2d[3 * (size_t)r + 1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
-        a.g2d[3 * (size_t)r + 2] = make_float4(acc[8], 0.f, 0.f, 0.f);
+    }
+    __syncthreads();
+    if (tid < NC && s_rec[tid] >= 0) {
+      const int key = s_rec[tid], r = r0 + key;
+      const int64_t f = s_pair[key], e = s_pair[key + 1];
+      if (f >= P0 && e <= Pe) {
+        const float* x = s_acc[tid];
+        a.g2d[3 * (size_t)r] = make_float4(x[0], x[1], x[2], x[3]);
+        a.g2d[3 * (size_t)r + 1] = make_float4(x[4], x[5], x[6], x[7]);
+        a.g2d[3 * (size_t)r + 2] = make_float4(x[8], 0.f, 0.f, 0.f);
       } else {
-        const int slot = first < P0 ? kPairThreads : (int)((first - P0) / kPairRun);
-        if (slot == tid || (slot == kPairThreads && p0 == P0)) s_rec[slot] = r;
+        float* D = reinterpret_cast<float*>(a.g2d + 3 * (size_t)r);
 #pragma unroll
         for (int q = 0; q < 9; ++q)
-          if (acc[q] != 0.f) atomicAdd(&s_acc[slot][q], acc[q]);
+          if (s_acc[tid][q] != 0.f) atomicAdd(D + q, s_acc[tid][q]);
       }
-#pragma unroll
-      for (int q = 0; q < 9; ++q) acc[q] = 0.f;
     }
-  }
-  __syncthreads();
-  for (int k = tid; k < NS; k += kPairThreads) {
-    const int r = s_rec[k];
-    if (r < 0) continue;
-    float* D = reinterpret_cast<float*>(a.g2d + 3 * (size_t)r);
-#pragma unroll
-    for (int q = 0; q < 9; ++q)
-      if (s_acc[k][q] != 0.f) atomicAdd(D + q, s_acc[k][q]);
+    __syncthreads();  // the next group rewrites the LDS read above
   }
 }
 
@@ -361,25 +426,30 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_reduce_det(BwdArgs a) {
   __shared__ int s_head_rec[kPairThreads];
   __shared__ float s_tail[kPairThreads][9];  // a run's last segment, of a record that runs on
   __shared__ int s_tail_rec[kPairThreads];
+  constexpr int NP = kPairThreads * kPairRun;
+  __shared__ int s_pair[NP + 2];
+  __shared__ int s_red[2 * kPairThreads / kWave];
   const int nrec = a.counters[S3R_CNT_SURV];
   const int64_t ndup = min((int64_t)a.counters[S3R_CNT_DUP], a.kp.cap_dup);
-  const int64_t P0 = (int64_t)blockIdx.x * kPairThreads * kPairRun;
+  const int64_t P0 = (int64_t)blockIdx.x * NP;
   if (P0 >= ndup || nrec <= 0) return;  // uniform over the workgroup
-  const int64_t Pend = min(ndup, P0 + (int64_t)kPairThreads * kPairRun);
+  const int64_t Pend = min(ndup, P0 + (int64_t)NP);
   const int tid = threadIdx.x;
   s_head_rec[tid] = -1;
   s_tail_rec[tid] = -1;
+  int nw;
+  const int r0 = record_window<kPairThreads>(a.rec_pair, nrec, P0, Pend, s_pair, s_red, &nw);
   const int64_t p0 = P0 + (int64_t)tid * kPairRun;
   const int64_t p1 = min(ndup, p0 + kPairRun);
   if (p0 < p1) {
-    int lo = 0, hi = nrec - 1;  // last record whose first pair is at or before p0
+    int lo = 0, hi = nw - 1;  // last window record whose first pair is at or before p0
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (a.rec_pair[mid] <= p0) lo = mid;
+      if (s_pair[mid] <= p0) lo = mid;
       else hi = mid - 1;
     }
-    int r = lo - 1;
-    int64_t first = 0, next = a.rec_pair[lo];
+    int r = r0 + lo - 1;
+    int64_t first = 0, next = s_pair[lo];
     int4 rc = make_int4(0, 0, 1, 1);
     int tx = 0, ty = 0, gx = 1, tbase = 0;
     uint32_t db = 0u;
@@ -391,7 +461,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_reduce_det(BwdArgs a) {
         do {
           ++r;
           first = next;
-          next = (r + 1 < nrec) ? (int64_t)a.rec_pair[r + 1] : INT64_MAX;
+          next = s_pair[r - r0 + 1];
         } while (p >= next);
         rc = a.rec_rect[r];
         const int v = a.rec_view[r];
@@ -446,7 +516,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_reduce_det(BwdArgs a) {
     for (int u = tid + 1; u < kPairThreads && s_head_rec[u] == r; ++u)
 #pragma unroll
       for (int q = 0; q < 9; ++q) sum[q] += s_head[u][q];
-    const int64_t end = min(r + 1 < nrec ? (int64_t)a.rec_pair[r + 1] : INT64_MAX, ndup);
+    const int64_t end = min((int64_t)s_pair[r - r0 + 1], ndup);
     if (end <= Pend) {
       a.g2d[3 * (size_t)r] = make_float4(sum[0], sum[1], sum[2], sum[3]);
       a.g2d[3 * (size_t)r + 1] = make_float4(sum[4], sum[5], sum[6], sum[7]);
@@ -459,13 +529,13 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_reduce_det(BwdArgs a) {
   }
   // carry-in: the record running into this workgroup, summed over its runs here
   if (tid == 0) {
-    const int r0 = s_head_rec[0];
-    a.carry_rec[2 * wg] = r0;
-    if (r0 >= 0) {
+    const int rin = s_head_rec[0];
+    a.carry_rec[2 * wg] = rin;
+    if (rin >= 0) {
       float sum[9];
 #pragma unroll
       for (int q = 0; q < 9; ++q) sum[q] = 0.f;
-      for (int u = 0; u < kPairThreads && s_head_rec[u] == r0; ++u)
+      for (int u = 0; u < kPairThreads && s_head_rec[u] == rin; ++u)
 #pragma unroll
         for (int q = 0; q < 9; ++q) sum[q] += s_head[u][q];
 #pragma unroll
@@ -1109,9 +1179,9 @@ hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st) {
       return hipErrorInvalidValue;
   }
   {
-    const int64_t per = (int64_t)kPairThreads * kPairRun;
+    const int64_t per = (int64_t)kPairThreads * (det ? kPairRun : kPairSlabs);
     const int64_t nb = (a.kp.cap_dup + per - 1) / per;
-    const dim3 g((unsigned)(nb > 0 ? nb : 1));
+    const dim3 g((unsigned)(nb > 0 ? (det ? nb : min(nb, (int64_t)kPairGrid)) : 1));
     if (det) {
       S3R_LAUNCH(K_PAIR_REDUCE, k_pair_reduce_det, g, dim3(kPairThreads), 0, st, a);
       S3R_LAUNCH(K_PAIR_REDUCE, k_pair_reduce_carry, dim3((unsigned)((nb + 255) / 256 > 0 ? (nb + 255) / 256 : 1)),

@@ -413,6 +413,52 @@ __device__ __forceinline__ bool box_hits(float4 b, float x0, float y0) {
   return (b.y >= x0) && (b.x <= x0 + 7.f) && (b.w >= y0) && (b.z <= y0 + 7.f);
 }
 
+// The records holding the pairs [P, Pe) of a workgroup of NTH threads (each
+// record has at least one pair, so at most Pe - P of them): their first pairs
+// (pair_off, non-decreasing) are staged in s_pair[0 .. nw) and s_pair[nw] is
+// the first pair after them.  The two record searches run cooperatively, NTH
+// probes per round (about three rounds of parallel loads instead of a chain
+// of dependent ones per thread).  Returns the first record; *nw_out gets nw.
+// s_pair holds Pe - P + 2 ints, s_red 2 NTH / 64.
+template <int NTH>
+__device__ __forceinline__ int record_window(const int32_t* __restrict__ pair_off, int nrec,
+                                             int64_t P, int64_t Pe, int* s_pair, int* s_red,
+                                             int* nw_out) {
+  const int tid = threadIdx.x, wave = tid / kWave;
+  constexpr int NW = NTH / kWave;
+  int lo0 = 0, hi0 = nrec - 1, lo1 = 0, hi1 = nrec - 1;  // last record with first pair <= P, <= Pe - 1
+  while (hi0 > lo0 || hi1 > lo1) {  // uniform over the workgroup
+    const int st0 = (hi0 - lo0 + NTH) / NTH;
+    const int st1 = (hi1 - lo1 + NTH) / NTH;
+    const int i0 = lo0 + tid * st0, i1 = lo1 + tid * st1;
+    const bool ok0 = i0 <= hi0 && pair_off[i0] <= P;
+    const bool ok1 = i1 <= hi1 && pair_off[i1] <= Pe - 1;
+    // first pairs are non-decreasing: the probes that pass form a prefix
+    const uint64_t b0 = ballot(ok0), b1 = ballot(ok1);
+    if ((tid % kWave) == 0) {
+      s_red[wave] = __popcll(b0);
+      s_red[NW + wave] = __popcll(b1);
+    }
+    __syncthreads();
+    int c0 = 0, c1 = 0;
+    for (int w = 0; w < NW; ++w) {
+      c0 += s_red[w];
+      c1 += s_red[NW + w];
+    }
+    __syncthreads();
+    lo0 += (c0 - 1) * st0;
+    hi0 = min(hi0, lo0 + st0 - 1);
+    lo1 += (c1 - 1) * st1;
+    hi1 = min(hi1, lo1 + st1 - 1);
+  }
+  const int nw = lo1 - lo0 + 1;
+  for (int i = tid; i <= nw; i += NTH)
+    s_pair[i] = (lo0 + i < nrec) ? pair_off[lo0 + i] : INT32_MAX;
+  __syncthreads();
+  *nw_out = nw;
+  return lo0;
+}
+
 // SH coefficients of one Gaussian (B*3 floats) into registers; 16-byte loads
 // when the per-Gaussian stride keeps them aligned (degrees 1 and 3)
 __device__ __forceinline__ void load_sh(const float* __restrict__ f, int B, float out[48]) {

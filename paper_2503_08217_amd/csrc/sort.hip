@@ -502,50 +502,6 @@ constexpr int kBinBlock = kBinThreads * kBinRun;
 constexpr int kBinMaxTiles = 12288;  // a 48 KB histogram: two workgroups per CU
 constexpr int kBinClaim = 8;         // slot claims in flight per thread
 
-// The records holding the pairs [P, Pe) of this workgroup (each record has at
-// least one pair, so at most Pe - P of them): their first pairs are staged in
-// s_pair[0 .. nw) and s_pair[nw] is the first pair after them.  The two
-// record searches run cooperatively, kBinThreads probes per round (about
-// three rounds of parallel loads instead of a chain of dependent ones per
-// thread).  Returns the first record; *nw_out gets nw.
-__device__ __forceinline__ int record_window(const int32_t* __restrict__ pair_off, int nrec,
-                                             int64_t P, int64_t Pe, int* s_pair, int* s_red,
-                                             int* nw_out) {
-  const int tid = threadIdx.x, wave = tid / kWave;
-  constexpr int NW = kBinThreads / kWave;
-  int lo0 = 0, hi0 = nrec - 1, lo1 = 0, hi1 = nrec - 1;  // last record with first pair <= P, <= Pe - 1
-  while (hi0 > lo0 || hi1 > lo1) {  // uniform over the workgroup
-    const int st0 = (hi0 - lo0 + kBinThreads) / kBinThreads;
-    const int st1 = (hi1 - lo1 + kBinThreads) / kBinThreads;
-    const int i0 = lo0 + tid * st0, i1 = lo1 + tid * st1;
-    const bool ok0 = i0 <= hi0 && pair_off[i0] <= P;
-    const bool ok1 = i1 <= hi1 && pair_off[i1] <= Pe - 1;
-    // first pairs are non-decreasing: the probes that pass form a prefix
-    const uint64_t b0 = ballot(ok0), b1 = ballot(ok1);
-    if ((tid % kWave) == 0) {
-      s_red[wave] = __popcll(b0);
-      s_red[NW + wave] = __popcll(b1);
-    }
-    __syncthreads();
-    int c0 = 0, c1 = 0;
-    for (int w = 0; w < NW; ++w) {
-      c0 += s_red[w];
-      c1 += s_red[NW + w];
-    }
-    __syncthreads();
-    lo0 += (c0 - 1) * st0;
-    hi0 = min(hi0, lo0 + st0 - 1);
-    lo1 += (c1 - 1) * st1;
-    hi1 = min(hi1, lo1 + st1 - 1);
-  }
-  const int nw = lo1 - lo0 + 1;
-  for (int i = tid; i <= nw; i += kBinThreads)
-    s_pair[i] = (lo0 + i < nrec) ? pair_off[lo0 + i] : INT32_MAX;
-  __syncthreads();
-  *nw_out = nw;
-  return lo0;
-}
-
 // the pairs [p0, p1) of this thread (inside the workgroup's window):
 // f(global tile, record, depth bits)
 template <class F>
@@ -599,7 +555,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(SortArgs a) {
   for (int t = tid; t < a.total_tiles; t += kBinThreads) s_h[t] = 0;
   const int64_t Pe = min(ndup, P + kBinBlock);
   int nw;
-  const int r0 = record_window(a.pair_off, nrec, P, Pe, s_pair, s_red, &nw);
+  const int r0 = record_window<kBinThreads>(a.pair_off, nrec, P, Pe, s_pair, s_red, &nw);
   const int64_t p0 = P + (int64_t)tid * kBinRun;
   const int64_t p1 = min(Pe, p0 + kBinRun);
   if (p0 < p1)
@@ -698,7 +654,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_place(SortArgs a) {
   for (int t = tid; t < T; t += kBinThreads) s_h[t] = 0;
   const int64_t Pe = min(ndup, P + kBinBlock);
   int nw;
-  const int r0 = record_window(a.pair_off, nrec, P, Pe, s_pair, s_red, &nw);
+  const int r0 = record_window<kBinThreads>(a.pair_off, nrec, P, Pe, s_pair, s_red, &nw);
   const int64_t p0 = P + (int64_t)tid * kBinRun;
   const int64_t p1 = min(Pe, p0 + kBinRun);
   if (p0 < p1)

@@ -409,6 +409,10 @@ int s3r_plain_transform_bwd(const S3RScene* scene, const int32_t* tsteps, int32_
  *   S3R_TUNE_RASTER_WAVES     waves per workgroup of s3r_raster_fwd: 1 (each
  *       8x8 sub-tile its own workgroup, default) or the tile's sub-tiles
  *       together (TILE^2 / 64; the value is clamped to that)
+ *   S3R_TUNE_FINE_TILES       s3r_raster_fwd gives the first this many tiles
+ *       of the launch order (the longest lists; rounded down to a multiple of
+ *       8) one wave per 4x4 pixel block instead of one per 8x8 sub-tile
+ *       (0..1048576, default 256)
  * s3r_set_tuning(knob, negative value) restores the default.  Errors:
  * S3R_E_ARG for an unknown knob or a value out of range.
  */
@@ -417,7 +421,8 @@ enum {
   S3R_TUNE_SCAN_FUSE_MAX = 1,
   S3R_TUNE_BIN_MAX_TILES = 2,
   S3R_TUNE_RASTER_WAVES = 3,
-  S3R_TUNE_COUNT = 4
+  S3R_TUNE_FINE_TILES = 4,
+  S3R_TUNE_COUNT = 5
 };
 int s3r_set_tuning(int32_t knob, int32_t value);
 int s3r_get_tuning(int32_t knob, int32_t* value);

@@ -22,9 +22,10 @@ S3R_DETERMINISTIC_GRADS = 64
 S3R_VIS_UPDATE, S3R_VIS_FOLD, S3R_VIS_RESET = 0, 1, 2
 S3R_WS_PROJECT, S3R_WS_SORT, S3R_WS_BACKWARD = 0, 1, 2
 S3R_TUNE_OFFSET_FUSE_MAX, S3R_TUNE_SCAN_FUSE_MAX, S3R_TUNE_BIN_MAX_TILES = 0, 1, 2
-S3R_TUNE_RASTER_WAVES = 3
+S3R_TUNE_RASTER_WAVES, S3R_TUNE_FINE_TILES = 3, 4
 TUNE_KNOBS = {"offset_fuse_max": S3R_TUNE_OFFSET_FUSE_MAX, "scan_fuse_max": S3R_TUNE_SCAN_FUSE_MAX,
-              "bin_max_tiles": S3R_TUNE_BIN_MAX_TILES, "raster_waves": S3R_TUNE_RASTER_WAVES}
+              "bin_max_tiles": S3R_TUNE_BIN_MAX_TILES, "raster_waves": S3R_TUNE_RASTER_WAVES,
+              "fine_tiles": S3R_TUNE_FINE_TILES}
 CNT_SURV, CNT_OVF_SURV, CNT_DUP, CNT_OVF_DUP, CNT_SPIN, CNT_PAIRS = 0, 1, 2, 3, 4, 7
 BSTAT = 8  # ints per (256-Gaussian block, view) entry of S3RProjected.bstat
 

@@ -409,8 +409,9 @@ __device__ __forceinline__ float4 cutoff_box(float u, float v, float A, float B,
   const float hy = sqrtf(grow * A) + 0.01f;
   return make_float4(u - hx, u + hx, v - hy, v + hy);
 }
-__device__ __forceinline__ bool box_hits(float4 b, float x0, float y0) {
-  return (b.y >= x0) && (b.x <= x0 + 7.f) && (b.w >= y0) && (b.z <= y0 + 7.f);
+// the box meets the pixel square [x0, x0 + ext] x [y0, y0 + ext]
+__device__ __forceinline__ bool box_hits(float4 b, float x0, float y0, float ext = 7.f) {
+  return (b.y >= x0) && (b.x <= x0 + ext) && (b.w >= y0) && (b.z <= y0 + ext);
 }
 
 // The records holding the pairs [P, Pe) of a workgroup of NTH threads (each

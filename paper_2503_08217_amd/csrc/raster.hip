@@ -2,7 +2,7 @@
 // one launch.
 //
 // One thread per pixel; each wave64 owns an 8x8 sub-tile of its tile and
-// walks the tile's sorted list independently of the other waves (no LDS, no
+// walks the tile's sorted list independently of the other waves (no
 // barriers), so every wave is a workgroup of its own and a wave slot freed
 // by a short sub-tile takes the next one at once (a workgroup of the whole
 // tile would wait for four free slots on one CU).  Workgroups are dealt
@@ -12,37 +12,61 @@
 // launch order.  A batch of 64 entries is fetched
 // lane-parallel; entries whose cutoff box misses the sub-tile (no pixel there
 // could pass the Mahalanobis cut) are dropped with one ballot, and the rest
-// are broadcast from their lane into scalar registers and blended in list
-// order.  A wave stops once all its pixels reached the transmittance floor.
+// are compacted into wave-private LDS rows and blended in list order, each
+// read back with one broadcast load per field (no per-field lane reads on
+// the vector ALU, which bounds this kernel).  A wave stops once all its
+// pixels reached the transmittance floor.
 // Pixels are sampled at integer coordinates (x, y).
 #include "internal.hpp"
 
 namespace s3r {
 
-template <int TS, int WPG>
+template <int TS, int WPG, bool EXTRA>
 __global__ __launch_bounds__(kWave * WPG)
-__attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a) {
+__attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a, int n_fine) {
   constexpr int NW = RasterShape<TS>::NW;
-  constexpr int G = NW / WPG;  // workgroups per tile
-  // id = kXcds (G q + g) + x  ->  tile rank kXcds q + x, sub-tiles g WPG ..
-  // g WPG + WPG - 1 (one per wave)
-  const int xcd = (int)(blockIdx.x % kXcds), k = (int)(blockIdx.x / kXcds);
-  const int rank = (k / G) * kXcds + xcd;
+  constexpr int G = NW / WPG;                    // workgroups per tile (8x8 sub-tiles)
+  constexpr int GF = (TS / 4) * (TS / 4) / WPG;  // workgroups per tile (4x4 blocks)
+  // the entries of the batch being blended that meet the wave's pixels,
+  // compacted in list order (wave-private: written and read by one wave)
+  __shared__ float4 s_geo[WPG][kWave];  // u, v, opacity, record id (bits)
+  __shared__ float4 s_con[WPG][kWave];  // conic A, B, C, -
+  __shared__ float4 s_rgb[WPG][kWave];  // colour, batch lane (bits)
+  // The n_fine first tiles of the launch order (the longest lists; n_fine is
+  // a multiple of kXcds) take one wave per 4x4 block, 16 lanes busy: a wave
+  // then walks only the entries near its block, which shortens the longest
+  // waves of the launch.  The other tiles take one wave per 8x8 sub-tile.
+  // id = kXcds (G q + g) + x  ->  tile rank kXcds q + x, waves g WPG ..
+  // g WPG + WPG - 1 (ids of the 4x4 part first, GF in place of G)
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const unsigned fine_ids = (unsigned)n_fine * GF;
+  const bool fine = blockIdx.x < fine_ids;
+  const unsigned id = fine ? blockIdx.x : blockIdx.x - fine_ids;
+  const int xcd = (int)(id % kXcds), k = (int)(id / kXcds);
+  const int per = fine ? GF : G;
+  const int rank = (fine ? 0 : n_fine) + (k / per) * kXcds + xcd;
   if (rank >= a.total_tiles) return;  // padding of the last group of tiles
-  const int lane = threadIdx.x % kWave;
-  const int tid = ((k % G) * WPG + (int)(threadIdx.x / kWave)) * kWave + lane;  // pixel slot
+  const int sub = (k % per) * WPG + wv;  // the wave's sub-tile or block
   const int t = a.tile_order[rank];
   const int v = find_view(a.tile_offset, a.nv, t);
   const int lt = t - a.tile_offset[v];
   const int W = a.wh[2 * v], H = a.wh[2 * v + 1];
   const int gx = (W + TS - 1) / TS;
   int ox, oy, sx, sy;
-  raster_pixel<TS>(tid, ox, oy, sx, sy);
+  if (fine) {
+    sx = 4 * (sub % (TS / 4));
+    sy = 4 * (sub / (TS / 4));
+    ox = sx + lane % 4;
+    oy = sy + (lane / 4) % 4;
+  } else {
+    raster_pixel<TS>(sub * kWave + lane, ox, oy, sx, sy);
+  }
+  const float ext = fine ? 3.f : 7.f;  // the wave's pixels: [sub, sub + ext]^2
   const int tx0 = (lt % gx) * TS, ty0 = (lt / gx) * TS;
   const int px = tx0 + ox, py = ty0 + oy;
   const float fxp = (float)px, fyp = (float)py;
   const float sub_x = (float)(tx0 + sx), sub_y = (float)(ty0 + sy);
-  const bool inside = (px < W) && (py < H);
+  const bool inside = (px < W) && (py < H) && (!fine || lane < 16);
   const int64_t s = a.tile_start[t];
   const int64_t e = min((int64_t)a.tile_start[t + 1], a.kp.cap_dup);
 
@@ -52,8 +76,10 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a) {
   unsigned long long n_eval = 0, n_blend = 0;  // work census (optional)
   // Each wave walks the tile's list on its own, 64 entries at a time: lane l
   // holds entry b0 + l, one ballot keeps the entries whose cutoff box meets
-  // the wave's sub-tile, and those are broadcast lane by lane.  Loads are
-  // pipelined: record ids two batches ahead, record fields one batch ahead.
+  // the wave's sub-tile, and those are compacted into the wave's LDS rows and
+  // read back one by one (a broadcast read: every lane the same address).
+  // Loads are pipelined: record ids two batches ahead, record fields one
+  // batch ahead.
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
   uint32_t rn = (s + lane < e) ? a.vals[s + lane] : 0u;
   float4 gn = zero4, cn = zero4, kn = zero4;
@@ -77,35 +103,42 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a) {
     rcur = rn;
     rn = (b0 + 2 * kWave + lane < e) ? a.vals[b0 + 2 * kWave + lane] : 0u;
     const bool near =
-        valid && box_hits(cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff), sub_x, sub_y);
-    uint64_t m = ballot(near);
-    while (m != 0ull) {
-      const int j = __builtin_ctzll(m);
-      m &= m - 1ull;
-      const float u = bcast(g.x, j), vv = bcast(g.y, j), o = bcast(g.z, j);
-      const float A = bcast(c.x, j), B = bcast(c.y, j), C = bcast(c.z, j);
-      const Blend bl = blend_eval(u, vv, A, B, C, o, fxp, fyp, a.kp);
-      if (a.census) n_eval += __popcll(ballot(!done));
+        valid && box_hits(cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff), sub_x, sub_y, ext);
+    const uint64_t m = ballot(near);
+    const int n = __popcll(m);
+    if (near) {
+      const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      s_geo[wv][slot] = make_float4(g.x, g.y, g.z, __int_as_float((int)rb));
+      s_con[wv][slot] = c;
+      s_rgb[wv][slot] = make_float4(col.x, col.y, col.z, __int_as_float(lane));
+    }
+    const int base = (int)(b0 - s) + 1;
+    for (int j = 0; j < n; ++j) {
+      if (ballot(!done) == 0ull) break;
+      const float4 eg = s_geo[wv][j], ec = s_con[wv][j], ek = s_rgb[wv][j];
+      const Blend bl = blend_eval(eg.x, eg.y, ec.x, ec.y, ec.z, eg.z, fxp, fyp, a.kp);
+      if (EXTRA && a.census) n_eval += __popcll(ballot(!done));
       const bool hit = bl.hit && !done;
-      if (ballot(hit) == 0ull) continue;  // no pixel of the wave takes it
-      const float kr = bcast(col.x, j), kg = bcast(col.y, j), kb = bcast(col.z, j);
       const float Tn = T * (1.0f - bl.alpha);
       const bool stop = Tn < a.kp.t_min;  // this entry would push T under the floor
       const bool take = hit && !stop;
-      if (a.census) n_blend += __popcll(ballot(take));
       done = done || (hit && stop);
-      const float w = bl.alpha * T;
-      cr = take ? fmaf(kr, w, cr) : cr;
-      cg = take ? fmaf(kg, w, cg) : cg;
-      cb = take ? fmaf(kb, w, cb) : cb;
+      const float w = take ? bl.alpha * T : 0.f;
+      cr = fmaf(ek.x, w, cr);
+      cg = fmaf(ek.y, w, cg);
+      cb = fmaf(ek.z, w, cb);
       T = take ? Tn : T;
-      last = take ? (int)(b0 - s) + j + 1 : last;
-      // rendering-derived visibility: mark the record (every writer stores 1)
-      if (a.rec_taken && ballot(take) != 0ull && lane == 0)
-        a.rec_taken[__builtin_amdgcn_readlane(rb, j)] = 1;
+      last = take ? base + __float_as_int(ek.w) : last;
+      if (EXTRA) {
+        if (a.census) n_blend += __popcll(ballot(take));
+        // rendering-derived visibility: mark the record (every writer stores 1)
+        if (a.rec_taken && ballot(take) != 0ull && lane == 0)
+          a.rec_taken[__float_as_int(eg.w)] = 1;
+      }
     }
   }
-  if (a.census && lane == 0) {
+  if (EXTRA && a.census && lane == 0) {
     atomicAdd(a.census, n_eval);
     atomicAdd(a.census + 1, n_blend);
   }
@@ -149,38 +182,45 @@ hipError_t launch_raster_mask(const int32_t* rec_taken, const int32_t* rec_gid,
 }
 
 template <int TS, int WPG>
-static void launch_fwd_shape(const RasterArgs& a, unsigned groups, hipStream_t st) {
-  constexpr int NW = RasterShape<TS>::NW;
-  const dim3 grid(groups * kXcds * (unsigned)(NW / WPG));
-  S3R_LAUNCH(K_RASTER_FWD, (k_raster_fwd<TS, WPG>), grid, dim3(kWave * WPG), 0, st, a);
+static void launch_fwd_shape(const RasterArgs& a, hipStream_t st) {
+  constexpr int NW = RasterShape<TS>::NW, NB = (TS / 4) * (TS / 4);
+  // tiles in 4x4 blocks: a multiple of kXcds, at most the tile count
+  const int n_fine = min(tune(S3R_TUNE_FINE_TILES), a.total_tiles) / kXcds * kXcds;
+  // the other tiles padded to a multiple of kXcds
+  const unsigned groups = ((unsigned)(a.total_tiles - n_fine) + kXcds - 1) / kXcds;
+  const dim3 grid((unsigned)n_fine * (NB / WPG) + groups * kXcds * (unsigned)(NW / WPG));
+  if (a.census || a.rec_taken)
+    S3R_LAUNCH(K_RASTER_FWD, (k_raster_fwd<TS, WPG, true>), grid, dim3(kWave * WPG), 0, st, a,
+               n_fine);
+  else
+    S3R_LAUNCH(K_RASTER_FWD, (k_raster_fwd<TS, WPG, false>), grid, dim3(kWave * WPG), 0, st, a,
+               n_fine);
 }
 
 // waves per workgroup: the largest power of two up to the knob and the tile's
 // sub-tile count
 template <int TS>
-static void launch_fwd_tile(const RasterArgs& a, unsigned groups, hipStream_t st) {
+static void launch_fwd_tile(const RasterArgs& a, hipStream_t st) {
   constexpr int NW = RasterShape<TS>::NW;
   const int want = min(tune(S3R_TUNE_RASTER_WAVES), NW);
   if constexpr (NW >= 16) {
-    if (want >= 16) return launch_fwd_shape<TS, 16>(a, groups, st);
-    if (want >= 8) return launch_fwd_shape<TS, 8>(a, groups, st);
+    if (want >= 16) return launch_fwd_shape<TS, 16>(a, st);
+    if (want >= 8) return launch_fwd_shape<TS, 8>(a, st);
   }
   if constexpr (NW >= 4) {
-    if (want >= 4) return launch_fwd_shape<TS, 4>(a, groups, st);
-    if (want >= 2) return launch_fwd_shape<TS, 2>(a, groups, st);
+    if (want >= 4) return launch_fwd_shape<TS, 4>(a, st);
+    if (want >= 2) return launch_fwd_shape<TS, 2>(a, st);
   }
-  launch_fwd_shape<TS, 1>(a, groups, st);
+  launch_fwd_shape<TS, 1>(a, st);
 }
 
 hipError_t launch_raster_fwd(const RasterArgs& a, hipStream_t st) {
   if (a.total_tiles <= 0) return hipSuccess;
-  // tiles padded to a multiple of kXcds; the sub-tiles of a tile take
-  // workgroup ids congruent modulo kXcds (one L2)
-  const unsigned groups = ((unsigned)a.total_tiles + kXcds - 1) / kXcds;
+  // the waves of a tile take workgroup ids congruent modulo kXcds (one L2)
   switch (a.kp.tile) {
-    case 8: launch_fwd_tile<8>(a, groups, st); break;
-    case 16: launch_fwd_tile<16>(a, groups, st); break;
-    case 32: launch_fwd_tile<32>(a, groups, st); break;
+    case 8: launch_fwd_tile<8>(a, st); break;
+    case 16: launch_fwd_tile<16>(a, st); break;
+    case 32: launch_fwd_tile<32>(a, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

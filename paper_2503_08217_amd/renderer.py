@@ -303,13 +303,19 @@ class Renderer:
     def work_census(self):
         """Forward of the current batch with the work census: returns the
         (pixel, entry) pairs evaluated (cutoff box met, pixel still blending)
-        and blended, summed over the batch."""
+        and blended, summed over the batch.  The census is taken with every
+        tile in 8x8 sub-tiles (the raster backward's decomposition), so the
+        evaluated count does not depend on S3R_TUNE_FINE_TILES."""
         self.census.zero_()
         if self.plain:
             self.plain_transform()
         self.project_cull()
         self.sort()
-        self.raster_fwd(census=True)
+        old = A.set_tuning(fine_tiles=0)
+        try:
+            self.raster_fwd(census=True)
+        finally:
+            A.set_tuning(**old)
         c = self.census.cpu().numpy()
         return dict(evaluated=int(c[0]), blended=int(c[1]))
 

@@ -225,8 +225,10 @@ def test_launch_paths_agree(which):
     """Every launch path gives the same records, first pairs, lists, launch
     order and image bit for bit: the record/pair offset scan in two launches
     or three (with the top scan), the radix histogram scans likewise, tile
-    binning or the radix tile partition, the full radix sort, and forward
-    workgroups of one wave or of a whole tile's sub-tiles."""
+    binning or the radix tile partition, the full radix sort, forward
+    workgroups of one wave or of a whole tile's sub-tiles, and forward waves
+    of 8x8 sub-tiles or 4x4 blocks (the image, final transmittance and last
+    contributors too)."""
     from paper_2503_08217_amd import _abi as A
     if which == "config1":
         c = scenes.make_config(1)
@@ -235,7 +237,9 @@ def test_launch_paths_agree(which):
         c = scenes.make_config(2, scale_n=0.1)
         views, p = c.views.subset([3, 27, 44]), c.params
     variants = [dict(), dict(offset_fuse_max=0, scan_fuse_max=0), dict(bin_max_tiles=0),
-                dict(raster_waves=16), dict(sort="global", scan_fuse_max=0)]
+                dict(raster_waves=16), dict(sort="global", scan_fuse_max=0), dict(fine_tiles=0),
+                dict(fine_tiles=8), dict(fine_tiles=0, raster_waves=16),
+                dict(fine_tiles=1 << 20, raster_waves=4)]
     out = []
     try:
         for var in variants:
@@ -249,7 +253,8 @@ def test_launch_paths_agree(which):
             out.append((r.rec_gid[:n].cpu().numpy().copy(), r.rec_pair[:n].cpu().numpy().copy(),
                         r.tile_start.cpu().numpy().copy(), r.vals.cpu().numpy()[:nd].copy(),
                         r.tile_order.cpu().numpy().copy(), r.stats.cpu().numpy().copy(),
-                        r.color.cpu().numpy().copy()))
+                        r.color.cpu().numpy().copy(), r.T_final.cpu().numpy().copy(),
+                        r.last.cpu().numpy().copy()))
             A.set_tuning(**{k: -1 for k in knobs})
     finally:
         A.set_tuning(**{k: -1 for k in A.TUNE_KNOBS})

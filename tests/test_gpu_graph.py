@@ -50,9 +50,10 @@ def test_graph_replay_matches_eager():
 
 def test_autotuner_picks_a_shape_that_renders_the_same_image():
     """The library-side autotuner times every (tile, sort, forward waves per
-    workgroup, binning) candidate on a step of an uneven batch, requires each
-    to render the same image bit for bit, and leaves the knobs at the
-    fastest; the renderer it returns renders that image too."""
+    workgroup, binning) candidate on a step of an uneven batch, then the
+    fine-tile counts at the fastest, requires each to render the same image
+    bit for bit, and leaves the knobs at the fastest; the renderer it
+    returns renders that image too."""
     from paper_2503_08217_amd import _abi as A
     from paper_2503_08217_amd.renderer import Renderer
     c = scenes.make_config(4, scale_n=0.01)
@@ -63,13 +64,14 @@ def test_autotuner_picks_a_shape_that_renders_the_same_image():
     banner("autotune")
     try:
         r, res = Renderer.autotuned(c.scene, views, c.params, target, tiles=(8, 16, 32),
-                                    raster_waves=(1, 16), reps=2)
+                                    raster_waves=(1, 16), fine_tiles=(0, 256, 4096), reps=2)
         table, best = res["table"], res["best"]
-        assert len(table) == 3 * (2 * 2 + 2)
+        assert len(table) == 3 * (2 * 2 + 2) + 2
         assert best["ms"] == min(row["ms"] for row in table)
         knobs = A.get_tuning()
         assert knobs["raster_waves"] == best["raster_waves"]
         assert knobs["bin_max_tiles"] == (12288 if best["binning"] else 0)
+        assert knobs["fine_tiles"] == best["fine_tiles"]
         r.forward()
         ref = make_renderer(c.scene, views, c.params)
         ref.forward()

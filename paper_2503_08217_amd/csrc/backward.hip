@@ -600,18 +600,22 @@ __device__ __forceinline__ void wave_segmented_add(int key, const float val[12],
   uint64_t todo = ballot(key >= 0);
   while (todo) {
     const int leader = __ffsll((unsigned long long)todo) - 1;
-    const int lk = __shfl(key, leader, kWave);
+    const int lk = __builtin_amdgcn_readlane(key, leader);
     const bool mine = (key == lk);
     const uint64_t grp = ballot(mine);
+    // twelve independent DPP reductions (no LDS round trips), totals in
+    // lane 63, then the twelve atomics
+    float s[12];
 #pragma unroll
-    for (int q = 0; q < 12; ++q) {
-      const float s = wave_sum(mine ? val[q] : 0.f);
-      if (lane == leader) {
+    for (int q = 0; q < 12; ++q) s[q] = wave_sum_dpp(mine ? val[q] : 0.f);
+    if (lane == kWave - 1) {
+#pragma unroll
+      for (int q = 0; q < 12; ++q) {
         if (fx)
           atomicAdd(fx + (size_t)lk * 12 + q,
-                    (unsigned long long)(long long)__double2ll_rn((double)s * kFixedScale));
+                    (unsigned long long)(long long)__double2ll_rn((double)s[q] * kFixedScale));
         else
-          atomicAdd(dst + (size_t)lk * 12 + q, s);
+          atomicAdd(dst + (size_t)lk * 12 + q, s[q]);
       }
     }
     todo &= ~grp;

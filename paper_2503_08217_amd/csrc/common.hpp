@@ -38,12 +38,6 @@ __device__ __forceinline__ int lane_rank(uint64_t mask) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), lo);
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
-
 // Sum over the 64 lanes with DPP row operations; the total is valid in lane 63.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_add(float x) {
@@ -98,10 +92,9 @@ __device__ __forceinline__ int wave_inclusive_scan(int x) {
   return x;
 }
 
+// wave total, in every lane (DPP scan, then lane 63: no LDS round trips)
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  return (uint32_t)__builtin_amdgcn_readlane(wave_inclusive_scan((int)v), kWave - 1);
 }
 
 // ---------------------------------------------------------------------------

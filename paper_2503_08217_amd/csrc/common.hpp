@@ -407,6 +407,44 @@ __device__ __forceinline__ bool box_hits(float4 b, float x0, float y0, float ext
   return (b.y >= x0) && (b.x <= x0 + ext) && (b.w >= y0) && (b.z <= y0 + ext);
 }
 
+// q = A dx^2 + 2 B dx dy + C dy^2 at dx on the segment dy in [dyl, dyh], at
+// the segment's minimising dy
+__device__ __forceinline__ float edge_min_q(float dx, float dyl, float dyh, float A, float B,
+                                            float C) {
+  const float dy = fminf(fmaxf(-B * dx / C, dyl), dyh);
+  return (A * dx) * dx + (2.f * B * dx) * dy + (C * dy) * dy;
+}
+
+// Can any pixel (x, y) of the square [x0, x0 + ext]^2 pass blend_eval's two
+// tests (-power <= cutoff, alpha >= alpha_min) for a record at (u, v) with
+// conic (A, B, C) and opacity o?  False only when none can.  blend_eval's
+// power is -q/2 with q = A dx^2 + 2 B dx dy + C dy^2 (dx = u - x, dy = v - y);
+// the minimum of q over the square is 0 when (u, v) lies in it and otherwise
+// the least of the four edges' minima (q is convex).  The binary32 power of
+// the kernel and this minimum each differ from the exact values by a few
+// units of rounding relative to A dx^2 + C dy^2 <= q / (1 - rho), rho =
+// |B| / sqrt(A C) < 1 for a positive-definite conic, so the minimum is
+// lowered by 64 u / (1 - rho) relative (u = 2^-24) before the tests, and
+// conics with rho > 0.999 are never skipped.  The alpha test allows the
+// exponential and the opacity product a relative error of 2^-16.
+__device__ __forceinline__ bool square_may_hit(float u, float v, float A, float B, float C,
+                                               float o, float x0, float y0, float ext,
+                                               const KParams& kp) {
+  const float dxl = u - (x0 + ext), dxh = u - x0;
+  const float dyl = v - (y0 + ext), dyh = v - y0;
+  if (dxl <= 0.f && dxh >= 0.f && dyl <= 0.f && dyh >= 0.f)
+    return o * 1.0000153f >= kp.alpha_min;  // alpha <= o e^(rounding) there
+  const float rho = fabsf(B) * __builtin_amdgcn_rsqf(A * C);
+  if (!(A > 0.f) || !(C > 0.f) || !(rho <= 0.999f)) return true;
+  float q = fminf(edge_min_q(dxl, dyl, dyh, A, B, C), edge_min_q(dxh, dyl, dyh, A, B, C));
+  q = fminf(q, edge_min_q(dyl, dxl, dxh, C, B, A));
+  q = fminf(q, edge_min_q(dyh, dxl, dxh, C, B, A));
+  const float qlo = q * (1.f - 3.8147e-6f / (1.f - rho));  // 64 u / (1 - rho)
+  const float pmax = -0.5f * qlo;                             // >= every pixel's power
+  if (-pmax > kp.cutoff) return false;
+  return o * __expf(pmax) * 1.0000153f >= kp.alpha_min;
+}
+
 // The records holding the pairs [P, Pe) of a workgroup of NTH threads (each
 // record has at least one pair, so at most Pe - P of them): their first pairs
 // (pair_off, non-decreasing) are staged in s_pair[0 .. nw) and s_pair[nw] is

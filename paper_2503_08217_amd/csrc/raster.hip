@@ -31,7 +31,7 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a, int n_fi
   // compacted in list order (wave-private: written and read by one wave)
   __shared__ float4 s_geo[WPG][kWave];  // u, v, opacity, record id (bits)
   __shared__ float4 s_con[WPG][kWave];  // conic A, B, C, -
-  __shared__ float4 s_rgb[WPG][kWave];  // colour, batch lane (bits)
+  __shared__ float4 s_rgb[WPG][kWave];  // colour, list position (bits)
   // The n_fine first tiles of the launch order (the longest lists; n_fine is
   // a multiple of kXcds) take one wave per 4x4 block, 16 lanes busy: a wave
   // then walks only the entries near its block, which shortens the longest
@@ -112,11 +112,14 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a, int n_fi
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
       s_geo[wv][slot] = make_float4(g.x, g.y, g.z, __int_as_float((int)rb));
       s_con[wv][slot] = c;
-      s_rgb[wv][slot] = make_float4(col.x, col.y, col.z, __int_as_float(lane));
+      // colour, and the entry's 1-based list position (the pixel's `last`
+      // once it blends the entry)
+      s_rgb[wv][slot] = make_float4(col.x, col.y, col.z, __int_as_float((int)(b0 - s) + lane + 1));
     }
-    const int base = (int)(b0 - s) + 1;
+    // (the batch's entries are blended to the end even if every pixel of the
+    // wave stops on the way: a per-entry exit test costs more than the rare
+    // tail it saves)
     for (int j = 0; j < n; ++j) {
-      if (ballot(!done) == 0ull) break;
       const float4 eg = s_geo[wv][j], ec = s_con[wv][j], ek = s_rgb[wv][j];
       const Blend bl = blend_eval(eg.x, eg.y, ec.x, ec.y, ec.z, eg.z, fxp, fyp, a.kp);
       if (EXTRA && a.census) n_eval += __popcll(ballot(!done));
@@ -130,7 +133,7 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a, int n_fi
       cg = fmaf(ek.y, w, cg);
       cb = fmaf(ek.z, w, cb);
       T = take ? Tn : T;
-      last = take ? base + __float_as_int(ek.w) : last;
+      last = take ? __float_as_int(ek.w) : last;
       if (EXTRA) {
         if (a.census) n_blend += __popcll(ballot(take));
         // rendering-derived visibility: mark the record (every writer stores 1)

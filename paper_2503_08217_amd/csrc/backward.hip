@@ -1224,7 +1224,9 @@ __global__ __launch_bounds__(256) void k_zero_plain_w(const int32_t* __restrict_
 // the Gaussians whose rows this call writes (its records' Gaussians).
 // kClearLanes consecutive lanes clear one listed row: its SH coefficients
 // as contiguous 16-byte stores (whole cache lines), and one lane each its
-// mean, scale, quaternion and opacity
+// mean, scale, quaternion and opacity.  A row whose Gaussian survives in a
+// view of this call is skipped when every survivor got a record: the
+// projection backward then writes that row whole (it owns the Gaussian).
 constexpr int kClearLanes = 16;
 
 __global__ __launch_bounds__(256) void k_clear_rows(const int32_t* __restrict__ rows,
@@ -1233,14 +1235,24 @@ __global__ __launch_bounds__(256) void k_clear_rows(const int32_t* __restrict__ 
                                                     float* __restrict__ scale,
                                                     float* __restrict__ quat,
                                                     float* __restrict__ opac,
-                                                    float* __restrict__ sh) {
+                                                    float* __restrict__ sh,
+                                                    const uint32_t* __restrict__ surv,
+                                                    int64_t mask_words, int nv,
+                                                    const int32_t* __restrict__ counters) {
   const int64_t cnt = *n_rows;
+  const bool all_kept = counters[S3R_CNT_OVF_SURV] == 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < cnt * kClearLanes;
        q += stride) {
     const int i = rows[q / kClearLanes];
     const int sub = (int)(q % kClearLanes);
     if (i < 0 || i >= n) continue;
+    if (all_kept) {
+      bool rewritten = false;
+      for (int v = 0; v < nv && !rewritten; ++v)
+        rewritten = (surv[(size_t)v * mask_words + (i >> 5)] >> (i & 31)) & 1u;
+      if (rewritten) continue;
+    }
     float* s = sh + (size_t)i * 3 * B;
     if (((3 * B) & 3) == 0) {
       float4* s4 = reinterpret_cast<float4*>(s);
@@ -1261,11 +1273,12 @@ __global__ __launch_bounds__(256) void k_clear_rows(const int32_t* __restrict__ 
 
 hipError_t launch_clear_rows(const int32_t* rows, const int32_t* n_rows, int64_t n, int B,
                              float* mean, float* scale, float* quat, float* opac, float* sh,
-                             int64_t cap, hipStream_t st) {
+                             int64_t cap, const uint32_t* surv, int64_t mask_words, int nv,
+                             const int32_t* counters, hipStream_t st) {
   const int64_t want = (cap * kClearLanes + 255) / 256;
   const int grid = (int)(want < 2048 ? (want > 0 ? want : 1) : 2048);
   S3R_LAUNCH(K_ZERO, k_clear_rows, dim3(grid), dim3(256), 0, st, rows, n_rows, n, B, mean, scale,
-             quat, opac, sh);
+             quat, opac, sh, surv, mask_words, nv, counters);
   return hipGetLastError();
 }
 

@@ -592,7 +592,9 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
     }
     if (sparse)
       S3R_HIP(launch_clear_rows(g->rows, g->n_rows, scene->n, (int)B, g->mean, g->scale, g->quat,
-                                g->opacity, g->sh, params->cap_surv, st));
+                                g->opacity, g->sh, params->cap_surv,
+                                reinterpret_cast<const uint32_t*>(proj->surv),
+                                ((scene->n + 63) / 64) * 2, views->n_views, proj->counters, st));
   }
   BwdArgs b{};
   b.rec_geo = reinterpret_cast<const float4*>(proj->rec_geo);

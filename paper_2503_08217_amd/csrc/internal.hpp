@@ -250,7 +250,8 @@ hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st);
 hipError_t launch_project_bwd(const ProjBwdArgs& a, hipStream_t st);
 hipError_t launch_clear_rows(const int32_t* rows, const int32_t* n_rows, int64_t n, int B,
                              float* mean, float* scale, float* quat, float* opac, float* sh,
-                             int64_t cap, hipStream_t st);
+                             int64_t cap, const uint32_t* surv, int64_t mask_words, int nv,
+                             const int32_t* counters, hipStream_t st);
 
 hipError_t launch_pose_bwd_det(const float* W, const int32_t* tstep, const float* pose,
                                const unsigned long long* d_cam_fx, int nv, int S, int T,

@@ -186,8 +186,10 @@ typedef struct S3RProjected {
   int32_t* rec_gid;   /* [cap_surv] Gaussian index of each survivor record    */
   int32_t* rec_view;  /* [cap_surv] view of each record                       */
   float* rec_geo;     /* [cap_surv][4] u, v, opacity, depth                   */
-  float* rec_conic;   /* [cap_surv][4] inverse 2D covariance A, B, C; pad     */
-  float* rec_rgb;     /* [cap_surv][4] r, g, b; pad                           */
+  float* rec_conic;   /* [cap_surv][4] inverse 2D covariance A, B, C, and the
+                         x half-width of the box that holds the pixels which
+                         can pass the Mahalanobis cut (3e38: unbounded)     */
+  float* rec_rgb;     /* [cap_surv][4] r, g, b, and that box's y half-width   */
   int32_t* rec_rect;  /* [cap_surv][4] tile rect x0, y0, x1, y1 (view-local)  */
   int32_t* counters;  /* [16] see S3R_CNT_*                                   */
   int32_t* stats;     /* [V][4] N_t (temporal pass), N_f (= |M_t|), N_r (records),

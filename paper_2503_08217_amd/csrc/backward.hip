@@ -145,7 +145,7 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
       }
       rn = mb >= 2 ? a.vals[b0 - 2 * kWave + lane] : 0u;
       const bool near =
-          valid && box_hits(cutoff_box(g.x, g.y, c.x, c.y, c.z, a.kp.cutoff), sub_x, sub_y) &&
+          valid && box_hits(cutoff_box(g.x, g.y, make_float2(c.w, col.w)), sub_x, sub_y) &&
           square_may_hit(g.x, g.y, c.x, c.y, c.z, g.z, sub_x, sub_y, 7.f, a.kp);
       uint64_t m = ballot(near);
       while (m != 0ull) {

@@ -383,24 +383,27 @@ __device__ __forceinline__ void raster_pixel(int tid, int& ox, int& oy, int& sx,
   oy = sy + (l / 8);
 }
 
-// Bounding box of the pixels where a record can pass the Mahalanobis cut.
-// -power <= cutoff means d^T Q d <= 2 cutoff (Q the conic), an ellipse whose
-// extent along x is sqrt(2 cutoff (Q^-1)_xx) = sqrt(2 cutoff C / det Q).  The
-// rasterizer's binary32 evaluation of the form differs from the exact one by
-// at most ~30 u kappa relative (u = 2^-24, kappa = condition of Q, bounded
-// above by (A + C)^2 / det); the box is grown by that margin so that skipping
-// records outside it never removes a pixel the blend test would keep, and is
-// unbounded when Q is too ill-conditioned for the bound to be useful.
-__device__ __forceinline__ float4 cutoff_box(float u, float v, float A, float B, float C,
-                                             float cutoff) {
+// Half-widths of the bounding box of the pixels where a record can pass the
+// Mahalanobis cut.  -power <= cutoff means d^T Q d <= 2 cutoff (Q the conic),
+// an ellipse whose extent along x is sqrt(2 cutoff (Q^-1)_xx) =
+// sqrt(2 cutoff C / det Q).  The rasterizer's binary32 evaluation of the form
+// differs from the exact one by at most ~30 u kappa relative (u = 2^-24,
+// kappa = condition of Q, bounded above by (A + C)^2 / det); the box is grown
+// by that margin so that skipping records outside it never removes a pixel
+// the blend test would keep, and is unbounded (3e38) when Q is too
+// ill-conditioned for the bound to be useful.  k_records stores them with
+// the record (the conic's and the colour's fourth component), so the
+// rasterizers' per-wave tests take no division or square root.
+__device__ __forceinline__ float2 cutoff_half(float A, float B, float C, float cutoff) {
   const float det = A * C - B * B;
   const float tr = A + C;
   const float kap = tr * tr / det;
-  if (!(det > 0.f) || !(kap < 1.0e5f)) return make_float4(-3.0e38f, 3.0e38f, -3.0e38f, 3.0e38f);
+  if (!(det > 0.f) || !(kap < 1.0e5f)) return make_float2(3.0e38f, 3.0e38f);
   const float grow = 2.f * cutoff * (1.002f + 64.f * 5.9604645e-8f * kap) / det;
-  const float hx = sqrtf(grow * C) + 0.01f;
-  const float hy = sqrtf(grow * A) + 0.01f;
-  return make_float4(u - hx, u + hx, v - hy, v + hy);
+  return make_float2(sqrtf(grow * C) + 0.01f, sqrtf(grow * A) + 0.01f);
+}
+__device__ __forceinline__ float4 cutoff_box(float u, float v, float2 h) {
+  return make_float4(u - h.x, u + h.x, v - h.y, v + h.y);
 }
 // the box meets the pixel square [x0, x0 + ext] x [y0, y0 + ext]
 __device__ __forceinline__ bool box_hits(float4 b, float x0, float y0, float ext = 7.f) {
@@ -408,10 +411,11 @@ __device__ __forceinline__ bool box_hits(float4 b, float x0, float y0, float ext
 }
 
 // q = A dx^2 + 2 B dx dy + C dy^2 at dx on the segment dy in [dyl, dyh], at
-// the segment's minimising dy
+// the segment's minimising dy (rC = 1 / C to about an ulp: a dy off the
+// minimiser by e raises q by C e^2, far inside the caller's margin)
 __device__ __forceinline__ float edge_min_q(float dx, float dyl, float dyh, float A, float B,
-                                            float C) {
-  const float dy = fminf(fmaxf(-B * dx / C, dyl), dyh);
+                                            float C, float rC) {
+  const float dy = fminf(fmaxf(-B * dx * rC, dyl), dyh);
   return (A * dx) * dx + (2.f * B * dx) * dy + (C * dy) * dy;
 }
 
@@ -436,10 +440,12 @@ __device__ __forceinline__ bool square_may_hit(float u, float v, float A, float 
     return o * 1.0000153f >= kp.alpha_min;  // alpha <= o e^(rounding) there
   const float rho = fabsf(B) * __builtin_amdgcn_rsqf(A * C);
   if (!(A > 0.f) || !(C > 0.f) || !(rho <= 0.999f)) return true;
-  float q = fminf(edge_min_q(dxl, dyl, dyh, A, B, C), edge_min_q(dxh, dyl, dyh, A, B, C));
-  q = fminf(q, edge_min_q(dyl, dxl, dxh, C, B, A));
-  q = fminf(q, edge_min_q(dyh, dxl, dxh, C, B, A));
-  const float qlo = q * (1.f - 3.8147e-6f / (1.f - rho));  // 64 u / (1 - rho)
+  const float rA = __builtin_amdgcn_rcpf(A), rC = __builtin_amdgcn_rcpf(C);
+  float q = fminf(edge_min_q(dxl, dyl, dyh, A, B, C, rC), edge_min_q(dxh, dyl, dyh, A, B, C, rC));
+  q = fminf(q, edge_min_q(dyl, dxl, dxh, C, B, A, rA));
+  q = fminf(q, edge_min_q(dyh, dxl, dxh, C, B, A, rA));
+  // 64 u / (1 - rho), the reciprocal rounded down by at most a few ulp
+  const float qlo = q * (1.f - 3.8148e-6f * __builtin_amdgcn_rcpf(1.f - rho));
   const float pmax = -0.5f * qlo;                             // >= every pixel's power
   if (-pmax > kp.cutoff) return false;
   return o * __expf(pmax) * 1.0000153f >= kp.alpha_min;

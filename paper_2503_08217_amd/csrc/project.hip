@@ -561,7 +561,12 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_records(ProjArgs a) {
     a.rec_gid[slot] = i;
     a.rec_view[slot] = v;
     a.rec_geo[slot] = make_float4(o.u, o.v, a.opac[i], o.pz);
-    a.rec_conic[slot] = make_float4(o.c / o.det, (-o.b) / o.det, o.a / o.det, 0.f);
+    {
+      // the conic, and the cutoff box's x half-width (the y one goes with
+      // the colour in pass 2)
+      const float A = o.c / o.det, Bc = (-o.b) / o.det, C = o.a / o.det;
+      a.rec_conic[slot] = make_float4(A, Bc, C, cutoff_half(A, Bc, C, a.kp.cutoff).x);
+    }
     a.rec_rect[slot] = make_int4(o.x0, o.y0, o.x1, o.y1);
     a.rec_npairs[slot] = (o.x1 - o.x0) * (o.y1 - o.y0);
   }
@@ -637,7 +642,8 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_records(ProjArgs a) {
     gg = fmaxf(gg + 0.5f, 0.f);
     bb = fmaxf(bb + 0.5f, 0.f);
 
-    a.rec_rgb[slot] = make_float4(r, gg, bb, 0.f);
+    const float4 cq = a.rec_conic[slot];  // (written by this lane in pass 1)
+    a.rec_rgb[slot] = make_float4(r, gg, bb, cutoff_half(cq.x, cq.y, cq.z, a.kp.cutoff).y);
   }
 }
 

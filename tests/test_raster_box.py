@@ -86,14 +86,15 @@ def square_may_hit32(u, v, A, B, C, o, x0, y0, ext, alpha_min):
     rho = (np.abs(B) * (one / np.sqrt((A * C).astype(np.float64))).astype(f32)).astype(f32)
 
     def edge(dx, lo, hi, A_, B_, C_):
-        dy = np.minimum(np.maximum((-B_ * dx / C_).astype(f32), lo), hi)
+        rC = (one / C_).astype(f32)  # the kernels take a hardware reciprocal
+        dy = np.minimum(np.maximum(((-B_ * dx).astype(f32) * rC).astype(f32), lo), hi)
         return (((A_ * dx).astype(f32) * dx).astype(f32) + ((f32(2.0) * B_ * dx).astype(f32) * dy).astype(f32)
                 + ((C_ * dy).astype(f32) * dy).astype(f32)).astype(f32)
 
     q = np.minimum(edge(dxl, dyl, dyh, A, B, C), edge(dxh, dyl, dyh, A, B, C))
     q = np.minimum(q, edge(dyl, dxl, dxh, C, B, A))
     q = np.minimum(q, edge(dyh, dxl, dxh, C, B, A))
-    qlo = (q * (one - (f32(3.8147e-6) / (one - rho)).astype(f32))).astype(f32)
+    qlo = (q * (one - (f32(3.8148e-6) * (one / (one - rho)).astype(f32)).astype(f32))).astype(f32)
     pmax = (f32(-0.5) * qlo).astype(f32)
     alpha_ok = (o * np.exp(pmax.astype(np.float64)).astype(f32) * f32(1.0000153)).astype(f32) >= alpha_min
     out = np.where(-pmax > CUTOFF, False, alpha_ok)

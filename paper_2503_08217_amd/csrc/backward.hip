@@ -50,6 +50,8 @@ struct BwdWindow {
   static constexpr int COPIES = DET ? NW : 1;
 };
 
+constexpr int kBwdRun = 4;  // consecutive launch-order tiles per XCD
+
 template <int TS, bool DET>
 // (64 VGPRs: eight waves per SIMD)
 __global__ __launch_bounds__(RasterShape<TS>::NT)
@@ -64,7 +66,15 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
   __shared__ int s_max[NW];
   const int tid = threadIdx.x;
   const int lane = tid % kWave, wave = tid / kWave;
-  const int t = a.tile_order[blockIdx.x];
+  // launch-order rank of this workgroup's tile: runs of kBwdRun consecutive
+  // ranks (neighbouring tiles of a length bucket, which share records) on one
+  // XCD, the runs dealt round-robin to the XCDs (so the longest lists still
+  // start first on every XCD); the grid is padded to whole rounds
+  const int kb = (int)(blockIdx.x / kXcds);
+  const int rank = (kb / kBwdRun) * (kXcds * kBwdRun) + (int)(blockIdx.x % kXcds) * kBwdRun +
+                   kb % kBwdRun;
+  if (rank >= a.total_tiles) return;  // padding (uniform over the workgroup)
+  const int t = a.tile_order[rank];
   const int v = find_view(a.tile_offset, a.nv, t);
   const int lt = t - a.tile_offset[v];
   const int W = a.wh[2 * v], H = a.wh[2 * v + 1];
@@ -1166,7 +1176,8 @@ hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st) {
              a.n_zero_a, a.zero_b, a.n_zero_b);
   if (a.total_tiles <= 0) return hipGetLastError();
   const bool det = (a.kp.flags & S3R_DETERMINISTIC_GRADS) != 0;
-  const dim3 grid(a.total_tiles);
+  const unsigned round = kXcds * kBwdRun;
+  const dim3 grid(((unsigned)a.total_tiles + round - 1) / round * round);
   switch (a.kp.tile) {
     case 8:
       if (det) S3R_LAUNCH(K_RASTER_BWD, (k_raster_bwd<8, true>), grid, dim3(64), 0, st, a);

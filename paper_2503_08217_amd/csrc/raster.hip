@@ -21,6 +21,8 @@
 
 namespace s3r {
 
+constexpr int kFwdRun = 4;  // consecutive launch-order tiles per XCD
+
 template <int TS, int WPG, bool EXTRA>
 __global__ __launch_bounds__(kWave * WPG)
 __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a, int n_fine) {
@@ -33,19 +35,24 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a, int n_fi
   __shared__ float4 s_con[WPG][kWave];  // conic A, B, C, -
   __shared__ float4 s_rgb[WPG][kWave];  // colour, list position (bits)
   // The n_fine first tiles of the launch order (the longest lists; n_fine is
-  // a multiple of kXcds) take one wave per 4x4 block, 16 lanes busy: a wave
+  // a multiple of kXcds kFwdRun) take one wave per 4x4 block, 16 lanes busy: a wave
   // then walks only the entries near its block, which shortens the longest
   // waves of the launch.  The other tiles take one wave per 8x8 sub-tile.
-  // id = kXcds (G q + g) + x  ->  tile rank kXcds q + x, waves g WPG ..
-  // g WPG + WPG - 1 (ids of the 4x4 part first, GF in place of G)
+  // id = kXcds (G q + g) + x  ->  the q-th tile of XCD x, waves g WPG ..
+  // g WPG + WPG - 1 (ids of the 4x4 part first, GF in place of G); an XCD
+  // takes runs of kFwdRun consecutive launch-order ranks (neighbouring tiles
+  // of a length bucket share records in its L2), the runs dealt round-robin
+  // to the XCDs, so the longest lists still start first on every XCD
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
   const unsigned fine_ids = (unsigned)n_fine * GF;
   const bool fine = blockIdx.x < fine_ids;
   const unsigned id = fine ? blockIdx.x : blockIdx.x - fine_ids;
   const int xcd = (int)(id % kXcds), k = (int)(id / kXcds);
   const int per = fine ? GF : G;
-  const int rank = (fine ? 0 : n_fine) + (k / per) * kXcds + xcd;
-  if (rank >= a.total_tiles) return;  // padding of the last group of tiles
+  const int q = k / per;
+  const int rank = (fine ? 0 : n_fine) + (q / kFwdRun) * (kXcds * kFwdRun) + xcd * kFwdRun +
+                   q % kFwdRun;
+  if (rank >= (fine ? n_fine : a.total_tiles)) return;  // padding of the last round
   const int sub = (k % per) * WPG + wv;  // the wave's sub-tile or block
   const int t = a.tile_order[rank];
   const int v = find_view(a.tile_offset, a.nv, t);
@@ -188,10 +195,12 @@ hipError_t launch_raster_mask(const int32_t* rec_taken, const int32_t* rec_gid,
 template <int TS, int WPG>
 static void launch_fwd_shape(const RasterArgs& a, hipStream_t st) {
   constexpr int NW = RasterShape<TS>::NW, NB = (TS / 4) * (TS / 4);
-  // tiles in 4x4 blocks: a multiple of kXcds, at most the tile count
-  const int n_fine = min(tune(S3R_TUNE_FINE_TILES), a.total_tiles) / kXcds * kXcds;
-  // the other tiles padded to a multiple of kXcds
-  const unsigned groups = ((unsigned)(a.total_tiles - n_fine) + kXcds - 1) / kXcds;
+  // tiles in 4x4 blocks: a multiple of kXcds kFwdRun, at most the tile count
+  const int n_fine =
+      min(tune(S3R_TUNE_FINE_TILES), a.total_tiles) / (kXcds * kFwdRun) * (kXcds * kFwdRun);
+  // the other tiles padded to whole rounds of kXcds kFwdRun
+  const unsigned round = kXcds * kFwdRun;
+  const unsigned groups = ((unsigned)(a.total_tiles - n_fine) + round - 1) / round * kFwdRun;
   const dim3 grid((unsigned)n_fine * (NB / WPG) + groups * kXcds * (unsigned)(NW / WPG));
   if (a.census || a.rec_taken)
     S3R_LAUNCH(K_RASTER_FWD, (k_raster_fwd<TS, WPG, true>), grid, dim3(kWave * WPG), 0, st, a,

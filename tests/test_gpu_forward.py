@@ -238,7 +238,7 @@ def test_launch_paths_agree(which):
         views, p = c.views.subset([3, 27, 44]), c.params
     variants = [dict(), dict(offset_fuse_max=0, scan_fuse_max=0), dict(bin_max_tiles=0),
                 dict(raster_waves=16), dict(sort="global", scan_fuse_max=0), dict(fine_tiles=0),
-                dict(fine_tiles=8), dict(fine_tiles=0, raster_waves=16),
+                dict(fine_tiles=32), dict(fine_tiles=0, raster_waves=16),
                 dict(fine_tiles=1 << 20, raster_waves=4)]
     out = []
     try:

@@ -67,7 +67,7 @@ KERNEL_SOURCES = {
 
 # kernels of steps a1-a8 (instance cameras through tile ranges)
 PCS_KERNELS = ("compose", "project", "block_offsets", "records", "scan", "emit_pairs", "radix",
-               "tile_ranges", "tile_order", "tile_sort", "tile_sort_chunks", "tile_sort_merge",
+               "tile_ranges", "tile_order", "tile_sort", "tile_sort_merge",
                "tile_bin")
 
 

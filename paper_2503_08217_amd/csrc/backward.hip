@@ -999,76 +999,10 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_project_bwd(ProjBwdArgs a) {
   if (a.n_rows && blockIdx.x == 0 && threadIdx.x == 0) *a.n_rows = nrec;
 }
 
-// dL/dG_{tau,k} += W_R^T dL/dP_{v,k} for every view v (slot 0 skipped)
-__global__ void k_pose_bwd(const float* __restrict__ W, const int32_t* __restrict__ tstep,
-                           const float* __restrict__ d_cam, int nv, int S, int T,
-                           float* __restrict__ d_pose) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nv * S) return;
-  const int v = idx / S, k = idx % S;
-  if (k == 0) return;
-  const float* w = W + v * 12;
-  const float* dP = d_cam + (size_t)idx * 12;
-  float* dG = d_pose + ((size_t)clampi(tstep[v], 0, T - 1) * S + k) * 12;
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const float g = w[0 * 4 + r] * dP[0 * 4 + c] + w[1 * 4 + r] * dP[1 * 4 + c] +
-                      w[2 * 4 + r] * dP[2 * 4 + c];
-      if (g != 0.f) atomicAdd(dG + r * 4 + c, g);
-    }
-}
-
-// deterministic mode: one thread per (timestep, slot) sums the fixed-point
-// camera gradients of the batch's views at that timestep, in view order, and
-// writes dL/dG_{tau,k} = sum_v W_R^T dL/dP_{v,k} (slot 0 skipped)
-__global__ void k_pose_bwd_det(const float* __restrict__ W, const int32_t* __restrict__ tstep,
-                               const unsigned long long* __restrict__ d_cam_fx, int nv, int S,
-                               int T, float* __restrict__ d_pose) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= T * S) return;
-  const int tau = idx / S, k = idx % S;
-  if (k == 0) return;
-  float g[12];
-#pragma unroll
-  for (int q = 0; q < 12; ++q) g[q] = 0.f;
-  bool any = false;
-  for (int v = 0; v < nv; ++v) {
-    if (clampi(tstep[v], 0, T - 1) != tau) continue;
-    any = true;
-    const float* w = W + v * 12;
-    float dP[12];
-#pragma unroll
-    for (int q = 0; q < 12; ++q)
-      dP[q] = (float)((double)(long long)d_cam_fx[((size_t)v * S + k) * 12 + q] / kFixedScale);
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-        g[r * 4 + c] += w[0 * 4 + r] * dP[0 * 4 + c] + w[1 * 4 + r] * dP[1 * 4 + c] +
-                        w[2 * 4 + r] * dP[2 * 4 + c];
-  }
-  if (!any) return;
-  float* dG = d_pose + ((size_t)tau * S + k) * 12;
-#pragma unroll
-  for (int q = 0; q < 12; ++q) dG[q] = g[q];
-}
-
-// 6-DoF form of the pose gradient: M = G~^T D, rho = M[0:3,3],
-// omega = (M21 - M12, M02 - M20, M10 - M01)
-__global__ void k_pose6(const float* __restrict__ pose, const float* __restrict__ d_pose, int TS_,
-                        int S, float* __restrict__ d_pose6) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= TS_) return;
-  float* o = d_pose6 + (size_t)idx * 6;
-  if (idx % S == 0) {  // slot 0 (static Gaussians) has no pose
-#pragma unroll
-    for (int c = 0; c < 6; ++c) o[c] = 0.f;
-    return;
-  }
-  const float* G = pose + (size_t)idx * 12;
-  const float* D = d_pose + (size_t)idx * 12;
+// 6-DoF form of one pose gradient D (3x4) at pose G: M = G~^T D,
+// rho = M[0:3,3], omega = (M21 - M12, M02 - M20, M10 - M01)
+__device__ __forceinline__ void pose6_of(const float* __restrict__ G, const float (&D)[12],
+                                         float* __restrict__ o) {
   float M[12];  // rows 0..2 of G~^T D: M[i][c] = sum_r G[r][i] D[r][c]
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -1080,6 +1014,70 @@ __global__ void k_pose6(const float* __restrict__ pose, const float* __restrict_
   o[3] = M[2 * 4 + 1] - M[1 * 4 + 2];
   o[4] = M[0 * 4 + 2] - M[2 * 4 + 0];
   o[5] = M[1 * 4 + 0] - M[0 * 4 + 1];
+}
+
+// One thread per (timestep, slot): dL/dG_{tau,k} = sum over the batch's views
+// v at timestep tau, in view order, of W_R^T dL/dP_{v,k}, written whole (no
+// atomics), and with d_pose6 its 6-DoF form.  Slot 0 (static Gaussians) has
+// no pose: its rows are left at the zeros the call wrote.  The camera
+// gradients are float sums, or with kFixed the fixed-point sums of the
+// deterministic mode.
+template <bool kFixed>
+__global__ void k_pose_bwd(const float* __restrict__ W, const int32_t* __restrict__ tstep,
+                           const void* __restrict__ d_cam_any, int nv, int S, int T,
+                           const float* __restrict__ pose, float* __restrict__ d_pose,
+                           float* __restrict__ d_pose6) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= T * S) return;
+  const int tau = idx / S, k = idx % S;
+  if (k == 0) {
+    if (d_pose6 != nullptr)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) d_pose6[(size_t)idx * 6 + c] = 0.f;
+    return;
+  }
+  float g[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) g[q] = 0.f;
+  for (int v = 0; v < nv; ++v) {
+    if (clampi(tstep[v], 0, T - 1) != tau) continue;
+    const float* w = W + v * 12;
+    const size_t c0 = ((size_t)v * S + k) * 12;
+    float dP[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q)
+      dP[q] = kFixed
+                  ? (float)((double)(long long)static_cast<const unsigned long long*>(d_cam_any)[c0 + q] /
+                            kFixedScale)
+                  : static_cast<const float*>(d_cam_any)[c0 + q];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        g[r * 4 + c] += w[0 * 4 + r] * dP[0 * 4 + c] + w[1 * 4 + r] * dP[1 * 4 + c] +
+                        w[2 * 4 + r] * dP[2 * 4 + c];
+  }
+  float* dG = d_pose + (size_t)idx * 12;
+#pragma unroll
+  for (int q = 0; q < 12; ++q) dG[q] = g[q];
+  if (d_pose6 != nullptr) pose6_of(pose + (size_t)idx * 12, g, d_pose6 + (size_t)idx * 6);
+}
+
+// 6-DoF form of pose gradients summed elsewhere (plain route)
+__global__ void k_pose6(const float* __restrict__ pose, const float* __restrict__ d_pose, int TS_,
+                        int S, float* __restrict__ d_pose6) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= TS_) return;
+  float* o = d_pose6 + (size_t)idx * 6;
+  if (idx % S == 0) {  // slot 0 (static Gaussians) has no pose
+#pragma unroll
+    for (int c = 0; c < 6; ++c) o[c] = 0.f;
+    return;
+  }
+  float D[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) D[q] = d_pose[(size_t)idx * 12 + q];
+  pose6_of(pose + (size_t)idx * 12, D, o);
 }
 
 // plain route: world-frame gradients -> local mean / quaternion and poses
@@ -1171,9 +1169,15 @@ __global__ __launch_bounds__(256) void k_zero_g2d(float4* __restrict__ g2d,
     for (int64_t i = i0; i < nb; i += stride) zb[i] = 0.f;
 }
 
-hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st) {
+hipError_t launch_zero_g2d(const BwdArgs& a, hipStream_t st) {
   S3R_LAUNCH(K_ZERO_G2D, k_zero_g2d, dim3(1024), dim3(256), 0, st, a.g2d, a.counters, a.zero_a,
              a.n_zero_a, a.zero_b, a.n_zero_b);
+  return hipGetLastError();
+}
+
+// (the gradient slots and accumulators are cleared before this launch, by
+// launch_zero_g2d or launch_clear_rows)
+hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st) {
   if (a.total_tiles <= 0) return hipGetLastError();
   const bool det = (a.kp.flags & S3R_DETERMINISTIC_GRADS) != 0;
   const unsigned round = kXcds * kBwdRun;
@@ -1232,7 +1236,9 @@ __global__ __launch_bounds__(256) void k_zero_plain_w(const int32_t* __restrict_
 }
 
 // Sparse gradient mode: clear the rows the previous call wrote, and record
-// the Gaussians whose rows this call writes (its records' Gaussians).
+// the Gaussians whose rows this call writes (its records' Gaussians); the
+// same launch clears the per-record gradient slots and the two small
+// accumulators, as k_zero_g2d does in the dense mode.
 // kClearLanes consecutive lanes clear one listed row: its SH coefficients
 // as contiguous 16-byte stores (whole cache lines), and one lane each its
 // mean, scale, quaternion and opacity.  A row whose Gaussian survives in a
@@ -1249,10 +1255,22 @@ __global__ __launch_bounds__(256) void k_clear_rows(const int32_t* __restrict__ 
                                                     float* __restrict__ sh,
                                                     const uint32_t* __restrict__ surv,
                                                     int64_t mask_words, int nv,
-                                                    const int32_t* __restrict__ counters) {
+                                                    const int32_t* __restrict__ counters,
+                                                    float4* __restrict__ g2d,
+                                                    float* __restrict__ za, int64_t na,
+                                                    float* __restrict__ zb, int64_t nb) {
   const int64_t cnt = *n_rows;
   const bool all_kept = counters[S3R_CNT_OVF_SURV] == 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ng = 3 * (int64_t)counters[S3R_CNT_SURV];
+    for (int64_t j = i0; j < ng; j += stride) g2d[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (za)
+      for (int64_t j = i0; j < na; j += stride) za[j] = 0.f;
+    if (zb)
+      for (int64_t j = i0; j < nb; j += stride) zb[j] = 0.f;
+  }
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < cnt * kClearLanes;
        q += stride) {
     const int i = rows[q / kClearLanes];
@@ -1285,11 +1303,13 @@ __global__ __launch_bounds__(256) void k_clear_rows(const int32_t* __restrict__ 
 hipError_t launch_clear_rows(const int32_t* rows, const int32_t* n_rows, int64_t n, int B,
                              float* mean, float* scale, float* quat, float* opac, float* sh,
                              int64_t cap, const uint32_t* surv, int64_t mask_words, int nv,
-                             const int32_t* counters, hipStream_t st) {
+                             const BwdArgs& a, hipStream_t st) {
+  // (at least the dense mode's 1024 workgroups for the per-record slots)
   const int64_t want = (cap * kClearLanes + 255) / 256;
-  const int grid = (int)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+  const int grid = (int)(want < 2048 ? (want > 1024 ? want : 1024) : 2048);
   S3R_LAUNCH(K_ZERO, k_clear_rows, dim3(grid), dim3(256), 0, st, rows, n_rows, n, B, mean, scale,
-             quat, opac, sh, surv, mask_words, nv, counters);
+             quat, opac, sh, surv, mask_words, nv, a.counters, a.g2d, a.zero_a, a.n_zero_a,
+             a.zero_b, a.n_zero_b);
   return hipGetLastError();
 }
 
@@ -1308,27 +1328,23 @@ hipError_t launch_pose_bwd_det(const float* W, const int32_t* tstep, const float
                                const unsigned long long* d_cam_fx, int nv, int S, int T,
                                float* d_pose, float* d_pose6, hipStream_t st) {
   const int ts = T * S;
-  if (ts > 0) {
-    S3R_LAUNCH(K_POSE_BWD, k_pose_bwd_det, dim3((ts + 127) / 128), dim3(128), 0, st, W, tstep,
-               d_cam_fx, nv, S, T, d_pose);
-    if (d_pose6 != nullptr)
-      S3R_LAUNCH(K_POSE6, k_pose6, dim3((ts + 127) / 128), dim3(128), 0, st, pose, d_pose, ts, S,
-                 d_pose6);
-  }
+  if (ts > 0)
+    S3R_LAUNCH(K_POSE_BWD, k_pose_bwd<true>, dim3((ts + 127) / 128), dim3(128), 0, st, W, tstep,
+               d_cam_fx, nv, S, T, pose, d_pose, d_pose6);
   return hipGetLastError();
 }
 
 hipError_t launch_pose_bwd(const float* W, const int32_t* tstep, const float* pose,
                            const float* d_cam, int nv, int S, int T, float* d_pose,
                            float* d_pose6, hipStream_t st) {
-  const int nvs = nv * S;
-  if (d_cam != nullptr && nvs > 0)
-    S3R_LAUNCH(K_POSE_BWD, k_pose_bwd, dim3((nvs + 127) / 128), dim3(128), 0, st, W, tstep, d_cam, nv,
-                       S, T, d_pose);
   const int ts = T * S;
-  if (d_pose6 != nullptr && ts > 0)
+  if (ts <= 0) return hipGetLastError();
+  if (d_cam != nullptr)
+    S3R_LAUNCH(K_POSE_BWD, k_pose_bwd<false>, dim3((ts + 127) / 128), dim3(128), 0, st, W, tstep,
+               d_cam, nv, S, T, pose, d_pose, d_pose6);
+  else if (d_pose6 != nullptr)
     S3R_LAUNCH(K_POSE6, k_pose6, dim3((ts + 127) / 128), dim3(128), 0, st, pose, d_pose, ts, S,
-                       d_pose6);
+               d_pose6);
   return hipGetLastError();
 }
 

@@ -577,25 +577,6 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   const hipStream_t st = as_stream(stream);
   const KParams kp = kparams(*params);
 
-  {
-    // every gradient output is written by this call: clear the dense arrays
-    // (Gaussians without records keep these zeros) and the accumulators
-    const size_t N = (size_t)scene->n;
-    const size_t B = (size_t)(scene->sh_degree + 1) * (scene->sh_degree + 1);
-    // (the camera and pose accumulators are cleared with the per-record
-    // gradient slots, inside launch_raster_bwd)
-    if (!sparse) {
-      void* ps[5] = {g->scale, g->opacity, g->sh, plain ? nullptr : g->mean,
-                     plain ? nullptr : g->quat};
-      const size_t bs[5] = {N * 12, N * 4, N * B * 12, N * 12, N * 16};
-      S3R_HIP(launch_zero_n(ps, bs, 5, st));
-    }
-    if (sparse)
-      S3R_HIP(launch_clear_rows(g->rows, g->n_rows, scene->n, (int)B, g->mean, g->scale, g->quat,
-                                g->opacity, g->sh, params->cap_surv,
-                                reinterpret_cast<const uint32_t*>(proj->surv),
-                                ((scene->n + 63) / 64) * 2, views->n_views, proj->counters, st));
-  }
   BwdArgs b{};
   b.rec_geo = reinterpret_cast<const float4*>(proj->rec_geo);
   b.rec_conic = reinterpret_cast<const float4*>(proj->rec_conic);
@@ -628,6 +609,27 @@ int s3r_raster_bwd(const S3RScene* scene, const S3RViews* views, const S3RParams
   b.n_zero_b = (int64_t)scene->n_timesteps * scene->n_slots * 12;
   b.g2d = w.g2d;
   b.kp = kp;
+  {
+    // every gradient output is written by this call: clear the dense arrays
+    // (Gaussians without records keep these zeros), the per-record gradient
+    // slots and the camera and pose accumulators -- in the sparse mode the
+    // rows the previous call wrote instead of the dense arrays, all in one
+    // launch
+    const size_t N = (size_t)scene->n;
+    const size_t B = (size_t)(scene->sh_degree + 1) * (scene->sh_degree + 1);
+    if (sparse) {
+      S3R_HIP(launch_clear_rows(g->rows, g->n_rows, scene->n, (int)B, g->mean, g->scale, g->quat,
+                                g->opacity, g->sh, params->cap_surv,
+                                reinterpret_cast<const uint32_t*>(proj->surv),
+                                ((scene->n + 63) / 64) * 2, views->n_views, b, st));
+    } else {
+      void* ps[5] = {g->scale, g->opacity, g->sh, plain ? nullptr : g->mean,
+                     plain ? nullptr : g->quat};
+      const size_t bs[5] = {N * 12, N * 4, N * B * 12, N * 12, N * 16};
+      S3R_HIP(launch_zero_n(ps, bs, 5, st));
+      S3R_HIP(launch_zero_g2d(b, st));
+    }
+  }
   S3R_HIP(launch_raster_bwd(b, st));
 
   ProjBwdArgs p{};

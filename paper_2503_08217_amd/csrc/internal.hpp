@@ -9,7 +9,7 @@ namespace s3r {
 // kernels timed by the opt-in profiler (names in profile.hip)
 enum KernelId {
   K_COMPOSE, K_PLAIN_TRANSFORM, K_PROJECT, K_STATS, K_RECORDS, K_SCAN, K_EMIT, K_RADIX,
-  K_TILE_RANGES, K_TILE_ORDER, K_TILE_SORT, K_TILE_SORT_CHUNKS, K_TILE_SORT_MERGE, K_TILE_BIN,
+  K_TILE_RANGES, K_TILE_ORDER, K_TILE_SORT, K_TILE_SORT_MERGE, K_TILE_BIN,
   K_RASTER_FWD, K_L1, K_ZERO_G2D, K_RASTER_BWD, K_PAIR_REDUCE, K_PROJECT_BWD,
   K_POSE_BWD, K_POSE6, K_PLAIN_TRANSFORM_BWD, K_VISIBILITY, K_ZERO, K_COUNT
 };
@@ -246,12 +246,14 @@ hipError_t launch_l1_loss(const float* color, const float* target, const int64_t
                           float* d_color, hipStream_t st);
 
 // backward.hip
+hipError_t launch_zero_g2d(const BwdArgs& a, hipStream_t st);
 hipError_t launch_raster_bwd(const BwdArgs& a, hipStream_t st);
 hipError_t launch_project_bwd(const ProjBwdArgs& a, hipStream_t st);
+// (also clears what launch_zero_g2d clears: a.g2d, a.zero_a, a.zero_b)
 hipError_t launch_clear_rows(const int32_t* rows, const int32_t* n_rows, int64_t n, int B,
                              float* mean, float* scale, float* quat, float* opac, float* sh,
                              int64_t cap, const uint32_t* surv, int64_t mask_words, int nv,
-                             const int32_t* counters, hipStream_t st);
+                             const BwdArgs& a, hipStream_t st);
 
 hipError_t launch_pose_bwd_det(const float* W, const int32_t* tstep, const float* pose,
                                const unsigned long long* d_cam_fx, int nv, int S, int T,

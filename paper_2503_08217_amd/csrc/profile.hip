@@ -9,7 +9,7 @@ namespace s3r {
 
 static const char* kNames[K_COUNT] = {
     "compose", "plain_transform", "project", "block_offsets", "records", "scan", "emit_pairs",
-    "radix", "tile_ranges", "tile_order", "tile_sort", "tile_sort_chunks", "tile_sort_merge",
+    "radix", "tile_ranges", "tile_order", "tile_sort", "tile_sort_merge",
     "tile_bin", "raster_fwd", "l1_loss", "zero_g2d", "raster_bwd", "pair_reduce",
     "project_bwd", "pose_bwd", "pose6", "plain_transform_bwd", "visibility", "zero"};
 

@@ -852,17 +852,17 @@ __device__ __forceinline__ void sort_tiny(const uint64_t* __restrict__ keys,
   gather_keys<E>(x, vin, vout, s0, 0, n, lane, direct);
 }
 
-// tiny lists, one wave each
-__global__ __launch_bounds__(kWave) void k_tile_sort_tiny(const uint64_t* __restrict__ keys,
-                                                          const uint32_t* __restrict__ vin,
-                                                          uint32_t* __restrict__ vout,
-                                                          const int32_t* __restrict__ start,
-                                                          const int32_t* __restrict__ order,
-                                                          int64_t cap, bool direct) {
+// list i of the launch order if it is tiny (fewer than kTsTiny entries), by
+// one wave
+__device__ __forceinline__ void tiny_list(const uint64_t* __restrict__ keys,
+                                          const uint32_t* __restrict__ vin,
+                                          uint32_t* __restrict__ vout,
+                                          const int32_t* __restrict__ start,
+                                          const int32_t* __restrict__ order, int i, int64_t cap,
+                                          bool direct, int lane) {
   int64_t s0;
   int n;
-  list_of(start, order, blockIdx.x, cap, s0, n);
-  const int lane = threadIdx.x;
+  list_of(start, order, i, cap, s0, n);
   if (n >= kTsTiny || n <= 0) return;
   if (n == 1) {
     if (lane == 0) vout[s0] = direct ? (uint32_t)keys[s0] : vin[s0];
@@ -887,18 +887,22 @@ __device__ __forceinline__ void class_bounds(const int32_t* ocnt, int nchunk, in
   t = ocnt[7 * nchunk];  // lengths >= 2^9
 }
 
-// small lists, and the chunks of large lists.  Work items are the kTsMaxChunks
-// chunks of every large list, then one item per small list.  Each wave sorts
-// its 512 keys in registers; merges of 1024 and 2048 keys take their steps
-// between waves through LDS.  A small list is written out, a large list's
-// chunk goes back in place as sorted composite keys.
-__global__ __launch_bounds__(256) void k_tile_sort_chunks(uint64_t* __restrict__ keys,
+// small lists, the chunks of large lists, then the tiny lists.  Work items
+// are the kTsMaxChunks chunks of every large list, then one item per small
+// list.  Each wave sorts its 512 keys in registers; merges of 1024 and 2048
+// keys take their steps between waves through LDS.  A small list is written
+// out, a large list's chunk goes back in place as sorted composite keys.
+// After its items every wave sorts tiny lists, one at a time, starting from
+// the workgroups numbered last (those with no item when the items are fewer
+// than the workgroups).  Launched with kTsChunkBlocks workgroups of 256.
+__global__ __launch_bounds__(256) void k_tile_sort(uint64_t* __restrict__ keys,
                                                           const uint32_t* __restrict__ vin,
                                                           uint32_t* __restrict__ vout,
                                                           const int32_t* __restrict__ start,
                                                           const int32_t* __restrict__ order,
                                                           const int32_t* __restrict__ ocnt,
-                                                          int nchunk, int64_t cap, bool direct) {
+                                                          int nchunk, int total_tiles,
+                                                          int64_t cap, bool direct) {
   __shared__ uint64_t s[kTsChunk];
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int base = wave * kTsWaveKeys;
@@ -951,6 +955,10 @@ __global__ __launch_bounds__(256) void k_tile_sort_chunks(uint64_t* __restrict__
       }
     }
   }
+  constexpr int kWpg = 256 / kWave;
+  const int gw = ((int)gridDim.x - 1 - (int)blockIdx.x) * kWpg + wave;
+  for (int i = lt + gw; i < total_tiles; i += (int)gridDim.x * kWpg)
+    tiny_list(keys, vin, vout, start, order, i, cap, direct, lane);
 }
 
 // lists of kTsLarge entries or more: the same network on the keys in global
@@ -1154,14 +1162,12 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
   // 4. depth order inside every list, written to the caller's value array
   if (a.by_tile) {
     uint64_t* keys = const_cast<uint64_t*>(parted);
-    S3R_LAUNCH(K_TILE_SORT_CHUNKS, k_tile_sort_chunks, dim3(kTsChunkBlocks), dim3(256), 0, st,
-               keys, pvals, a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk,
-               a.cap_dup, binned);
+    S3R_LAUNCH(K_TILE_SORT, k_tile_sort, dim3(kTsChunkBlocks), dim3(256), 0, st, keys,
+               pvals, a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk,
+               a.total_tiles, a.cap_dup, binned);
     S3R_LAUNCH(K_TILE_SORT_MERGE, k_tile_sort_merge, dim3(kTsMergeBlocks), dim3(1024), 0, st,
                keys, pvals, a.vals_out, a.tile_start, a.tile_order, a.order_cnt, nchunk,
                a.cap_dup, binned);
-    S3R_LAUNCH(K_TILE_SORT, k_tile_sort_tiny, dim3(a.total_tiles), dim3(kWave), 0, st, keys,
-               pvals, a.vals_out, a.tile_start, a.tile_order, a.cap_dup, binned);
   }
   return hipGetLastError();
 }

@@ -488,16 +488,18 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_place(const int32_t* __
 // ---------------------------------------------------------------------------
 // Each workgroup takes kBinBlock consecutive pairs (in emission order) and
 // counts them per tile in an LDS histogram; k_bin_count adds the non-zero
-// bins to the global counts, k_bin_scan turns the counts into list starts
-// (and the launch order), and k_bin_place claims, per non-zero bin, a block of
-// slots of the tile's list with one atomic on its cursor and writes each pair
-// there as the key (depth bits << 32 | record).  The order inside a list is
+// bins to the global counts, and k_bin_place takes each tile's list start
+// from an exclusive scan of the counts, claims, per non-zero bin, a block of
+// slots of the tile's list with one atomic on its fill counter and writes each
+// pair there as the key (depth bits << 32 | record).  One more workgroup of
+// the placement launch writes the list starts and lengths and the launch
+// order.  The order inside a list is
 // left arbitrary: the per-list sort orders it by that key, whose record part
 // is the Gaussian order within a view, so the lists come out exactly as a
 // stable sort would leave them.  Same-address atomics are one per tile and
 // workgroup, never one per pair.
-constexpr int kBinThreads = 256;
-constexpr int kBinRun = 16;  // consecutive pairs per thread
+constexpr int kBinThreads = 1024;
+constexpr int kBinRun = 4;  // consecutive pairs per thread
 constexpr int kBinBlock = kBinThreads * kBinRun;
 constexpr int kBinMaxTiles = 12288;  // a 48 KB histogram: two workgroups per CU
 constexpr int kBinClaim = 8;         // slot claims in flight per thread
@@ -539,8 +541,13 @@ __device__ __forceinline__ void walk_pairs(const SortArgs& a, const int* s_pair,
   }
 }
 
-__global__ __launch_bounds__(256) void k_bin_zero(int32_t* __restrict__ c, int n) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) c[t] = 0;
+// the per-tile counts and fill counters start at zero
+__global__ __launch_bounds__(256) void k_bin_zero(int32_t* __restrict__ c, int32_t* __restrict__ f,
+                                                  int n) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    c[t] = 0;
+    f[t] = 0;
+  }
 }
 
 __global__ __launch_bounds__(kBinThreads) void k_bin_count(SortArgs a) {
@@ -565,89 +572,119 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(SortArgs a) {
     if (s_h[t] != 0) atomicAdd(&a.bin_count[t], s_h[t]);
 }
 
-// One workgroup: list starts (exclusive scan of the counts), list lengths,
-// the slot cursors, each view's pair count, and the rasterizers' launch
-// order -- tiles by descending binary logarithm of the list length (empty
-// lists last), tile order within a bucket -- with the bucket starts the
-// per-list sorts read (order_cnt[b * nchunk], nchunk tile chunks of
-// kOrderChunk).  Global arrays are read and written tile-consecutively
-// through LDS; each thread scans a contiguous run of tiles.
-constexpr int kBinScanThreads = 1024;
-__global__ __launch_bounds__(kBinScanThreads) void k_bin_scan(SortArgs a, int nchunk) {
-  __shared__ int s_c[kOrderBuckets * kBinScanThreads];
-  __shared__ int s_start[kBinMaxTiles + 1];
-  __shared__ int s_w[kBinScanThreads / kWave];
-  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+// tiles per thread in the placement launch's scans of the counts (thread t
+// takes tiles t kBinTpt .. t kBinTpt + kBinTpt - 1)
+constexpr int kBinTpt = kBinMaxTiles / kBinThreads;
+static_assert(kBinTpt * kBinThreads == kBinMaxTiles, "whole tile runs per thread");
+
+// exclusive scan of x over the workgroup in thread order; the total out
+__device__ __forceinline__ int bin_block_scan(int x, int* s_w, int& total) {
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int incl = wave_inclusive_scan(x);
+  if (lane == kWave - 1) s_w[wave] = incl;
+  __syncthreads();
+  int base = 0;
+  total = 0;
+  for (int w = 0; w < kBinThreads / kWave; ++w) {
+    if (w < wave) base += s_w[w];
+    total += s_w[w];
+  }
+  __syncthreads();
+  return base + incl - x;
+}
+
+__device__ __forceinline__ int order_bucket(int c) {
+  return c <= 0 ? kOrderBuckets - 1 : 15 - min(15, 31 - __builtin_clz((unsigned)c));
+}
+
+// The last workgroup of the placement launch: list lengths and starts
+// (exclusive scan of the counts), each view's pair count, and the
+// rasterizers' launch order -- tiles by descending binary logarithm of the
+// list length (empty lists last), tile order within a bucket -- with the
+// bucket starts the per-list sorts read (order_cnt[b * nchunk], nchunk tile
+// chunks of kOrderChunk).  s_c holds kOrderBuckets x kBinThreads counters.
+__device__ __forceinline__ void bin_lists(const SortArgs& a, int nchunk, int* s_c, int* s_w,
+                                          int* s_v, int* s_toff) {
+  const int tid = threadIdx.x;
   const int T = a.total_tiles;
-  const int per = (T + kBinScanThreads - 1) / kBinScanThreads;
-  const int t0 = min(T, tid * per), t1 = min(T, t0 + per);
-  auto scan = [&](int x, int& total) {
-    const int incl = wave_inclusive_scan(x);
-    if (lane == kWave - 1) s_w[wave] = incl;
-    __syncthreads();
-    int base = 0;
-    total = 0;
-    for (int w = 0; w < kBinScanThreads / kWave; ++w) {
-      if (w < wave) base += s_w[w];
-      total += s_w[w];
-    }
-    __syncthreads();
-    return base + incl - x;
-  };
-  for (int t = tid; t < T; t += kBinScanThreads) {
-    const int c = a.bin_count[t];
-    s_start[t] = c;
-    a.tile_count[t] = c;
+  const int t0 = tid * kBinTpt;
+  for (int v = tid; v < a.nv; v += kBinThreads) s_v[v] = 0;
+  for (int v = tid; v <= a.nv; v += kBinThreads) s_toff[v] = a.tile_offset[v];
+  for (int b = 0; b < kOrderBuckets; ++b) s_c[b * kBinThreads + tid] = 0;
+  int c[kBinTpt], sum = 0;
+#pragma unroll
+  for (int k = 0; k < kBinTpt; ++k) {
+    c[k] = t0 + k < T ? a.bin_count[t0 + k] : 0;
+    sum += c[k];
   }
-  for (int b = 0; b < kOrderBuckets; ++b) s_c[b * kBinScanThreads + tid] = 0;
-  __syncthreads();
-  int sum = 0;
-  for (int t = t0; t < t1; ++t) sum += s_start[t];
   int total;
-  int run = scan(sum, total);
-  for (int t = t0; t < t1; ++t) {
-    const int c = s_start[t];
-    s_start[t] = run;
-    run += c;
-    const int b = c <= 0 ? kOrderBuckets - 1 : 15 - min(15, 31 - __builtin_clz((unsigned)c));
-    s_c[b * kBinScanThreads + tid] += 1;
+  int run = bin_block_scan(sum, s_w, total);
+  int v = 0, vsum = 0;
+#pragma unroll
+  for (int k = 0; k < kBinTpt; ++k) {
+    const int t = t0 + k;
+    if (t < T) {
+      a.tile_count[t] = c[k];
+      a.tile_start[t] = run;
+      run += c[k];
+      while (s_toff[v + 1] <= t) {
+        if (vsum) atomicAdd(&s_v[v], vsum);
+        vsum = 0;
+        ++v;
+      }
+      vsum += c[k];
+      s_c[order_bucket(c[k]) * kBinThreads + tid] += 1;
+    }
   }
-  if (tid == 0) s_start[T] = total;
+  if (vsum) atomicAdd(&s_v[v], vsum);
+  if (tid == 0) a.tile_start[T] = total;
   __syncthreads();
-  for (int t = tid; t <= T; t += kBinScanThreads) {
-    const int st = s_start[t];
-    a.tile_start[t] = st;
-    if (t < T) a.bin_cursor[t] = st;
-  }
   // (bucket, thread) offsets: thread i scans the kOrderBuckets consecutive
   // entries i * kOrderBuckets .. of the bucket-major linear order
   int bsum = 0;
   for (int k = 0; k < kOrderBuckets; ++k) bsum += s_c[tid * kOrderBuckets + k];
   int btot;
-  int brun = scan(bsum, btot);
+  int brun = bin_block_scan(bsum, s_w, btot);
   for (int k = 0; k < kOrderBuckets; ++k) {
     const int x = s_c[tid * kOrderBuckets + k];
     s_c[tid * kOrderBuckets + k] = brun;
     brun += x;
   }
   __syncthreads();
-  if (tid < kOrderBuckets) a.order_cnt[tid * nchunk] = s_c[tid * kBinScanThreads];
-  if (tid < a.nv) a.stats[tid * 4 + 3] = s_start[a.tile_offset[tid + 1]] - s_start[a.tile_offset[tid]];
-  __syncthreads();
-  for (int t = t0; t < t1; ++t) {
-    const int c = s_start[t + 1] - s_start[t];
-    const int b = c <= 0 ? kOrderBuckets - 1 : 15 - min(15, 31 - __builtin_clz((unsigned)c));
-    a.tile_order[s_c[b * kBinScanThreads + tid]++] = t;
+  if (tid < kOrderBuckets) a.order_cnt[tid * nchunk] = s_c[tid * kBinThreads];
+  if (tid < a.nv) a.stats[tid * 4 + 3] = s_v[tid];
+#pragma unroll
+  for (int k = 0; k < kBinTpt; ++k) {
+    const int t = t0 + k;
+    if (t < T) a.tile_order[s_c[order_bucket(c[k]) * kBinThreads + tid]++] = t;
   }
 }
 
-__global__ __launch_bounds__(kBinThreads) void k_bin_place(SortArgs a) {
-  __shared__ int s_h[kBinMaxTiles];
-  __shared__ int s_pair[kBinBlock + 2];
+// Workgroup 0 runs bin_lists (dispatched first, it overlaps the placement);
+// workgroups 1 .. gridDim.x - 1 place the pairs.  A placing workgroup takes
+// each tile's list start from a scan of the counts over its waves: wave w
+// holds tiles w kBinTpt kWave + k kWave + lane (k < kBinTpt), so its loads
+// and slot claims are lane-consecutive.  LDS: the placing workgroups' tile
+// histogram and record window share one array with bin_lists' counters.
+constexpr int kBinLds = (kBinMaxTiles + kBinBlock + 2 > kOrderBuckets * kBinThreads)
+                            ? kBinMaxTiles + kBinBlock + 2
+                            : kOrderBuckets * kBinThreads;
+
+__global__ __launch_bounds__(kBinThreads) void k_bin_place(SortArgs a, int nchunk) {
+  __shared__ int s_mem[kBinLds];
   __shared__ int s_red[2 * kBinThreads / kWave];
+  __shared__ int s_w[kBinThreads / kWave];
+  __shared__ int s_v[kMaxViews];
+  __shared__ int s_toff[kMaxViews + 1];
+  if (blockIdx.x == 0) {  // uniform over the workgroup
+    bin_lists(a, nchunk, s_mem, s_w, s_v, s_toff);
+    return;
+  }
+  int* s_h = s_mem;
+  int* s_pair = s_mem + kBinMaxTiles;
   const int nrec = a.counters[S3R_CNT_SURV];
   const int64_t ndup = min((int64_t)a.counters[S3R_CNT_DUP], a.cap_dup);
-  const int64_t P = (int64_t)blockIdx.x * kBinBlock;
+  const int64_t P = (int64_t)(blockIdx.x - 1) * kBinBlock;
   if (P >= ndup || nrec <= 0) return;  // uniform over the workgroup
   const int tid = threadIdx.x;
   const int T = a.total_tiles;
@@ -659,27 +696,32 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_place(SortArgs a) {
   const int64_t p1 = min(Pe, p0 + kBinRun);
   if (p0 < p1)
     walk_pairs(a, s_pair, r0, nw, p0, p1, [&](int t, int, uint32_t) { atomicAdd(&s_h[t], 1); });
-  __syncthreads();
-  // this workgroup's block of slots in every list it touches; kBinClaim
-  // claims are in flight before their results are used
-  for (int tb = 0; tb < T; tb += kBinThreads * kBinClaim) {
-    int c[kBinClaim], base[kBinClaim];
+  // list starts of this thread's tiles, then this workgroup's block of slots
+  // in every list it touches
+  const int lane = tid % kWave, wave = tid / kWave;
+  const int tw = wave * kBinTpt * kWave + lane;  // this thread's tile of round k: tw + k kWave
+  int ex[kBinTpt], carry = 0;
 #pragma unroll
-    for (int u = 0; u < kBinClaim; ++u) {
-      const int t = tb + u * kBinThreads + tid;
-      c[u] = t < T ? s_h[t] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < kBinClaim; ++u) {
-      const int t = tb + u * kBinThreads + tid;
-      base[u] = c[u] != 0 ? atomicAdd(&a.bin_cursor[t], c[u]) : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < kBinClaim; ++u) {
-      const int t = tb + u * kBinThreads + tid;
-      if (c[u] != 0) s_h[t] = base[u];
-    }
+  for (int k = 0; k < kBinTpt; ++k) {
+    const int t = tw + k * kWave;
+    const int c = t < T ? a.bin_count[t] : 0;
+    const int incl = wave_inclusive_scan(c);
+    ex[k] = carry + incl - c;
+    carry += __builtin_amdgcn_readlane(incl, kWave - 1);
   }
+  if (lane == 0) s_w[wave] = carry;
+  __syncthreads();  // (also orders the histogram above before the claims)
+  int wbase = 0;
+  for (int w = 0; w < wave; ++w) wbase += s_w[w];
+  int h[kBinTpt], base[kBinTpt];
+#pragma unroll
+  for (int k = 0; k < kBinTpt; ++k) h[k] = tw + k * kWave < T ? s_h[tw + k * kWave] : 0;
+#pragma unroll
+  for (int k = 0; k < kBinTpt; ++k)
+    base[k] = h[k] != 0 ? atomicAdd(&a.bin_cursor[tw + k * kWave], h[k]) : 0;
+#pragma unroll
+  for (int k = 0; k < kBinTpt; ++k)
+    if (h[k] != 0) s_h[tw + k * kWave] = wbase + ex[k] + base[k];
   __syncthreads();
   if (p0 < p1)
     walk_pairs(a, s_pair, r0, nw, p0, p1, [&](int t, int r, uint32_t db) {
@@ -1103,15 +1145,15 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t st) {
   const uint64_t* parted = a.keys;
   const uint32_t* pvals = a.vals0;
   if (binned) {
-    // 1. pairs per tile, 2. list starts and launch order, 3. pairs into
-    // their lists as (depth bits << 32 | record) keys
+    // 1. pairs per tile, 2. pairs into their lists as (depth bits << 32 |
+    // record) keys, the list starts and the launch order by the placement
+    // launch's last workgroup
     S3R_LAUNCH(K_TILE_BIN, k_bin_zero, dim3((a.total_tiles + 255) / 256), dim3(256), 0, st,
-               a.bin_count, a.total_tiles);
+               a.bin_count, a.bin_cursor, a.total_tiles);
     S3R_LAUNCH(K_TILE_BIN, k_bin_count, dim3((unsigned)(bin_grid > 0 ? bin_grid : 1)),
                dim3(kBinThreads), 0, st, a);
-    S3R_LAUNCH(K_TILE_BIN, k_bin_scan, dim3(1), dim3(kBinScanThreads), 0, st, a, nchunk);
-    S3R_LAUNCH(K_TILE_BIN, k_bin_place, dim3((unsigned)(bin_grid > 0 ? bin_grid : 1)),
-               dim3(kBinThreads), 0, st, a);
+    S3R_LAUNCH(K_TILE_BIN, k_bin_place, dim3((unsigned)((bin_grid > 0 ? bin_grid : 0) + 1)),
+               dim3(kBinThreads), 0, st, a, nchunk);
   } else {
     // radix passes over the tile bits only (then a depth sort per list) or
     // over all key bits; the values of a full sort end in the caller's array

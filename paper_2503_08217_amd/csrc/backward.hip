@@ -205,19 +205,19 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a) {
             if (row == 3) G[8] = sb;
           }
         } else {
-          // the LDS slot adds the last partials: two per row of s1 and s2
-          // (8-lane half-rows), one per row of sb -- the full wave sums'
-          // remaining DPP steps would cost more issue slots than these adds
-          const float s1 = wave_half_sum4(m_x, m_y, m_xx, m_xy);
-          const float s2 = wave_half_sum4(m_yy, g_o, wgt * dCr, wgt * dCg);
+          // the LDS slot adds sb's four row partials: the two row
+          // broadcasts of a full wave sum cost more issue slots than three
+          // more lanes of the slot's atomic add
+          const float s1 = wave_sum4(m_x, m_y, m_xx, m_xy);
+          const float s2 = wave_sum4(m_yy, g_o, wgt * dCr, wgt * dCg);
           const float sb = row_sum(wgt * dCb);
-          if ((lane & 7) == 7) {
+          if ((lane & 15) == 15) {
             const int row = lane >> 4;
             const int q = ((row & 1) << 1) | (row >> 1);
             float* G = s_g[0][(int)(b0 - w0) + j];
             atomicAdd(G + q, s1);
             atomicAdd(G + 4 + q, s2);
-            if ((lane & 15) == 15) atomicAdd(G + 8, sb);
+            atomicAdd(G + 8, sb);
           }
         }
       }

@@ -59,10 +59,7 @@ __device__ __forceinline__ float wave_sum_dpp(float x) {
 // other's in lanes 32-63), a permlane16 swap pairs the two results, and DPP
 // row sums finish.  On return every lane of row k (lanes 16k..16k+15) holds
 // the wave total of x (k = 0), z (k = 1), y (k = 2) or w (k = 3).
-// (the swap levels and the steps inside 8-lane half-rows: lanes 8 h + 7 of
-// row k (h = 0, 1) then hold two disjoint partial sums whose total is the
-// value's wave total)
-__device__ __forceinline__ float wave_half_sum4(float x, float y, float z, float w) {
+__device__ __forceinline__ float wave_sum4(float x, float y, float z, float w) {
   const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
                                                   false);
   const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(z), __float_as_uint(w), false,
@@ -75,11 +72,8 @@ __device__ __forceinline__ float wave_half_sum4(float x, float y, float z, float
   s = dpp_add<0xB1, 0xf>(s);   // quad_perm [1,0,3,2]
   s = dpp_add<0x4E, 0xf>(s);   // quad_perm [2,3,0,1]
   s = dpp_add<0x124, 0xf>(s);  // row_ror:4
+  s = dpp_add<0x128, 0xf>(s);  // row_ror:8
   return s;
-}
-
-__device__ __forceinline__ float wave_sum4(float x, float y, float z, float w) {
-  return dpp_add<0x128, 0xf>(wave_half_sum4(x, y, z, w));  // row_ror:8
 }
 
 // sum over each 16-lane row, in every lane of the row

@@ -929,6 +929,16 @@ __device__ __forceinline__ void class_bounds(const int32_t* ocnt, int nchunk, in
   t = ocnt[7 * nchunk];  // lengths >= 2^9
 }
 
+// LDS slot of network position p in the steps between waves: inside each
+// wave's 512 positions, key e of lane l goes to e 64 + l, so the 64 lanes of
+// a store, of a load at p ^ j (j >= 512: the same lane and key of another
+// wave) and of a load at p ^ (k - 1) (lane 63 - l, key 7 - e) touch
+// consecutive slots (no bank conflicts; lane-major, a lane's eight keys were
+// 64 bytes apart)
+__device__ __forceinline__ int ts_swz(int p) {
+  return (p & ~(kTsWaveKeys - 1)) | ((p & (kTsE - 1)) * kWave) | ((p / kTsE) & (kWave - 1));
+}
+
 // small lists, the chunks of large lists, then the tiny lists.  Work items
 // are the kTsMaxChunks chunks of every large list, then one item per small
 // list.  Each wave sorts its 512 keys in registers; merges of 1024 and 2048
@@ -974,13 +984,13 @@ __global__ __launch_bounds__(256) void k_tile_sort(uint64_t* __restrict__ keys,
     for (int k = 2 * kTsWaveKeys; k <= mtop; k <<= 1) {
       for (int j = k >> 1; j >= kTsWaveKeys; j >>= 1) {
 #pragma unroll
-        for (int e = 0; e < kTsE; ++e) s[base + lane * kTsE + e] = x[e];
+        for (int e = 0; e < kTsE; ++e) s[ts_swz(base + lane * kTsE + e)] = x[e];
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < kTsE; ++e) {
           const int p = base + lane * kTsE + e;
           const int q = (j == (k >> 1)) ? (p ^ (k - 1)) : (p ^ j);
-          const uint64_t y = s[q];
+          const uint64_t y = s[ts_swz(q)];
           x[e] = ((y < x[e]) == (p < q)) ? y : x[e];
         }
         __syncthreads();

@@ -109,9 +109,11 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_raster_fwd(RasterArgs a, int n_fi
     }
     rcur = rn;
     rn = (b0 + 2 * kWave + lane < e) ? a.vals[b0 + 2 * kWave + lane] : 0u;
+    // (a 4x4 block's box test is nearly as tight as the square test, which
+    // then costs more than the entries it drops: coarse waves only)
     const bool near =
         valid && box_hits(cutoff_box(g.x, g.y, make_float2(c.w, col.w)), sub_x, sub_y, ext) &&
-        square_may_hit(g.x, g.y, c.x, c.y, c.z, g.z, sub_x, sub_y, ext, a.kp);
+        (fine || square_may_hit(g.x, g.y, c.x, c.y, c.z, g.z, sub_x, sub_y, ext, a.kp));
     const uint64_t m = ballot(near);
     const int n = __popcll(m);
     if (near) {

@@ -433,7 +433,12 @@ __device__ __forceinline__ float edge_min_q(float dx, float dyl, float dyh, floa
 // conic (A, B, C) and opacity o?  False only when none can.  blend_eval's
 // power is -q/2 with q = A dx^2 + 2 B dx dy + C dy^2 (dx = u - x, dy = v - y);
 // the minimum of q over the square is 0 when (u, v) lies in it and otherwise
-// the least of the four edges' minima (q is convex).  The binary32 power of
+// lies on an edge facing (u, v) -- the x-edge on (u, v)'s side when u is
+// outside [x0, x0 + ext], the y-edge likewise: q is convex, and at a minimum
+// inside an edge whose line (u, v) does not cross q would fall into the
+// square -- so the least of those (at most) two edges' minima; the edge
+// taken when (u, v) is within an edge's range is harmless (its minimum is
+// not below the square's).  The binary32 power of
 // the kernel and this minimum each differ from the exact values by a few
 // units of rounding relative to A dx^2 + C dy^2 <= q / (1 - rho), rho =
 // |B| / sqrt(A C) < 1 for a positive-definite conic, so the minimum is
@@ -450,9 +455,9 @@ __device__ __forceinline__ bool square_may_hit(float u, float v, float A, float 
   const float rho = fabsf(B) * __builtin_amdgcn_rsqf(A * C);
   if (!(A > 0.f) || !(C > 0.f) || !(rho <= 0.999f)) return true;
   const float rA = __builtin_amdgcn_rcpf(A), rC = __builtin_amdgcn_rcpf(C);
-  float q = fminf(edge_min_q(dxl, dyl, dyh, A, B, C, rC), edge_min_q(dxh, dyl, dyh, A, B, C, rC));
-  q = fminf(q, edge_min_q(dyl, dxl, dxh, C, B, A, rA));
-  q = fminf(q, edge_min_q(dyh, dxl, dxh, C, B, A, rA));
+  const float dxe = dxl > 0.f ? dxl : dxh;  // u right of the square: its right edge
+  const float dye = dyl > 0.f ? dyl : dyh;
+  const float q = fminf(edge_min_q(dxe, dyl, dyh, A, B, C, rC), edge_min_q(dye, dxl, dxh, C, B, A, rA));
   // 64 u / (1 - rho), the reciprocal rounded down by at most a few ulp
   const float qlo = q * (1.f - 3.8148e-6f * __builtin_amdgcn_rcpf(1.f - rho));
   const float pmax = -0.5f * qlo;                             // >= every pixel's power

@@ -91,9 +91,10 @@ def square_may_hit32(u, v, A, B, C, o, x0, y0, ext, alpha_min):
         return (((A_ * dx).astype(f32) * dx).astype(f32) + ((f32(2.0) * B_ * dx).astype(f32) * dy).astype(f32)
                 + ((C_ * dy).astype(f32) * dy).astype(f32)).astype(f32)
 
-    q = np.minimum(edge(dxl, dyl, dyh, A, B, C), edge(dxh, dyl, dyh, A, B, C))
-    q = np.minimum(q, edge(dyl, dxl, dxh, C, B, A))
-    q = np.minimum(q, edge(dyh, dxl, dxh, C, B, A))
+    # the edges facing the centre (the x-edge on its side, the y-edge likewise)
+    dxe = np.where(dxl > 0, dxl, dxh)
+    dye = np.where(dyl > 0, dyl, dyh)
+    q = np.minimum(edge(dxe, dyl, dyh, A, B, C), edge(dye, dxl, dxh, C, B, A))
     qlo = (q * (one - (f32(3.8148e-6) * (one / (one - rho)).astype(f32)).astype(f32))).astype(f32)
     pmax = (f32(-0.5) * qlo).astype(f32)
     alpha_ok = (o * np.exp(pmax.astype(np.float64)).astype(f32) * f32(1.0000153)).astype(f32) >= alpha_min

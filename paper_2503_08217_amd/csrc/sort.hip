@@ -502,7 +502,6 @@ constexpr int kBinThreads = 1024;
 constexpr int kBinRun = 4;  // consecutive pairs per thread
 constexpr int kBinBlock = kBinThreads * kBinRun;
 constexpr int kBinMaxTiles = 12288;  // a 48 KB histogram: two workgroups per CU
-constexpr int kBinClaim = 8;         // slot claims in flight per thread
 
 // the pairs [p0, p1) of this thread (inside the workgroup's window):
 // f(global tile, record, depth bits)

@@ -652,6 +652,7 @@ __device__ __forceinline__ void bin_lists(const SortArgs& a, int nchunk, int* s_
   __syncthreads();
   if (tid < kOrderBuckets) a.order_cnt[tid * nchunk] = s_c[tid * kBinThreads];
   if (tid < a.nv) a.stats[tid * 4 + 3] = s_v[tid];
+  __syncthreads();  // (the bucket starts are read before the cursors below move)
 #pragma unroll
   for (int k = 0; k < kBinTpt; ++k) {
     const int t = t0 + k;

@@ -414,7 +414,7 @@ int s3r_plain_transform_bwd(const S3RScene* scene, const int32_t* tsteps, int32_
  *   S3R_TUNE_FINE_TILES       s3r_raster_fwd gives the first this many tiles
  *       of the launch order (the longest lists; rounded down to a multiple of
  *       32) one wave per 4x4 pixel block instead of one per 8x8 sub-tile
- *       (0..1048576, default 256)
+ *       (0..1048576, default 160)
  * s3r_set_tuning(knob, negative value) restores the default.  Errors:
  * S3R_E_ARG for an unknown knob or a value out of range.
  */

@@ -48,7 +48,7 @@ def _time_step(r, target, reps, warm=2):
 
 
 def autotune(scene, views, params, target, *, tiles=(8, 16, 32), sorts=("tiles", "global"),
-             raster_waves=(1, 4, 16), binning=(True, False), fine_tiles=(0, 64, 256, 1024),
+             raster_waves=(1, 4, 16), binning=(True, False), fine_tiles=(0, 64, 160, 256, 1024),
              reps=5, vis=None, device="cuda", cap_surv=None, cap_dup=None, log=None):
     """Time every candidate launch shape on a step of `views`; returns
     {"best": {...}, "table": [...]} (times in ms, median of `reps`).

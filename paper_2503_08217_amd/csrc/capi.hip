@@ -16,7 +16,7 @@ static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 namespace s3r {
 namespace {
 // defaults, and the largest value, of the launch-shape knobs
-constexpr int kTuneDefault[S3R_TUNE_COUNT] = {1024, 1024, 12288, 1, 256};
+constexpr int kTuneDefault[S3R_TUNE_COUNT] = {1024, 1024, 12288, 1, 160};
 constexpr int kTuneMax[S3R_TUNE_COUNT] = {1024, 1024, 12288, 16, 1 << 20};
 std::atomic<int> g_tune[S3R_TUNE_COUNT] = {{kTuneDefault[0]}, {kTuneDefault[1]},
                                            {kTuneDefault[2]}, {kTuneDefault[3]},

@@ -158,10 +158,10 @@ def test_tuning_knobs(lib):
     assert lib.s3r_set_tuning(A.S3R_TUNE_BIN_MAX_TILES, 12289) == A.S3R_E_ARG
     assert lib.s3r_set_tuning(A.S3R_TUNE_RASTER_WAVES, 0) == A.S3R_E_ARG
     assert lib.s3r_set_tuning(A.S3R_TUNE_FINE_TILES, (1 << 20) + 1) == A.S3R_E_ARG
-    assert lib.s3r_get_tuning(A.S3R_TUNE_FINE_TILES, C.byref(v)) == 0 and v.value == 256
+    assert lib.s3r_get_tuning(A.S3R_TUNE_FINE_TILES, C.byref(v)) == 0 and v.value == 160
     old = A.set_tuning(offset_fuse_max=0, bin_max_tiles=0, raster_waves=4)
     assert old == {"offset_fuse_max": 1024, "bin_max_tiles": 12288, "raster_waves": 1}
     assert A.get_tuning()["raster_waves"] == 4
     A.set_tuning(offset_fuse_max=-1, bin_max_tiles=-1, raster_waves=-1)
     assert A.get_tuning() == {"offset_fuse_max": 1024, "scan_fuse_max": 1024,
-                              "bin_max_tiles": 12288, "raster_waves": 1, "fine_tiles": 256}
+                              "bin_max_tiles": 12288, "raster_waves": 1, "fine_tiles": 160}

@@ -64,7 +64,7 @@ def test_autotuner_picks_a_shape_that_renders_the_same_image():
     banner("autotune")
     try:
         r, res = Renderer.autotuned(c.scene, views, c.params, target, tiles=(8, 16, 32),
-                                    raster_waves=(1, 16), fine_tiles=(0, 256, 4096), reps=2)
+                                    raster_waves=(1, 16), fine_tiles=(0, 160, 4096), reps=2)
         table, best = res["table"], res["best"]
         assert len(table) == 3 * (2 * 2 + 2) + 2
         assert best["ms"] == min(row["ms"] for row in table)
